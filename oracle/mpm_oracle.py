@@ -1,0 +1,458 @@
+"""FP64 CPU oracle of the MLS-MPM substep (FastPhysGS, arXiv 2602.01723).
+
+TEST INFRASTRUCTURE.  Only the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import this module.  The product path never
+calls it and shares no code with it (no kernels, helpers or constants).
+
+What it computes, step by step, in float64 with plain PyTorch CPU ops:
+
+  O0  Lame parameters from (log E, nu)                       App. B.1 (Lame relations)
+  O1  clear the grid
+  O2  Kirchhoff stress tau = P F^T of the particle's model    App. A.2 (fixed corotated, StVK/Hencky);
+                                                              App. B.1 (Corotated, SigmaElasticity)
+  O3  P2G: quadratic B-spline weights, APIC affine momentum  Sec. 4.2 momentum-exchange equation;
+      with the MLS stress term                                App. A.1 (P2G)
+  O4  grid update: normalise, gravity, sticky walls          App. A.1 (grid update)
+  O5  G2P: v, C (with the 4/dx^2 factor), x                  App. A.1 (G2P)
+  O6  F_trial = (I + dt C') F                                 MLS-MPM reading of App. A.1's grad-v update
+  O7  plastic return map applied after the stress            App. A.2 (identity, Drucker-Prager,
+                                                              von Mises); App. B.2 (ordering); Alg. 1
+
+The adjoint is torch autograd through the same steps (``adjoint``), with the
+polar factor of the fixed-corotated model computed by the Newton iteration
+X <- (X + X^-T) / 2 instead of an SVD, whose derivative is undefined at
+repeated singular values (e.g. F = I).  It is restricted to the elastic
+(identity-plasticity) models and to det F > 0.
+
+Readings of points the paper leaves open (each also listed in the design doc):
+  * grid nodes sit at i*dx, i in [0, n); base = floor(x/dx - 0.5) per axis,
+    computed exactly (x is a float32 value, the product is exact in float64);
+  * sticky walls: v_i = 0 where any node index is < bound or >= n - bound;
+    gravity is an acceleration, v_i += dt g, applied after normalisation;
+  * empty nodes (m_i = 0) get v_i = 0;
+  * the SVD takes U, V in SO(3), the sign moved onto the last singular value;
+  * log of singular values is taken of max(sigma, 1e-4);
+  * Drucker-Prager: delta_gamma = |eps_hat| + (3 lam + 2 mu)/(2 mu) tr(eps) alpha,
+    alpha = sqrt(2/3) 2 sin(phi) / (3 - sin(phi)), zero cohesion (Klar et al. 2016);
+  * the elastic model paired with von Mises and Drucker-Prager is Hencky.
+
+Array conventions: x, v [N,3]; C, F [N,3,3]; grid arrays flattened over
+(ix, iy, iz) with iz fastest, m [n^3], mv / v [n^3, 3].
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+F64 = torch.float64
+SIGMA_MIN = 1e-4
+
+ELASTIC_FCR, ELASTIC_HENCKY = 0, 1
+PLASTIC_NONE, PLASTIC_VON_MISES, PLASTIC_DRUCKER_PRAGER = 0, 1, 2
+
+
+def as64(a) -> torch.Tensor:
+    return torch.as_tensor(a).to(F64)
+
+
+# ---------------------------------------------------------------------------
+# O0: Lame parameters (App. B.1)
+# ---------------------------------------------------------------------------
+
+def lame(log_E: torch.Tensor, nu: torch.Tensor):
+    E = torch.exp(log_E)
+    mu = E / (2.0 * (1.0 + nu))
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    return mu, lam
+
+
+# ---------------------------------------------------------------------------
+# SVD with rotations (library SVD plus the sign convention)
+# ---------------------------------------------------------------------------
+
+def svd_rot(F: torch.Tensor):
+    """F = U diag(S) V^T with U, V in SO(3); S sorted by magnitude, only the
+    last entry may be negative (its sign is the sign of det F)."""
+    U, S, Vh = torch.linalg.svd(F)
+    U = U.clone()
+    S = S.clone()
+    V = Vh.transpose(-1, -2).clone()
+    neg = torch.linalg.det(U) < 0
+    U[neg, :, 2] = -U[neg, :, 2]
+    S[neg, 2] = -S[neg, 2]
+    neg = torch.linalg.det(V) < 0
+    V[neg, :, 2] = -V[neg, :, 2]
+    S[neg, 2] = -S[neg, 2]
+    return U, S, V
+
+
+def _diag_sandwich(A, d, B):
+    """A diag(d) B^T for batches."""
+    return (A * d[:, None, :]) @ B.transpose(-1, -2)
+
+
+# ---------------------------------------------------------------------------
+# O2: Kirchhoff stress (App. A.2 / B.1)
+# ---------------------------------------------------------------------------
+
+def tau_fixed_corotated(F, mu, lam):
+    """tau = 2 mu (F - R) F^T + lam J (J - 1) I, R the rotation of F's polar decomposition."""
+    U, S, V = svd_rot(F)
+    R = U @ V.transpose(-1, -2)
+    J = torch.linalg.det(F)
+    eye = torch.eye(3, dtype=F.dtype)
+    return 2.0 * mu[:, None, None] * (F - R) @ F.transpose(-1, -2) \
+        + (lam * J * (J - 1.0))[:, None, None] * eye
+
+
+def tau_hencky(F, mu, lam):
+    """tau = U diag(2 mu eps + lam tr(eps)) U^T with eps = log(sigma)."""
+    U, S, V = svd_rot(F)
+    eps = torch.log(torch.clamp(S, min=SIGMA_MIN))
+    d = 2.0 * mu[:, None] * eps + (lam * eps.sum(-1))[:, None]
+    return _diag_sandwich(U, d, U)
+
+
+def kirchhoff_stress(F, mu, lam, mat_id, materials: Sequence[Dict]):
+    tau = torch.zeros_like(F)
+    for k, mat in enumerate(materials):
+        sel = mat_id == k
+        if not bool(sel.any()):
+            continue
+        fn = tau_fixed_corotated if mat["elastic"] == ELASTIC_FCR else tau_hencky
+        tau[sel] = fn(F[sel], mu[sel], lam[sel])
+    return tau
+
+
+# ---------------------------------------------------------------------------
+# O7: plastic return maps (App. A.2 / B.2)
+# ---------------------------------------------------------------------------
+
+def _log_strain(F):
+    U, S, V = svd_rot(F)
+    eps = torch.log(torch.clamp(S, min=SIGMA_MIN))
+    eps_hat = eps - eps.mean(-1, keepdim=True)
+    nrm = torch.linalg.vector_norm(eps_hat, dim=-1)
+    return U, V, eps, eps_hat, nrm
+
+
+def return_von_mises(F, mu, yield_stress):
+    U, V, eps, eps_hat, nrm = _log_strain(F)
+    dgamma = nrm - yield_stress / (2.0 * mu)
+    out = F.clone()
+    y = dgamma > 0
+    if bool(y.any()):
+        e = eps[y] - (dgamma[y] / nrm[y])[:, None] * eps_hat[y]
+        out[y] = _diag_sandwich(U[y], torch.exp(e), V[y])
+    return out
+
+
+def drucker_prager_alpha(friction_deg):
+    s = math.sin(math.radians(friction_deg))
+    return math.sqrt(2.0 / 3.0) * 2.0 * s / (3.0 - s)
+
+
+def return_drucker_prager(F, mu, lam, friction_deg):
+    U, V, eps, eps_hat, nrm = _log_strain(F)
+    alpha = drucker_prager_alpha(friction_deg)
+    tr = eps.sum(-1)
+    out = F.clone()
+    tension = tr > 0
+    if bool(tension.any()):  # Z = I
+        out[tension] = U[tension] @ V[tension].transpose(-1, -2)
+    dgamma = nrm + (3.0 * lam + 2.0 * mu) / (2.0 * mu) * tr * alpha
+    y = (~tension) & (dgamma > 0)
+    if bool(y.any()):
+        e = eps[y] - (dgamma[y] / nrm[y])[:, None] * eps_hat[y]
+        out[y] = _diag_sandwich(U[y], torch.exp(e), V[y])
+    return out
+
+
+def plasticity(F, mu, lam, mat_id, materials: Sequence[Dict]):
+    out = F.clone()
+    for k, mat in enumerate(materials):
+        sel = mat_id == k
+        if not bool(sel.any()) or mat["plastic"] == PLASTIC_NONE:
+            continue
+        if mat["plastic"] == PLASTIC_VON_MISES:
+            out[sel] = return_von_mises(F[sel], mu[sel], mat["yield_stress"])
+        elif mat["plastic"] == PLASTIC_DRUCKER_PRAGER:
+            out[sel] = return_drucker_prager(F[sel], mu[sel], lam[sel], mat["friction_deg"])
+        else:
+            raise ValueError(f"unknown plastic model {mat['plastic']}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O3 / O5: quadratic B-spline stencil
+# ---------------------------------------------------------------------------
+
+def stencil(x, n):
+    """base cell (int64 [N,3]), fractional offset f in [0.5, 1.5) and weights
+    w[N, 3 (offset), 3 (axis)] of the quadratic B-spline."""
+    xs = x * float(n)
+    base = torch.floor(xs - 0.5).detach()
+    fx = xs - base
+    w = torch.stack([0.5 * (1.5 - fx) ** 2, 0.75 - (fx - 1.0) ** 2, 0.5 * (fx - 0.5) ** 2], dim=1)
+    return base.long(), fx, w
+
+
+OFFSETS = [(a, b, c) for a in range(3) for b in range(3) for c in range(3)]
+
+
+def _check_inside(base, n):
+    if base.numel() and (int(base.min()) < 0 or int(base.max()) + 2 >= n):
+        raise ValueError("particle stencil leaves the grid")
+
+
+def p2g(x, v, C, tau, mass, vol0, n, dt):
+    """Grid mass and momentum [n^3], [n^3, 3] (Sec. 4.2 momentum exchange; App. A.1)."""
+    inv_dx = float(n)
+    dx = 1.0 / n
+    base, fx, w = stencil(x, n)
+    _check_inside(base, n)
+    affine = mass[:, None, None] * C - (4.0 * inv_dx * inv_dx * dt) * vol0[:, None, None] * tau
+    mom = mass[:, None] * v
+    m_grid = torch.zeros(n ** 3, dtype=x.dtype)
+    mv_grid = torch.zeros(n ** 3, 3, dtype=x.dtype)
+    for (a, b, c) in OFFSETS:
+        weight = w[:, a, 0] * w[:, b, 1] * w[:, c, 2]
+        dpos = (torch.tensor([a, b, c], dtype=x.dtype) - fx) * dx
+        node = ((base[:, 0] + a) * n + (base[:, 1] + b)) * n + (base[:, 2] + c)
+        m_grid = m_grid.index_add(0, node, weight * mass)
+        contrib = weight[:, None] * (mom + (affine @ dpos[:, :, None])[:, :, 0])
+        mv_grid = mv_grid.index_add(0, node, contrib)
+    return m_grid, mv_grid
+
+
+def node_indices(n):
+    i = torch.arange(n)
+    return torch.stack(torch.meshgrid(i, i, i, indexing="ij"), -1).reshape(-1, 3)
+
+
+def grid_update(m, mv, n, dt, gravity, bound):
+    """Grid velocity: mv / m, plus dt g, zero on sticky walls and empty nodes (App. A.1)."""
+    has = m > 0
+    safe_m = torch.where(has, m, torch.ones_like(m))
+    v = mv / safe_m[:, None] + dt * torch.as_tensor(gravity, dtype=mv.dtype)
+    idx = node_indices(n)
+    wall = ((idx < bound) | (idx >= n - bound)).any(-1)
+    keep = has & ~wall
+    return torch.where(keep[:, None], v, torch.zeros_like(v))
+
+
+def g2p(x, F, v_grid, n, dt):
+    """v', C', x', F_trial (App. A.1 G2P; F_trial = (I + dt C') F)."""
+    inv_dx = float(n)
+    dx = 1.0 / n
+    base, fx, w = stencil(x, n)
+    _check_inside(base, n)
+    v_new = torch.zeros_like(x)
+    B = torch.zeros(x.shape[0], 3, 3, dtype=x.dtype)
+    for (a, b, c) in OFFSETS:
+        weight = w[:, a, 0] * w[:, b, 1] * w[:, c, 2]
+        dpos = (torch.tensor([a, b, c], dtype=x.dtype) - fx) * dx
+        node = ((base[:, 0] + a) * n + (base[:, 1] + b)) * n + (base[:, 2] + c)
+        vi = v_grid[node]
+        v_new = v_new + weight[:, None] * vi
+        B = B + weight[:, None, None] * vi[:, :, None] * dpos[:, None, :]
+    C_new = 4.0 * inv_dx * inv_dx * B
+    x_new = x + dt * v_new
+    eye = torch.eye(3, dtype=x.dtype)
+    F_trial = (eye + dt * C_new) @ F
+    return x_new, v_new, C_new, F_trial
+
+
+# ---------------------------------------------------------------------------
+# The substep and its driver (Alg. 1 stage-1 order: stress, MPM step, plasticity)
+# ---------------------------------------------------------------------------
+
+class Params:
+    """Per-particle parameters and the run configuration, all float64."""
+
+    def __init__(self, mass, vol0, log_E, nu, mat_id, materials, grid_res, dt,
+                 gravity=(0.0, -9.8, 0.0), bound=3, batch_offsets=None):
+        self.mass = as64(mass)
+        self.vol0 = as64(vol0)
+        self.log_E = as64(log_E)
+        self.nu = as64(nu)
+        self.mat_id = torch.as_tensor(mat_id).long()
+        self.materials = list(materials)
+        self.n = int(grid_res)
+        self.dt = float(dt)
+        self.gravity = tuple(float(g) for g in gravity)
+        self.bound = int(bound)
+        N = self.mass.shape[0]
+        self.batch_offsets = [0, N] if batch_offsets is None else [int(b) for b in batch_offsets]
+
+    @classmethod
+    def from_scene(cls, sc):
+        return cls(sc.mass, sc.vol0, sc.log_E, sc.nu, sc.mat_id, sc.materials, sc.grid_res, sc.dt,
+                   sc.gravity, sc.bound, sc.batch_offsets)
+
+
+def _substep_one(x, v, C, F, p: Params, sl, log_E=None, nu=None):
+    mass, vol0 = p.mass[sl], p.vol0[sl]
+    mu, lam = lame(p.log_E[sl] if log_E is None else log_E, p.nu[sl] if nu is None else nu)
+    mat = p.mat_id[sl]
+    tau = kirchhoff_stress(F, mu, lam, mat, p.materials)                  # O2
+    m, mv = p2g(x, v, C, tau, mass, vol0, p.n, p.dt)                       # O3
+    vg = grid_update(m, mv, p.n, p.dt, p.gravity, p.bound)                 # O4
+    x1, v1, C1, Ftr = g2p(x, F, vg, p.n, p.dt)                             # O5, O6
+    F1 = plasticity(Ftr, mu, lam, mat, p.materials)                        # O7
+    return (x1, v1, C1, F1), (m, mv, vg)
+
+
+def substep(state, p: Params, return_grid=False):
+    """One substep of every scene of the batch.  state = (x, v, C, F) float64."""
+    x, v, C, F = state
+    outs, grids = [], []
+    for b in range(len(p.batch_offsets) - 1):
+        sl = slice(p.batch_offsets[b], p.batch_offsets[b + 1])
+        o, g = _substep_one(x[sl], v[sl], C[sl], F[sl], p, sl)
+        outs.append(o)
+        grids.append(g)
+    new = tuple(torch.cat([o[i] for o in outs]) for i in range(4))
+    if return_grid:
+        return new, grids
+    return new
+
+
+def step_n(state, p: Params, n_steps: int):
+    for _ in range(n_steps):
+        state = substep(state, p)
+    return state
+
+
+def state_from_scene(sc):
+    return tuple(as64(a) for a in (sc.x, sc.v, sc.C, sc.F))
+
+
+# ---------------------------------------------------------------------------
+# Gaussian kinematics: covariance Sigma(t) = F Sigma0 F^T (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+def covariance(F, cov0_6):
+    c = as64(cov0_6)
+    S = torch.stack([torch.stack([c[:, 0], c[:, 1], c[:, 2]], -1),
+                     torch.stack([c[:, 1], c[:, 3], c[:, 4]], -1),
+                     torch.stack([c[:, 2], c[:, 4], c[:, 5]], -1)], 1)
+    out = F @ S @ F.transpose(-1, -2)
+    return torch.stack([out[:, 0, 0], out[:, 0, 1], out[:, 0, 2],
+                        out[:, 1, 1], out[:, 1, 2], out[:, 2, 2]], -1)
+
+
+# ---------------------------------------------------------------------------
+# Adjoint (autograd through the elastic substep)
+# ---------------------------------------------------------------------------
+
+def polar_rotation_newton(F, iters=40):
+    """Rotation factor of F = R S (det F > 0) by X <- (X + X^-T)/2."""
+    X = F
+    for _ in range(iters):
+        X = 0.5 * (X + torch.linalg.inv(X).transpose(-1, -2))
+    return X
+
+
+def _tau_fcr_differentiable(F, mu, lam):
+    R = polar_rotation_newton(F)
+    J = torch.linalg.det(F)
+    eye = torch.eye(3, dtype=F.dtype)
+    return 2.0 * mu[:, None, None] * (F - R) @ F.transpose(-1, -2) \
+        + (lam * J * (J - 1.0))[:, None, None] * eye
+
+
+def _tau_hencky_differentiable(F, mu, lam):
+    """Hencky tau = mu log(F F^T) + (lam/2) tr(log(F F^T)) I, the log of the
+    SPD matrix b = F F^T taken by inverse scaling and squaring (square roots
+    by the Denman-Beavers iteration, then the log series), so no SVD enters
+    the derivative."""
+    b = F @ F.transpose(-1, -2)
+    eye = torch.eye(3, dtype=F.dtype).expand_as(b)
+    k = 0
+    Y = b
+    # square roots until close to I
+    for _ in range(8):
+        Z = eye
+        Yk = Y
+        for _ in range(30):
+            Yk, Z = 0.5 * (Yk + torch.linalg.inv(Z)), 0.5 * (Z + torch.linalg.inv(Yk))
+        Y = Yk
+        k += 1
+    X = Y - eye
+    L = torch.zeros_like(X)
+    P = eye.clone()
+    for j in range(1, 30):
+        P = P @ X
+        L = L + ((-1.0) ** (j + 1) / j) * P
+    logb = (2.0 ** k) * L
+    tr = logb.diagonal(dim1=-2, dim2=-1).sum(-1)
+    return mu[:, None, None] * logb + (0.5 * lam * tr)[:, None, None] * eye
+
+
+def _kirchhoff_differentiable(F, mu, lam, mat_id, materials):
+    tau = torch.zeros_like(F)
+    for k, mat in enumerate(materials):
+        sel = mat_id == k
+        if not bool(sel.any()):
+            continue
+        if mat["plastic"] != PLASTIC_NONE:
+            raise NotImplementedError("the adjoint oracle covers the elastic models only")
+        fn = _tau_fcr_differentiable if mat["elastic"] == ELASTIC_FCR else _tau_hencky_differentiable
+        tau = tau.index_put((sel.nonzero()[:, 0],), fn(F[sel], mu[sel], lam[sel]))
+    return tau
+
+
+def substep_differentiable(state, p: Params, log_E, nu):
+    x, v, C, F = state
+    outs = []
+    for b in range(len(p.batch_offsets) - 1):
+        sl = slice(p.batch_offsets[b], p.batch_offsets[b + 1])
+        xb, vb, Cb, Fb = x[sl], v[sl], C[sl], F[sl]
+        if bool((torch.linalg.det(Fb.detach()) <= 0).any()):
+            raise ValueError("adjoint oracle needs det F > 0")
+        mu, lam = lame(log_E[sl], nu[sl])
+        tau = _kirchhoff_differentiable(Fb, mu, lam, p.mat_id[sl], p.materials)
+        m, mv = p2g(xb, vb, Cb, tau, p.mass[sl], p.vol0[sl], p.n, p.dt)
+        vg = grid_update(m, mv, p.n, p.dt, p.gravity, p.bound)
+        outs.append(g2p(xb, Fb, vg, p.n, p.dt))  # identity plasticity
+    return tuple(torch.cat([o[i] for o in outs]) for i in range(4))
+
+
+def forward_differentiable(state0, p: Params, n_steps, log_E=None, nu=None):
+    log_E = p.log_E if log_E is None else log_E
+    nu = p.nu if nu is None else nu
+    state = state0
+    for _ in range(n_steps):
+        state = substep_differentiable(state, p, log_E, nu)
+    return state
+
+
+def adjoint(state0, p: Params, n_steps: int, cotangents, want_state0=False):
+    """Vector-Jacobian product of the n-substep map.
+
+    cotangents = (gx, gv, gC, gF) on the final state (None = zero).  Returns
+    dict with g_logE, g_nu [N] and, if asked, g_x0, g_v0, g_C0, g_F0.
+    """
+    log_E = p.log_E.clone().requires_grad_(True)
+    nu = p.nu.clone().requires_grad_(True)
+    s0 = tuple(a.clone().requires_grad_(want_state0) for a in state0)
+    out = forward_differentiable(s0, p, n_steps, log_E, nu)
+    total = torch.zeros((), dtype=F64)
+    for o, g in zip(out, cotangents):
+        if g is not None:
+            total = total + (o * as64(g)).sum()
+    inputs = [log_E, nu] + (list(s0) if want_state0 else [])
+    grads = torch.autograd.grad(total, inputs, allow_unused=True)
+    grads = [torch.zeros_like(i) if g is None else g for g, i in zip(grads, inputs)]
+    res = dict(g_logE=grads[0], g_nu=grads[1], final=tuple(o.detach() for o in out))
+    if want_state0:
+        res.update(g_x0=grads[2], g_v0=grads[3], g_C0=grads[4], g_F0=grads[5])
+    return res
+
+
+def position_mse(x, x_target):
+    """Loss of the differentiation workload: mean over N x 3 components."""
+    return ((x - as64(x_target)) ** 2).mean()
