@@ -1,0 +1,177 @@
+/*
+ * fastmpm.h -- C ABI of the MI355X MLS-MPM substep library (libfastmpm.so).
+ *
+ * The library advances particles (Gaussian centres and interior fill points
+ * of FastPhysGS, arXiv 2602.01723) through the MLS-MPM substep:
+ *   Kirchhoff stress of the particle's elastic model (App. A.2, App. B.1),
+ *   particle-to-grid transfer with quadratic B-spline weights, APIC affine
+ *   momentum and the MLS stress term (Sec. 4.2 momentum-exchange equation;
+ *   App. A.1 P2G),
+ *   grid update with gravity and sticky walls (App. A.1 grid update),
+ *   grid-to-particle transfer of v, C, x and F (App. A.1 G2P),
+ *   plastic return mapping after the stress (App. A.2, App. B.2; Alg. 1).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an int status (mpm_status); 0 is success.
+ *  - Argument and configuration checks run on the host, before any device
+ *    work, and return MPM_EINVAL without touching device memory.
+ *  - Device pointers are caller-owned (allocate them with hipMalloc or a
+ *    PyTorch CUDA tensor).  The library never frees them.  The context owns
+ *    its internal workspace, allocated by mpm_init and released by
+ *    mpm_destroy; no other call allocates device memory.
+ *  - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ *    void*; NULL = the null stream) and is asynchronous unless stated.
+ *  - One context may be used by one stream at a time; calls on a context
+ *    are not thread-safe.
+ *  - HIP runtime failures return MPM_EDEVICE; mpm_last_error() gives text.
+ *
+ * Particle arrays are structure-of-arrays, float32, component-major:
+ *    x[3][N], v[3][N]          (x[c*N + p] is component c of particle p)
+ *    C[9][N], F[9][N]          (row-major 3x3: entry (r,c) at plane 3*r+c)
+ *    mass[N], vol0[N]          (kg, m^3: m_p and the rest volume V_p^0)
+ *    log_E[N], nu[N]           (natural log of Young's modulus in Pa; Poisson ratio)
+ *    mat_id[N]                 (int32 index into the material table)
+ * The simulation domain is [0,1)^3 with n^3 grid nodes at i*dx, dx = 1/n.
+ * A batch of scenes is stored back to back: scene b owns particles
+ * [offsets[b], offsets[b+1]) and its own n^3 grid.
+ */
+#ifndef FASTMPM_H
+#define FASTMPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPM_ABI_VERSION 1
+
+typedef struct mpm_context* mpm_ctx;
+
+typedef enum {
+  MPM_OK = 0,
+  MPM_EINVAL = -1,       /* bad argument or configuration (nothing was enqueued) */
+  MPM_ENOMEM = -2,       /* device allocation failed, or a caller buffer is too small */
+  MPM_EDEVICE = -3,      /* a HIP runtime call failed */
+  MPM_ESTATE = -4,       /* call out of order (e.g. backward without a taped forward) */
+  MPM_EUNSTABLE = -5,    /* device counters saw NaN/Inf or a stencil leaving the grid */
+  MPM_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} mpm_status;
+
+/* Elastic models (App. A.2 / B.1).
+ *   FCR:    tau = 2 mu (F - R) F^T + lam J (J - 1) I, R the rotation of F = R S.
+ *   HENCKY: tau = U diag(2 mu eps + lam tr(eps)) U^T, eps = log(max(sigma, 1e-4)),
+ *           F = U diag(sigma) V^T with U, V rotations.  */
+enum { MPM_ELASTIC_FCR = 0, MPM_ELASTIC_HENCKY = 1 };
+
+/* Plastic return maps (App. A.2 / B.2), applied to F after the stress.
+ *   NONE:            F' = F.
+ *   VON_MISES:       project the log-strain deviator onto |eps_hat| = yield/(2 mu).
+ *   DRUCKER_PRAGER:  tension (tr eps > 0) -> F' = U V^T; else
+ *                    dgamma = |eps_hat| + (3 lam + 2 mu)/(2 mu) tr(eps) alpha,
+ *                    alpha = sqrt(2/3) 2 sin(phi)/(3 - sin(phi)), zero cohesion.  */
+enum { MPM_PLASTIC_NONE = 0, MPM_PLASTIC_VON_MISES = 1, MPM_PLASTIC_DRUCKER_PRAGER = 2 };
+
+typedef struct {
+  int32_t elastic;       /* MPM_ELASTIC_* */
+  int32_t plastic;       /* MPM_PLASTIC_* */
+  float yield_stress;    /* von Mises yield stress sigma_y, Pa (> 0 for VON_MISES) */
+  float friction_deg;    /* Drucker-Prager friction angle phi in degrees (0 < phi < 90) */
+} mpm_material;
+
+typedef struct {
+  int32_t abi_version;   /* must be MPM_ABI_VERSION */
+  int32_t grid_res;      /* n: nodes per axis, 8 <= n <= 1024 */
+  int32_t bound;         /* sticky wall width in nodes (v_i = 0 if any index < bound or >= n - bound) */
+  int32_t n_batch;       /* number of independent scenes, >= 1 */
+  float dt;              /* substep, s (> 0) */
+  float gravity[3];      /* acceleration, m/s^2, added to grid velocity as dt * g */
+  int32_t sort_every;    /* re-sort particles by cell every this many substeps (0 = library default) */
+  uint32_t flags;        /* reserved, must be 0 */
+} mpm_config;
+
+typedef struct {
+  float* x;              /* [3][N] in/out */
+  float* v;              /* [3][N] in/out */
+  float* C;              /* [9][N] in/out (APIC affine matrix) */
+  float* F;              /* [9][N] in/out (elastic deformation gradient) */
+  const float* mass;     /* [N] */
+  const float* vol0;     /* [N] */
+  const float* log_E;    /* [N] */
+  const float* nu;       /* [N], 0 <= nu < 0.5 */
+  const int32_t* mat_id; /* [N], 0 <= mat_id < n_materials */
+} mpm_particles;
+
+typedef struct {
+  int64_t nonfinite;     /* particle-substeps that produced a NaN/Inf x or F */
+  int64_t out_of_grid;   /* particle-substeps whose stencil left the grid (skipped) */
+  int64_t tile_overflow; /* P2G/G2P chunks that fell back to global-memory transfers */
+  int64_t substeps;      /* substeps run since mpm_init */
+} mpm_diag;
+
+/* Status code as text (static storage). */
+const char* mpm_status_string(int status);
+
+/* Text of the last error on this context (static per context; never NULL). */
+const char* mpm_last_error(mpm_ctx ctx);
+
+/* Create a context for n_particles particles split into cfg->n_batch scenes
+ * by batch_offsets (host array of n_batch + 1 int64, offsets[0] = 0,
+ * non-decreasing, offsets[n_batch] = n_particles; NULL allowed when
+ * n_batch == 1).  Copies the material table (n_materials >= 1).
+ * Allocates the internal workspace (grids, sort and particle buffers) on the
+ * current HIP device.  On success *out holds the context. */
+int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_materials,
+             int64_t n_particles, const int64_t* batch_offsets, mpm_ctx* out);
+
+/* One substep: stress -> P2G -> grid update -> G2P -> return map, updating
+ * x, v, C, F in place.  Equivalent to mpm_step_n(ctx, p, 1, NULL, stream). */
+int mpm_substep(mpm_ctx ctx, const mpm_particles* p, void* stream);
+
+/* n_steps >= 0 substeps (Alg. 1 stage-1 inner loop).  tape: NULL for a
+ * forward-only run, else a device buffer of mpm_tape_size() bytes that
+ * receives the checkpoints mpm_backward needs (state every K substeps,
+ * K = checkpoint_every >= 1). */
+int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps,
+               void* tape, int32_t checkpoint_every, void* stream);
+
+/* Bytes of the tape buffer for n_steps substeps checkpointed every K. */
+int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes);
+
+/* Reverse of the n_steps substeps taped by the last mpm_step_n call with
+ * the same tape (elastic models with identity plasticity).  Inputs: the
+ * adjoints of the final x, v, C, F (device [3][N], [3][N], [9][N], [9][N];
+ * any may be NULL = zero).  Outputs (overwritten): g_log_E[N], g_nu[N] and,
+ * when non-NULL, the adjoints of the initial state g_x0, g_v0, g_C0, g_F0.
+ * p supplies the parameter arrays (its state arrays are not read). */
+int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t n_steps,
+                 const float* g_x, const float* g_v, const float* g_C, const float* g_F,
+                 float* g_log_E, float* g_nu,
+                 float* g_x0, float* g_v0, float* g_C0, float* g_F0, void* stream);
+
+/* Grid of the most recent substep, for tests: m [B][n^3], mv and v [B][n^3][3],
+ * node (ix, iy, iz) at ((ix*n)+iy)*n+iz (iz fastest).  Any pointer may be NULL. */
+int mpm_grid_state(mpm_ctx ctx, float* m, float* mv, float* v, void* stream);
+
+/* Gaussian covariances Sigma_p = F_p Sigma0_p F_p^T (Sec. 3.2) for n
+ * particles: F [9][n], cov0 and cov [6][n] as (xx, xy, xz, yy, yz, zz). */
+int mpm_export_covariance(mpm_ctx ctx, const float* F, const float* cov0, float* cov,
+                          int64_t n, void* stream);
+
+/* Synchronises the context's last stream and reads the device counters. */
+int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out);
+
+/* Launch tuning (set by the autotuner; 0 keeps the current value):
+ * chunk = particles per workgroup (64..1024, multiple of 64),
+ * sort_every = substeps between re-sorts, tile_cap = LDS tile nodes. */
+int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_cap);
+
+/* Release the context and its workspace (synchronises the device). */
+int mpm_destroy(mpm_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTMPM_H */

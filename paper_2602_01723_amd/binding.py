@@ -1,0 +1,270 @@
+"""Python binding of libfastmpm.so (ctypes; argument marshalling only).
+
+The functions keep the C names (``mpm_init``, ``mpm_substep``,
+``mpm_step_n``, ``mpm_backward``, ...).  Device memory comes from PyTorch
+CUDA (HIP) tensors and work is enqueued on the current torch stream.  Every
+step of the simulation runs in the HIP library; if the library is missing
+the binding raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfastmpm.so")
+
+MPM_ABI_VERSION = 1
+MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_tape_size",
+            "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
+            "mpm_set_tuning", "mpm_destroy")
+
+
+class MPMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class mpm_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("grid_res", ctypes.c_int32), ("bound", ctypes.c_int32),
+                ("n_batch", ctypes.c_int32), ("dt", ctypes.c_float), ("gravity", ctypes.c_float * 3),
+                ("sort_every", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class mpm_material(ctypes.Structure):
+    _fields_ = [("elastic", ctypes.c_int32), ("plastic", ctypes.c_int32), ("yield_stress", ctypes.c_float),
+                ("friction_deg", ctypes.c_float)]
+
+
+class mpm_particles(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "v", "C", "F", "mass", "vol0", "log_E", "nu", "mat_id")]
+
+
+class mpm_diag(ctypes.Structure):
+    _fields_ = [("nonfinite", ctypes.c_int64), ("out_of_grid", ctypes.c_int64), ("tile_overflow", ctypes.c_int64),
+                ("substeps", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (built by ``paper_2602_01723_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2602_01723_amd.build` "
+                           "(there is no other implementation of the substep)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "mpm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "mpm_last_error": (ctypes.c_char_p, [vp]),
+        "mpm_init": (ctypes.c_int, [ctypes.POINTER(mpm_config), ctypes.POINTER(mpm_material), i32, i64,
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp)]),
+        "mpm_substep": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp]),
+        "mpm_step_n": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), i32, vp, i32, vp]),
+        "mpm_tape_size": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(sz)]),
+        "mpm_backward": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp, i32] + [vp] * 10 + [vp]),
+        "mpm_grid_state": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "mpm_export_covariance": (ctypes.c_int, [vp, vp, vp, vp, i64, vp]),
+        "mpm_get_diagnostics": (ctypes.c_int, [vp, ctypes.POINTER(mpm_diag)]),
+        "mpm_set_tuning": (ctypes.c_int, [vp, i32, i32, i32]),
+        "mpm_destroy": (ctypes.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream=None) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream) or None
+
+
+class Context:
+    """Owns an mpm_ctx; destroyed on close() / garbage collection."""
+
+    def __init__(self, handle, n_particles, n_batch, grid_res):
+        self.handle = handle
+        self.n_particles = n_particles
+        self.n_batch = n_batch
+        self.grid_res = grid_res
+
+    def close(self):
+        if self.handle:
+            load().mpm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return load().mpm_last_error(self.handle).decode()
+
+
+def _check(ctx: Optional[Context], rc: int, what: str):
+    if rc != MPM_OK:
+        lib = load()
+        detail = ctx.last_error() if ctx is not None and ctx.handle else ""
+        raise MPMError(rc, f"{what}: {lib.mpm_status_string(rc).decode()} ({detail})")
+
+
+@dataclass
+class Particles:
+    """Device particle arrays in the library's SoA layout (float32 / int32)."""
+    x: "torch.Tensor"       # [3, N]
+    v: "torch.Tensor"       # [3, N]
+    C: "torch.Tensor"       # [9, N]
+    F: "torch.Tensor"       # [9, N]
+    mass: "torch.Tensor"    # [N]
+    vol0: "torch.Tensor"    # [N]
+    log_E: "torch.Tensor"   # [N]
+    nu: "torch.Tensor"      # [N]
+    mat_id: "torch.Tensor"  # [N] int32
+
+    @property
+    def n(self) -> int:
+        return int(self.mass.shape[0])
+
+    def as_struct(self) -> mpm_particles:
+        return mpm_particles(*[_ptr(getattr(self, k)) for k in ("x", "v", "C", "F", "mass", "vol0", "log_E",
+                                                                "nu", "mat_id")])
+
+    @classmethod
+    def from_arrays(cls, x, v, C, F, mass, vol0, log_E, nu, mat_id, device="cuda"):
+        import torch
+        N = len(mass)
+
+        def f32(a, shape):
+            t = torch.as_tensor(np.ascontiguousarray(np.asarray(a, np.float32).reshape(N, -1).T)
+                                if shape else np.asarray(a, np.float32))
+            return t.contiguous().to(device)
+        return cls(x=f32(x, 3), v=f32(v, 3), C=f32(C, 9), F=f32(F, 9), mass=f32(mass, 0), vol0=f32(vol0, 0),
+                   log_E=f32(log_E, 0), nu=f32(nu, 0),
+                   mat_id=torch.as_tensor(np.asarray(mat_id, np.int32)).contiguous().to(device))
+
+    @classmethod
+    def from_scene(cls, sc, device="cuda"):
+        return cls.from_arrays(sc.x, sc.v, sc.C, sc.F, sc.mass, sc.vol0, sc.log_E, sc.nu, sc.mat_id, device)
+
+    def state_numpy(self):
+        """(x [N,3], v [N,3], C [N,3,3], F [N,3,3]) as float32 NumPy arrays."""
+        N = self.n
+        return (self.x.T.cpu().numpy().copy(), self.v.T.cpu().numpy().copy(),
+                self.C.T.cpu().numpy().reshape(N, 3, 3).copy(), self.F.T.cpu().numpy().reshape(N, 3, 3).copy())
+
+    def clone(self) -> "Particles":
+        return Particles(**{k: getattr(self, k).clone() for k in self.__dataclass_fields__})
+
+
+def mpm_init(grid_res, dt, materials: Sequence[dict], n_particles, batch_offsets=None, gravity=(0.0, -9.8, 0.0),
+             bound=3, sort_every=0) -> Context:
+    lib = load()
+    n_batch = 1 if batch_offsets is None else len(batch_offsets) - 1
+    cfg = mpm_config(MPM_ABI_VERSION, int(grid_res), int(bound), int(n_batch), float(dt),
+                     (ctypes.c_float * 3)(*[float(g) for g in gravity]), int(sort_every), 0)
+    mats = (mpm_material * len(materials))(*[mpm_material(int(m["elastic"]), int(m["plastic"]),
+                                                          float(m.get("yield_stress", 0.0)),
+                                                          float(m.get("friction_deg", 0.0))) for m in materials])
+    offs = None
+    if batch_offsets is not None:
+        offs = (ctypes.c_int64 * len(batch_offsets))(*[int(b) for b in batch_offsets])
+    h = ctypes.c_void_p()
+    rc = lib.mpm_init(ctypes.byref(cfg), mats, len(materials), int(n_particles), offs, ctypes.byref(h))
+    _check(None, rc, "mpm_init")
+    return Context(h, int(n_particles), n_batch, int(grid_res))
+
+
+def init_from_scene(sc, sort_every=0) -> Context:
+    return mpm_init(sc.grid_res, sc.dt, sc.materials, sc.n,
+                    None if sc.n_batch == 1 else sc.batch_offsets, sc.gravity, sc.bound, sort_every)
+
+
+def mpm_substep(ctx: Context, p: Particles, stream=None):
+    s = p.as_struct()
+    _check(ctx, load().mpm_substep(ctx.handle, ctypes.byref(s), _stream(stream)), "mpm_substep")
+
+
+def mpm_step_n(ctx: Context, p: Particles, n_steps: int, tape=None, checkpoint_every=0, stream=None):
+    s = p.as_struct()
+    rc = load().mpm_step_n(ctx.handle, ctypes.byref(s), int(n_steps), _ptr(tape), int(checkpoint_every),
+                           _stream(stream))
+    _check(ctx, rc, "mpm_step_n")
+
+
+def mpm_tape_size(ctx: Context, n_steps: int, checkpoint_every: int) -> int:
+    out = ctypes.c_size_t()
+    _check(ctx, load().mpm_tape_size(ctx.handle, int(n_steps), int(checkpoint_every), ctypes.byref(out)),
+           "mpm_tape_size")
+    return int(out.value)
+
+
+def mpm_backward(ctx: Context, p: Particles, tape, n_steps: int, g_x=None, g_v=None, g_C=None, g_F=None,
+                 g_log_E=None, g_nu=None, g_x0=None, g_v0=None, g_C0=None, g_F0=None, stream=None):
+    s = p.as_struct()
+    rc = load().mpm_backward(ctx.handle, ctypes.byref(s), _ptr(tape), int(n_steps), _ptr(g_x), _ptr(g_v),
+                             _ptr(g_C), _ptr(g_F), _ptr(g_log_E), _ptr(g_nu), _ptr(g_x0), _ptr(g_v0), _ptr(g_C0),
+                             _ptr(g_F0), _stream(stream))
+    _check(ctx, rc, "mpm_backward")
+
+
+def mpm_grid_state(ctx: Context, m=None, mv=None, v=None, stream=None):
+    rc = load().mpm_grid_state(ctx.handle, _ptr(m), _ptr(mv), _ptr(v), _stream(stream))
+    _check(ctx, rc, "mpm_grid_state")
+
+
+def grid_state(ctx: Context):
+    """Convenience: (m [B, n^3], mv [B, n^3, 3], v [B, n^3, 3]) device tensors."""
+    import torch
+    nodes = ctx.n_batch * ctx.grid_res ** 3
+    m = torch.empty(nodes, device="cuda")
+    mv = torch.empty(nodes, 3, device="cuda")
+    v = torch.empty(nodes, 3, device="cuda")
+    mpm_grid_state(ctx, m, mv, v)
+    return m, mv, v
+
+
+def mpm_export_covariance(ctx: Context, F, cov0, cov, stream=None):
+    n = int(F.shape[-1])
+    rc = load().mpm_export_covariance(ctx.handle, _ptr(F), _ptr(cov0), _ptr(cov), n, _stream(stream))
+    _check(ctx, rc, "mpm_export_covariance")
+
+
+def mpm_get_diagnostics(ctx: Context) -> dict:
+    d = mpm_diag()
+    rc = load().mpm_get_diagnostics(ctx.handle, ctypes.byref(d))
+    out = dict(nonfinite=d.nonfinite, out_of_grid=d.out_of_grid, tile_overflow=d.tile_overflow,
+               substeps=d.substeps, status=rc)
+    if rc not in (MPM_OK, MPM_EUNSTABLE):
+        _check(ctx, rc, "mpm_get_diagnostics")
+    return out
+
+
+def mpm_set_tuning(ctx: Context, chunk=0, sort_every=0, tile_cap=0):
+    _check(ctx, load().mpm_set_tuning(ctx.handle, int(chunk), int(sort_every), int(tile_cap)), "mpm_set_tuning")
+
+
+def mpm_destroy(ctx: Context):
+    ctx.close()

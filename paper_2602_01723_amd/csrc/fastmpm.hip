@@ -1,0 +1,433 @@
+// libfastmpm.so: host side of the C ABI declared in include/fastmpm.h.
+//
+// A context holds the configuration, the material table and the internal
+// workspace: cell-sorted copies of the particle state, two grids (the one a
+// kernel reads and the one it accumulates into), the counting-sort buffers
+// and the device diagnostics counters.  mpm_step_n sorts the caller's
+// particles by cell, runs the substeps on the sorted copies (re-sorting
+// every `sort_every` substeps) and writes the state back in caller order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fastmpm.h"
+#include "mpm_kernels.hpp"
+
+using fmpm::kBlock;
+
+struct mpm_context {
+  mpm_config cfg{};
+  int n_mat = 0;
+  fmpm::Material mats[fmpm::kMaxMaterials]{};
+  int64_t N = 0;
+  int B = 1;
+  std::vector<int64_t> offsets;
+  int n = 0, nb = 0;
+  int64_t nodes = 0;  // B * n^3
+  int64_t bins = 0;   // sort bins
+  int64_t n_bsum = 0;
+  int n_chunks = 0;
+  int tile_cap = fmpm::kTileCapMax;
+  int sort_every = 8;
+
+  float *xs = nullptr, *vs = nullptr, *Cs = nullptr, *Fs = nullptr, *xs2 = nullptr, *Fs2 = nullptr;
+  float4 *prm = nullptr, *prm2 = nullptr;
+  int *mat = nullptr, *mat2 = nullptr, *pid = nullptr, *pid2 = nullptr, *perm = nullptr;
+  float4* grid[2] = {nullptr, nullptr};
+  int *chunk_start = nullptr, *chunk_batch = nullptr;
+  uint32_t *keys = nullptr, *slots = nullptr, *count = nullptr, *bsum = nullptr;
+  unsigned long long* diag = nullptr;
+  std::vector<void*> allocations;
+
+  int last_grid = -1;
+  int64_t substeps = 0;
+  hipStream_t last_stream = nullptr;
+  std::string err = "no error";
+};
+
+namespace {
+
+const char* kStatusText[] = {"ok", "invalid argument", "out of memory", "HIP device error",
+                             "call out of order", "unstable simulation", "unsupported"};
+
+int fail(mpm_ctx ctx, int code, const std::string& what) {
+  if (ctx) ctx->err = what;
+  return code;
+}
+
+int hip_fail(mpm_ctx ctx, const char* what, hipError_t e) {
+  return fail(ctx, MPM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                   \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_fail((ctx), #call, e_); \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx, name)                                  \
+  do {                                                           \
+    hipError_t e_ = hipGetLastError();                           \
+    if (e_ != hipSuccess) return hip_fail((ctx), (name), e_);   \
+  } while (0)
+
+template <typename T>
+int alloc(mpm_ctx ctx, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MPM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  ctx->allocations.push_back(q);
+  *p = static_cast<T*>(q);
+  return MPM_OK;
+}
+
+inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads); }
+
+int fill_u32(mpm_ctx ctx, void* p, int64_t count, hipStream_t s) {
+  const int64_t n4 = std::max<int64_t>(count >> 2, 4);
+  fmpm::k_fill_u32<<<blocks_for(n4, 256), 256, 0, s>>>((uint32_t*)p, 0u, count);
+  LAUNCH_CHECK(ctx, "k_fill_u32");
+  return MPM_OK;
+}
+
+fmpm::SubstepArgs make_args(mpm_ctx c) {
+  fmpm::SubstepArgs a{};
+  a.x = c->xs;
+  a.v = c->vs;
+  a.C = c->Cs;
+  a.F = c->Fs;
+  a.prm = c->prm;
+  a.mat = c->mat;
+  a.N = c->N;
+  a.chunk_start = c->chunk_start;
+  a.chunk_batch = c->chunk_batch;
+  a.n = c->n;
+  a.bound = c->cfg.bound;
+  a.dt = c->cfg.dt;
+  for (int k = 0; k < 3; ++k) a.g[k] = c->cfg.gravity[k];
+  a.tile_cap = c->tile_cap;
+  a.diag = c->diag;
+  a.n_materials = c->n_mat;
+  for (int k = 0; k < c->n_mat; ++k) a.mats[k] = c->mats[k];
+  return a;
+}
+
+// counting sort of particles by cell key; perm[j] = source index of slot j
+int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
+  int rc = fill_u32(c, c->count, c->bins, s);
+  if (rc) return rc;
+  fmpm::k_cell_keys<<<c->n_chunks, kBlock, 0, s>>>(x, c->N, c->chunk_start, c->chunk_batch, c->n, c->nb, c->keys,
+                                                   c->slots, c->count);
+  LAUNCH_CHECK(c, "k_cell_keys");
+  fmpm::k_scan_reduce<<<(unsigned)c->n_bsum, fmpm::kScanThreads, 0, s>>>(c->count, c->bsum, c->bins);
+  LAUNCH_CHECK(c, "k_scan_reduce");
+  fmpm::k_scan_top<<<1, fmpm::kScanThreads, 0, s>>>(c->bsum, c->n_bsum);
+  LAUNCH_CHECK(c, "k_scan_top");
+  fmpm::k_scan_apply<<<(unsigned)c->n_bsum, fmpm::kScanThreads, 0, s>>>(c->count, c->bsum, c->bins);
+  LAUNCH_CHECK(c, "k_scan_apply");
+  fmpm::k_place<<<blocks_for(c->N, 256), 256, 0, s>>>(c->keys, c->slots, c->count, c->perm, c->N);
+  LAUNCH_CHECK(c, "k_place");
+  return MPM_OK;
+}
+
+int gather_from_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
+  int rc = sort_keys(c, p->x, s);
+  if (rc) return rc;
+  const unsigned g = blocks_for(c->N, 256);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->xs, p->x, c->perm, 3, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->vs, p->v, c->perm, 3, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Cs, p->C, c->perm, 9, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Fs, p->F, c->perm, 9, c->N);
+  fmpm::k_gather_params<<<g, 256, 0, s>>>(c->prm, c->mat, c->pid, p->mass, p->vol0, p->log_E, p->nu, p->mat_id,
+                                          c->perm, c->N);
+  LAUNCH_CHECK(c, "gather");
+  return MPM_OK;
+}
+
+int resort_internal(mpm_ctx c, hipStream_t s) {
+  int rc = sort_keys(c, c->xs, s);
+  if (rc) return rc;
+  const unsigned g = blocks_for(c->N, 256);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->xs2, c->xs, c->perm, 3, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Fs2, c->Fs, c->perm, 9, c->N);
+  fmpm::k_gather_misc<<<g, 256, 0, s>>>(c->prm2, c->mat2, c->pid2, c->prm, c->mat, c->pid, c->perm, c->N);
+  LAUNCH_CHECK(c, "resort");
+  std::swap(c->xs, c->xs2);
+  std::swap(c->Fs, c->Fs2);
+  std::swap(c->prm, c->prm2);
+  std::swap(c->mat, c->mat2);
+  std::swap(c->pid, c->pid2);
+  return MPM_OK;
+}
+
+int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
+  const unsigned g = blocks_for(c->N, 256);
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->x, c->xs, c->pid, 3, c->N);
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->v, c->vs, c->pid, 3, c->N);
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->C, c->Cs, c->pid, 9, c->N);
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->F, c->Fs, c->pid, 9, c->N);
+  LAUNCH_CHECK(c, "scatter");
+  return MPM_OK;
+}
+
+template <int MODE>
+int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hipStream_t s) {
+  fmpm::SubstepArgs a = make_args(c);
+  a.grid_in = gin;
+  a.grid_out = gout;
+  a.write_vc = write_vc;
+  fmpm::k_substep<MODE><<<c->n_chunks, kBlock, 0, s>>>(a);
+  LAUNCH_CHECK(c, "k_substep");
+  return MPM_OK;
+}
+
+int check_particles(mpm_ctx ctx, const mpm_particles* p) {
+  if (!p) return fail(ctx, MPM_EINVAL, "particles is NULL");
+  if (ctx->N == 0) return MPM_OK;
+  if (!p->x || !p->v || !p->C || !p->F || !p->mass || !p->vol0 || !p->log_E || !p->nu || !p->mat_id)
+    return fail(ctx, MPM_EINVAL, "a particle array is NULL");
+  return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpm_status_string(int status) {
+  if (status > 0 || status < -6) return "unknown status";
+  return kStatusText[-status];
+}
+
+const char* mpm_last_error(mpm_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_materials, int64_t n_particles,
+             const int64_t* batch_offsets, mpm_ctx* out) {
+  if (!out) return MPM_EINVAL;
+  *out = nullptr;
+  if (!cfg || !materials) return MPM_EINVAL;
+  if (cfg->abi_version != MPM_ABI_VERSION) return MPM_EINVAL;
+  if (cfg->grid_res < 8 || cfg->grid_res > 1024) return MPM_EINVAL;
+  if (cfg->bound < 0 || 2 * cfg->bound + 3 > cfg->grid_res) return MPM_EINVAL;
+  if (cfg->n_batch < 1) return MPM_EINVAL;
+  if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt)) return MPM_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(cfg->gravity[k])) return MPM_EINVAL;
+  if (cfg->sort_every < 0 || cfg->flags != 0) return MPM_EINVAL;
+  if (n_materials < 1 || n_materials > fmpm::kMaxMaterials) return MPM_EINVAL;
+  if (n_particles < 0 || n_particles > (int64_t)0x7fffff00) return MPM_EINVAL;
+  std::vector<int64_t> off;
+  if (batch_offsets) {
+    off.assign(batch_offsets, batch_offsets + cfg->n_batch + 1);
+  } else {
+    if (cfg->n_batch != 1) return MPM_EINVAL;
+    off = {0, n_particles};
+  }
+  if (off[0] != 0 || off.back() != n_particles) return MPM_EINVAL;
+  for (int b = 0; b < cfg->n_batch; ++b)
+    if (off[b + 1] < off[b]) return MPM_EINVAL;
+  fmpm::Material mats[fmpm::kMaxMaterials]{};
+  for (int k = 0; k < n_materials; ++k) {
+    const mpm_material& m = materials[k];
+    if (m.elastic != MPM_ELASTIC_FCR && m.elastic != MPM_ELASTIC_HENCKY) return MPM_EINVAL;
+    if (m.plastic < MPM_PLASTIC_NONE || m.plastic > MPM_PLASTIC_DRUCKER_PRAGER) return MPM_EINVAL;
+    if (m.plastic == MPM_PLASTIC_VON_MISES && !(m.yield_stress > 0.0f)) return MPM_EINVAL;
+    if (m.plastic == MPM_PLASTIC_DRUCKER_PRAGER && !(m.friction_deg > 0.0f && m.friction_deg < 90.0f))
+      return MPM_EINVAL;
+    mats[k].elastic = m.elastic;
+    mats[k].plastic = m.plastic;
+    mats[k].yield_stress = m.yield_stress;
+    const double sp = std::sin((double)m.friction_deg * M_PI / 180.0);
+    mats[k].dp_alpha = (float)(std::sqrt(2.0 / 3.0) * 2.0 * sp / (3.0 - sp));
+  }
+  const int n = cfg->grid_res;
+  const int nb = (n + 3) / 4;
+  const int64_t bins = (int64_t)cfg->n_batch * nb * nb * nb * 64;
+  if (bins >= ((int64_t)1 << 32)) return MPM_EINVAL;
+
+  mpm_ctx c = new mpm_context();
+  c->cfg = *cfg;
+  c->n_mat = n_materials;
+  std::memcpy(c->mats, mats, sizeof(mats));
+  c->N = n_particles;
+  c->B = cfg->n_batch;
+  c->offsets = off;
+  c->n = n;
+  c->nb = nb;
+  c->nodes = (int64_t)cfg->n_batch * n * n * n;
+  c->bins = bins;
+  c->n_bsum = (bins + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  if (cfg->sort_every > 0) c->sort_every = cfg->sort_every;
+
+  std::vector<int> cs, cb;
+  for (int b = 0; b < c->B; ++b)
+    for (int64_t s = off[b]; s < off[b + 1]; s += kBlock) {
+      cs.push_back((int)s);
+      cb.push_back(b);
+    }
+  cs.push_back((int)n_particles);
+  c->n_chunks = (int)cb.size();
+
+  const int64_t N = std::max<int64_t>(n_particles, 1);
+  int rc = MPM_OK;
+  rc = rc ? rc : alloc(c, &c->xs, 3 * N);
+  rc = rc ? rc : alloc(c, &c->vs, 3 * N);
+  rc = rc ? rc : alloc(c, &c->Cs, 9 * N);
+  rc = rc ? rc : alloc(c, &c->Fs, 9 * N);
+  rc = rc ? rc : alloc(c, &c->xs2, 3 * N);
+  rc = rc ? rc : alloc(c, &c->Fs2, 9 * N);
+  rc = rc ? rc : alloc(c, &c->prm, N);
+  rc = rc ? rc : alloc(c, &c->prm2, N);
+  rc = rc ? rc : alloc(c, &c->mat, N);
+  rc = rc ? rc : alloc(c, &c->mat2, N);
+  rc = rc ? rc : alloc(c, &c->pid, N);
+  rc = rc ? rc : alloc(c, &c->pid2, N);
+  rc = rc ? rc : alloc(c, &c->perm, N);
+  rc = rc ? rc : alloc(c, &c->keys, N);
+  rc = rc ? rc : alloc(c, &c->slots, N);
+  rc = rc ? rc : alloc(c, &c->grid[0], c->nodes);
+  rc = rc ? rc : alloc(c, &c->grid[1], c->nodes);
+  rc = rc ? rc : alloc(c, &c->count, bins);
+  rc = rc ? rc : alloc(c, &c->bsum, c->n_bsum);
+  rc = rc ? rc : alloc(c, &c->chunk_start, (int64_t)cs.size());
+  rc = rc ? rc : alloc(c, &c->chunk_batch, (int64_t)std::max<size_t>(cb.size(), 1));
+  rc = rc ? rc : alloc(c, &c->diag, 8);
+  if (rc) {
+    mpm_destroy(c);
+    return rc;
+  }
+  hipError_t e = hipMemcpy(c->chunk_start, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !cb.empty())
+    e = hipMemcpy(c->chunk_batch, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->diag, 0, 8 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->grid[0], 0, (size_t)c->nodes * sizeof(float4));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    mpm_destroy(c);
+    return MPM_EDEVICE;
+  }
+  *out = c;
+  return MPM_OK;
+}
+
+int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, int32_t checkpoint_every,
+               void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  int rc = check_particles(ctx, p);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(ctx, MPM_EINVAL, "n_steps < 0");
+  if (tape) return fail(ctx, MPM_EUNSUPPORTED, "tape not supported by this build");
+  (void)checkpoint_every;
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  if (n_steps == 0 || ctx->N == 0) {
+    ctx->substeps += n_steps;
+    return MPM_OK;
+  }
+  rc = gather_from_caller(ctx, p, s);
+  if (rc) return rc;
+  rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s);
+  if (rc) return rc;
+  rc = launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s);
+  if (rc) return rc;
+  int cur = 0;
+  for (int st = 0; st < n_steps; ++st) {
+    if (st == n_steps - 1) {
+      rc = launch_substep<fmpm::kG2P>(ctx, ctx->grid[cur], nullptr, 1, s);
+      if (rc) return rc;
+    } else {
+      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s);
+      if (rc) return rc;
+      rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], 0, s);
+      if (rc) return rc;
+      cur = 1 - cur;
+      if (ctx->sort_every > 0 && (st + 1) % ctx->sort_every == 0) {
+        rc = resort_internal(ctx, s);
+        if (rc) return rc;
+      }
+    }
+  }
+  ctx->last_grid = cur;
+  ctx->substeps += n_steps;
+  return scatter_to_caller(ctx, p, s);
+}
+
+int mpm_substep(mpm_ctx ctx, const mpm_particles* p, void* stream) {
+  return mpm_step_n(ctx, p, 1, nullptr, 0, stream);
+}
+
+int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes) {
+  if (!ctx || !bytes || n_steps < 0 || checkpoint_every < 1) return MPM_EINVAL;
+  *bytes = 0;
+  return fail(ctx, MPM_EUNSUPPORTED, "tape not supported by this build");
+}
+
+int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t n_steps, const float* g_x,
+                 const float* g_v, const float* g_C, const float* g_F, float* g_log_E, float* g_nu, float* g_x0,
+                 float* g_v0, float* g_C0, float* g_F0, void* stream) {
+  (void)p; (void)tape; (void)n_steps; (void)g_x; (void)g_v; (void)g_C; (void)g_F; (void)g_log_E; (void)g_nu;
+  (void)g_x0; (void)g_v0; (void)g_C0; (void)g_F0; (void)stream;
+  if (!ctx) return MPM_EINVAL;
+  return fail(ctx, MPM_EUNSUPPORTED, "backward not supported by this build");
+}
+
+int mpm_grid_state(mpm_ctx ctx, float* m, float* mv, float* v, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (ctx->last_grid < 0) return fail(ctx, MPM_ESTATE, "no substep has run");
+  hipStream_t s = (hipStream_t)stream;
+  fmpm::SubstepArgs a = make_args(ctx);
+  fmpm::k_grid_export<<<blocks_for(ctx->nodes, 256), 256, 0, s>>>(ctx->grid[ctx->last_grid], ctx->nodes, a, m, mv, v);
+  LAUNCH_CHECK(ctx, "k_grid_export");
+  return MPM_OK;
+}
+
+int mpm_export_covariance(mpm_ctx ctx, const float* F, const float* cov0, float* cov, int64_t n, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (n < 0) return fail(ctx, MPM_EINVAL, "n < 0");
+  if (n == 0) return MPM_OK;
+  if (!F || !cov0 || !cov) return fail(ctx, MPM_EINVAL, "NULL array");
+  fmpm::k_covariance<<<blocks_for(n, 256), 256, 0, (hipStream_t)stream>>>(F, cov0, cov, n);
+  LAUNCH_CHECK(ctx, "k_covariance");
+  return MPM_OK;
+}
+
+int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out) {
+  if (!ctx || !out) return MPM_EINVAL;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  unsigned long long h[8];
+  HIP_TRY(ctx, hipMemcpy(h, ctx->diag, sizeof(h), hipMemcpyDeviceToHost));
+  out->nonfinite = (int64_t)h[0];
+  out->out_of_grid = (int64_t)h[1];
+  out->tile_overflow = (int64_t)h[2];
+  out->substeps = ctx->substeps;
+  return (h[0] || h[1]) ? MPM_EUNSTABLE : MPM_OK;
+}
+
+int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_cap) {
+  if (!ctx) return MPM_EINVAL;
+  if (chunk != 0 && chunk != kBlock) return fail(ctx, MPM_EUNSUPPORTED, "chunk must be 256 in this build");
+  if (sort_every < 0) return fail(ctx, MPM_EINVAL, "sort_every < 0");
+  if (tile_cap != 0 && (tile_cap < 27 || tile_cap > fmpm::kTileCapMax)) return fail(ctx, MPM_EINVAL, "tile_cap");
+  if (sort_every > 0) ctx->sort_every = sort_every;
+  if (tile_cap > 0) ctx->tile_cap = tile_cap;
+  return MPM_OK;
+}
+
+int mpm_destroy(mpm_ctx ctx) {
+  if (!ctx) return MPM_EINVAL;
+  (void)hipDeviceSynchronize();
+  for (void* q : ctx->allocations) (void)hipFree(q);
+  delete ctx;
+  return MPM_OK;
+}
+
+}  // extern "C"

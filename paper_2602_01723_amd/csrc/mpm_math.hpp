@@ -1,0 +1,246 @@
+// Device math of the MLS-MPM substep: FP64 3x3 SVD / polar decomposition,
+// the elastic Kirchhoff stresses and the plastic return maps.
+//
+// SVD: cyclic Jacobi on the symmetric matrix F^T F gives V and the squared
+// singular values; the columns of F V are sorted by length and reduced by
+// three Givens rotations (QR), which yields U in SO(3) and the singular
+// values with the sign of det F carried by the last one (the convention of
+// Irving et al. 2004 for inverted elements).  V in SO(3) as well.
+//
+// Stresses are Kirchhoff tau = P F^T (App. A.2 fixed corotated and StVK /
+// Hencky forms, App. B.1 Corotated and SigmaElasticity).  Return maps follow
+// App. A.2 / B.2 (identity, von Mises, Drucker-Prager with the Klar et al.
+// 2016 plastic multiplier).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace fmpm {
+
+constexpr double kSigmaMin = 1e-4;  // log-strain floor for singular values
+
+struct Material {
+  int32_t elastic;
+  int32_t plastic;
+  float yield_stress;
+  float dp_alpha;  // sqrt(2/3) * 2 sin(phi) / (3 - sin(phi)), precomputed on the host
+};
+
+// -------------------------------------------------------------------------
+// 3x3 helpers (row-major double[9])
+// -------------------------------------------------------------------------
+__device__ __forceinline__ double det3(const double* A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// One Jacobi rotation in plane (P, Q) of the symmetric S, accumulated into V.
+template <int P, int Q>
+__device__ __forceinline__ void jacobi_rotate(double S[3][3], double V[3][3]) {
+  constexpr int R = 3 - P - Q;
+  const double apq = S[P][Q];
+  if (apq == 0.0) return;
+  const double theta = (S[Q][Q] - S[P][P]) / (2.0 * apq);
+  const double at = fabs(theta);
+  double t = (at > 1e150) ? 0.5 / at : 1.0 / (at + sqrt(at * at + 1.0));
+  t = (theta < 0.0) ? -t : t;
+  const double c = 1.0 / sqrt(t * t + 1.0);
+  const double s = t * c;
+  const double arp = S[R][P], arq = S[R][Q];
+  S[P][P] -= t * apq;
+  S[Q][Q] += t * apq;
+  S[P][Q] = 0.0;
+  S[Q][P] = 0.0;
+  const double nrp = c * arp - s * arq;
+  const double nrq = s * arp + c * arq;
+  S[R][P] = nrp;
+  S[P][R] = nrp;
+  S[R][Q] = nrq;
+  S[Q][R] = nrq;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double vp = V[r][P], vq = V[r][Q];
+    V[r][P] = c * vp - s * vq;
+    V[r][Q] = s * vp + c * vq;
+  }
+}
+
+template <int I, int J>
+__device__ __forceinline__ void swap_cols_keep_det(double V[3][3], double lam[3]) {
+  // exchange columns I and J and negate the new column J: det unchanged
+  const double t = lam[I];
+  lam[I] = lam[J];
+  lam[J] = t;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double a = V[r][I];
+    V[r][I] = V[r][J];
+    V[r][J] = -a;
+  }
+}
+
+// Givens rotation of rows (I, K) of B zeroing B[K][COL]; U <- U G^T.
+template <int I, int K, int COL>
+__device__ __forceinline__ void givens_qr(double B[3][3], double U[3][3]) {
+  const double a = B[I][COL], b = B[K][COL];
+  const double rho = sqrt(a * a + b * b);
+  if (rho == 0.0) return;
+  const double c = a / rho, s = b / rho;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double bi = B[I][j], bk = B[K][j];
+    B[I][j] = c * bi + s * bk;
+    B[K][j] = -s * bi + c * bk;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double ui = U[r][I], uk = U[r][K];
+    U[r][I] = c * ui + s * uk;
+    U[r][K] = -s * ui + c * uk;
+  }
+}
+
+// F = U diag(sig) V^T, U, V in SO(3), |sig0| >= |sig1| >= |sig2|, sig0, sig1 >= 0.
+__device__ __forceinline__ void svd3(const double* F, double U[3][3], double sig[3], double V[3][3]) {
+  double S[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const double v = F[0 + i] * F[0 + j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+      S[i][j] = v;
+      S[j][i] = v;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[1][2] * S[1][2];
+    const double dia = S[0][0] * S[0][0] + S[1][1] * S[1][1] + S[2][2] * S[2][2];
+    if (off <= 1e-34 * dia) break;
+    jacobi_rotate<0, 1>(S, V);
+    jacobi_rotate<0, 2>(S, V);
+    jacobi_rotate<1, 2>(S, V);
+  }
+  double lam[3] = {S[0][0], S[1][1], S[2][2]};
+  if (lam[0] < lam[1]) swap_cols_keep_det<0, 1>(V, lam);
+  if (lam[0] < lam[2]) swap_cols_keep_det<0, 2>(V, lam);
+  if (lam[1] < lam[2]) swap_cols_keep_det<1, 2>(V, lam);
+  double B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[i][j] = F[3 * i + 0] * V[0][j] + F[3 * i + 1] * V[1][j] + F[3 * i + 2] * V[2][j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) U[i][j] = (i == j) ? 1.0 : 0.0;
+  givens_qr<0, 1, 0>(B, U);
+  givens_qr<0, 2, 0>(B, U);
+  givens_qr<1, 2, 1>(B, U);
+  sig[0] = B[0][0];
+  sig[1] = B[1][1];
+  sig[2] = B[2][2];
+}
+
+// A diag(d) B^T
+__device__ __forceinline__ void diag_sandwich(const double A[3][3], const double* d, const double B[3][3],
+                                              double* out) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) out[3 * i + j] = A[i][0] * d[0] * B[j][0] + A[i][1] * d[1] * B[j][1] + A[i][2] * d[2] * B[j][2];
+}
+
+// -------------------------------------------------------------------------
+// Kirchhoff stresses (tau symmetric; full 3x3 returned)
+// -------------------------------------------------------------------------
+
+// Fixed corotated: tau = 2 mu (F - R) F^T + lam J (J - 1) I with R = U V^T.
+__device__ __forceinline__ void tau_fixed_corotated(const double* F, const double U[3][3], const double V[3][3],
+                                                    double mu, double lam, double* tau) {
+  double P[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[3 * i + j] = F[3 * i + j] - (U[i][0] * V[j][0] + U[i][1] * V[j][1] + U[i][2] * V[j][2]);
+  const double J = det3(F);
+  const double vol = lam * J * (J - 1.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double pf = P[3 * i + 0] * F[3 * j + 0] + P[3 * i + 1] * F[3 * j + 1] + P[3 * i + 2] * F[3 * j + 2];
+      tau[3 * i + j] = 2.0 * mu * pf + ((i == j) ? vol : 0.0);
+    }
+}
+
+// Hencky (logarithmic strain): tau = U diag(2 mu eps + lam tr(eps)) U^T.
+__device__ __forceinline__ void tau_hencky(const double U[3][3], const double* sig, double mu, double lam,
+                                           double* tau) {
+  double e[3], d[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) e[k] = log(fmax(sig[k], kSigmaMin));
+  const double tr = e[0] + e[1] + e[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d[k] = 2.0 * mu * e[k] + lam * tr;
+  diag_sandwich(U, d, U, tau);
+}
+
+// -------------------------------------------------------------------------
+// Return maps.  Input: F_trial (FP64) and its SVD.  Output: F' and the
+// singular values of F' (U, V unchanged), so the next stress can reuse them.
+// Returns true if F' differs from F_trial.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ bool return_map(const Material& mat, double mu, double lam, const double* Ftr,
+                                           const double U[3][3], const double* sig, const double V[3][3],
+                                           double* Fout, double* sig_out) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Fout[k] = Ftr[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) sig_out[k] = sig[k];
+  if (mat.plastic == 0) return false;
+  double e[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) e[k] = log(fmax(sig[k], kSigmaMin));
+  const double tr = e[0] + e[1] + e[2];
+  const double mean = tr / 3.0;
+  double eh[3] = {e[0] - mean, e[1] - mean, e[2] - mean};
+  const double nrm = sqrt(eh[0] * eh[0] + eh[1] * eh[1] + eh[2] * eh[2]);
+  double dgamma;
+  if (mat.plastic == 1) {  // von Mises
+    dgamma = nrm - (double)mat.yield_stress / (2.0 * mu);
+  } else {  // Drucker-Prager
+    if (tr > 0.0) {
+      const double one[3] = {1.0, 1.0, 1.0};
+      diag_sandwich(U, one, V, Fout);
+      sig_out[0] = sig_out[1] = sig_out[2] = 1.0;
+      return true;
+    }
+    dgamma = nrm + (3.0 * lam + 2.0 * mu) / (2.0 * mu) * tr * (double)mat.dp_alpha;
+  }
+  if (!(dgamma > 0.0)) return false;
+  const double scale = dgamma / nrm;
+  double s2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s2[k] = exp(e[k] - scale * eh[k]);
+  diag_sandwich(U, s2, V, Fout);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) sig_out[k] = s2[k];
+  return true;
+}
+
+// Kirchhoff stress of F whose SVD is (U, sig, V).
+__device__ __forceinline__ void kirchhoff(const Material& mat, double mu, double lam, const double* F,
+                                          const double U[3][3], const double* sig, const double V[3][3],
+                                          double* tau) {
+  if (mat.elastic == 0)
+    tau_fixed_corotated(F, U, V, mu, lam, tau);
+  else
+    tau_hencky(U, sig, mu, lam, tau);
+}
+
+}  // namespace fmpm
