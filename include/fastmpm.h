@@ -167,6 +167,17 @@ int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out);
  * sort_every = substeps between re-sorts, tile_cap = LDS tile nodes. */
 int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_cap);
 
+/* Kernel timing with HIP events recorded on the launch stream around each
+ * launch, by class: 0 fused G2P+P2G substep kernel, 1 P2G-only kernel,
+ * 2 G2P-only kernel, 3 sort and permute, 4 grid clear, 5 gather from /
+ * scatter to the caller's arrays.  enable = 0 stops recording. */
+#define MPM_PROFILE_CLASSES 8
+int mpm_profile(mpm_ctx ctx, int32_t enable);
+
+/* Synchronises, then returns the summed milliseconds and the number of
+ * timed launches per class (arrays of MPM_PROFILE_CLASSES) and resets them. */
+int mpm_profile_read(mpm_ctx ctx, double* ms, int64_t* launches);
+
 /* Release the context and its workspace (synchronises the device). */
 int mpm_destroy(mpm_ctx ctx);
 

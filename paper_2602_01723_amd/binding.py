@@ -23,7 +23,9 @@ MPM_ABI_VERSION = 1
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_tape_size",
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
-            "mpm_set_tuning", "mpm_destroy")
+            "mpm_set_tuning", "mpm_profile", "mpm_profile_read", "mpm_destroy")
+PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io", "unused",
+                   "other_fill")
 
 
 class MPMError(RuntimeError):
@@ -78,6 +80,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_export_covariance": (ctypes.c_int, [vp, vp, vp, vp, i64, vp]),
         "mpm_get_diagnostics": (ctypes.c_int, [vp, ctypes.POINTER(mpm_diag)]),
         "mpm_set_tuning": (ctypes.c_int, [vp, i32, i32, i32]),
+        "mpm_profile": (ctypes.c_int, [vp, i32]),
+        "mpm_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
         "mpm_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -158,7 +162,7 @@ class Particles:
         N = len(mass)
 
         def f32(a, shape):
-            t = torch.as_tensor(np.ascontiguousarray(np.asarray(a, np.float32).reshape(N, -1).T)
+            t = torch.as_tensor(np.ascontiguousarray(np.asarray(a, np.float32).reshape(N, shape).T)
                                 if shape else np.asarray(a, np.float32))
             return t.contiguous().to(device)
         return cls(x=f32(x, 3), v=f32(v, 3), C=f32(C, 9), F=f32(F, 9), mass=f32(mass, 0), vol0=f32(vol0, 0),
@@ -264,6 +268,18 @@ def mpm_get_diagnostics(ctx: Context) -> dict:
 
 def mpm_set_tuning(ctx: Context, chunk=0, sort_every=0, tile_cap=0):
     _check(ctx, load().mpm_set_tuning(ctx.handle, int(chunk), int(sort_every), int(tile_cap)), "mpm_set_tuning")
+
+
+def mpm_profile(ctx: Context, enable: bool = True):
+    _check(ctx, load().mpm_profile(ctx.handle, int(bool(enable))), "mpm_profile")
+
+
+def mpm_profile_read(ctx: Context) -> dict:
+    """{class: (total_ms, launches)} of the launches timed since the last read."""
+    ms = (ctypes.c_double * 8)()
+    cnt = (ctypes.c_int64 * 8)()
+    _check(ctx, load().mpm_profile_read(ctx.handle, ms, cnt), "mpm_profile_read")
+    return {name: (ms[k], cnt[k]) for k, name in enumerate(PROFILE_CLASSES)}
 
 
 def mpm_destroy(ctx: Context):

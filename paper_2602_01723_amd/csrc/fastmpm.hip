@@ -44,6 +44,13 @@ struct mpm_context {
   unsigned long long* diag = nullptr;
   std::vector<void*> allocations;
 
+  // kernel timing (mpm_profile): event pairs recorded around launches
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_cls;
+  double prof_ms[MPM_PROFILE_CLASSES] = {0};
+  int64_t prof_cnt[MPM_PROFILE_CLASSES] = {0};
+
   int last_grid = -1;
   int64_t substeps = 0;
   hipStream_t last_stream = nullptr;
@@ -91,9 +98,30 @@ int alloc(mpm_ctx ctx, T** p, int64_t count) {
   return MPM_OK;
 }
 
+constexpr int kProfPairs = 4096;
+
+// Records a HIP event pair around the launches issued in its scope.
+struct ProfScope {
+  mpm_ctx c;
+  hipStream_t s;
+  int cls;
+  int idx = -1;
+  ProfScope(mpm_ctx c_, hipStream_t s_, int cls_) : c(c_), s(s_), cls(cls_) {
+    if (cls >= 0 && c->prof_on && (int)c->prof_cls.size() < kProfPairs) {
+      idx = (int)c->prof_cls.size();
+      c->prof_cls.push_back(-1);  // slot reserved; class set when the pair is complete
+      if (hipEventRecord(c->prof_ev[2 * idx], s) != hipSuccess) idx = -1;
+    }
+  }
+  ~ProfScope() {
+    if (idx >= 0 && hipEventRecord(c->prof_ev[2 * idx + 1], s) == hipSuccess) c->prof_cls[idx] = cls;
+  }
+};
+
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads); }
 
-int fill_u32(mpm_ctx ctx, void* p, int64_t count, hipStream_t s) {
+int fill_u32(mpm_ctx ctx, void* p, int64_t count, hipStream_t s, int cls = -1) {
+  ProfScope ps(ctx, s, cls);
   const int64_t n4 = std::max<int64_t>(count >> 2, 4);
   fmpm::k_fill_u32<<<blocks_for(n4, 256), 256, 0, s>>>((uint32_t*)p, 0u, count);
   LAUNCH_CHECK(ctx, "k_fill_u32");
@@ -141,6 +169,7 @@ int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
 }
 
 int gather_from_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
+  ProfScope ps(c, s, 5);
   int rc = sort_keys(c, p->x, s);
   if (rc) return rc;
   const unsigned g = blocks_for(c->N, 256);
@@ -155,6 +184,7 @@ int gather_from_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
 }
 
 int resort_internal(mpm_ctx c, hipStream_t s) {
+  ProfScope ps(c, s, 3);
   int rc = sort_keys(c, c->xs, s);
   if (rc) return rc;
   const unsigned g = blocks_for(c->N, 256);
@@ -171,6 +201,7 @@ int resort_internal(mpm_ctx c, hipStream_t s) {
 }
 
 int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
+  ProfScope ps(c, s, 5);
   const unsigned g = blocks_for(c->N, 256);
   fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->x, c->xs, c->pid, 3, c->N);
   fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->v, c->vs, c->pid, 3, c->N);
@@ -186,6 +217,7 @@ int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hip
   a.grid_in = gin;
   a.grid_out = gout;
   a.write_vc = write_vc;
+  ProfScope ps(c, s, MODE == fmpm::kFused ? 0 : (MODE == fmpm::kP2G ? 1 : 2));
   fmpm::k_substep<MODE><<<c->n_chunks, kBlock, 0, s>>>(a);
   LAUNCH_CHECK(c, "k_substep");
   return MPM_OK;
@@ -335,7 +367,7 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape,
   }
   rc = gather_from_caller(ctx, p, s);
   if (rc) return rc;
-  rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s);
+  rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, 4);
   if (rc) return rc;
   rc = launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s);
   if (rc) return rc;
@@ -345,7 +377,7 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape,
       rc = launch_substep<fmpm::kG2P>(ctx, ctx->grid[cur], nullptr, 1, s);
       if (rc) return rc;
     } else {
-      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s);
+      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, 4);
       if (rc) return rc;
       rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], 0, s);
       if (rc) return rc;
@@ -422,9 +454,40 @@ int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_
   return MPM_OK;
 }
 
+int mpm_profile(mpm_ctx ctx, int32_t enable) {
+  if (!ctx) return MPM_EINVAL;
+  if (enable && ctx->prof_ev.empty()) {
+    ctx->prof_ev.resize(2 * kProfPairs);
+    for (auto& e : ctx->prof_ev) HIP_TRY(ctx, hipEventCreate(&e));
+  }
+  ctx->prof_on = enable != 0;
+  return MPM_OK;
+}
+
+int mpm_profile_read(mpm_ctx ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return MPM_EINVAL;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  for (size_t i = 0; i < ctx->prof_cls.size(); ++i) {
+    if (ctx->prof_cls[i] < 0) continue;
+    float t = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&t, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+    ctx->prof_ms[ctx->prof_cls[i]] += t;
+    ctx->prof_cnt[ctx->prof_cls[i]] += 1;
+  }
+  ctx->prof_cls.clear();
+  for (int k = 0; k < MPM_PROFILE_CLASSES; ++k) {
+    ms[k] = ctx->prof_ms[k];
+    launches[k] = ctx->prof_cnt[k];
+    ctx->prof_ms[k] = 0.0;
+    ctx->prof_cnt[k] = 0;
+  }
+  return MPM_OK;
+}
+
 int mpm_destroy(mpm_ctx ctx) {
   if (!ctx) return MPM_EINVAL;
   (void)hipDeviceSynchronize();
+  for (auto& e : ctx->prof_ev) (void)hipEventDestroy(e);
   for (void* q : ctx->allocations) (void)hipFree(q);
   delete ctx;
   return MPM_OK;
