@@ -39,7 +39,12 @@ struct mpm_context {
   float4 *prm = nullptr, *prm2 = nullptr;
   int *mat = nullptr, *mat2 = nullptr, *pid = nullptr, *pid2 = nullptr, *perm = nullptr;
   float4* grid[2] = {nullptr, nullptr};
-  int *chunk_start = nullptr, *chunk_batch = nullptr;
+  int *chunk_start = nullptr, *chunk_batch = nullptr;            // by scene, fixed (cell keys)
+  int *dchunk_start = nullptr, *dchunk_batch = nullptr, *dn_chunks = nullptr;  // by cell block, per sort
+  uint32_t* nchk = nullptr;
+  int64_t nblocks = 0;
+  int64_t max_chunks = 0;
+  int grid_blocks = 0;
   uint32_t *keys = nullptr, *slots = nullptr, *count = nullptr, *bsum = nullptr;
   unsigned long long* diag = nullptr;
   std::vector<void*> allocations;
@@ -137,8 +142,9 @@ fmpm::SubstepArgs make_args(mpm_ctx c) {
   a.prm = c->prm;
   a.mat = c->mat;
   a.N = c->N;
-  a.chunk_start = c->chunk_start;
-  a.chunk_batch = c->chunk_batch;
+  a.chunk_start = c->dchunk_start;
+  a.chunk_batch = c->dchunk_batch;
+  a.n_chunks = c->dn_chunks;
   a.n = c->n;
   a.bound = c->cfg.bound;
   a.dt = c->cfg.dt;
@@ -165,6 +171,16 @@ int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
   LAUNCH_CHECK(c, "k_scan_apply");
   fmpm::k_place<<<blocks_for(c->N, 256), 256, 0, s>>>(c->keys, c->slots, c->count, c->perm, c->N);
   LAUNCH_CHECK(c, "k_place");
+  // chunk table of the new order
+  const unsigned gb = blocks_for(c->nblocks, 256);
+  fmpm::k_block_chunk_count<<<gb, 256, 0, s>>>(c->count, c->nblocks, c->N, c->nchk);
+  const int64_t nbs = (c->nblocks + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  fmpm::k_scan_reduce<<<(unsigned)nbs, fmpm::kScanThreads, 0, s>>>(c->nchk, c->bsum, c->nblocks);
+  fmpm::k_scan_top<<<1, fmpm::kScanThreads, 0, s>>>(c->bsum, nbs);
+  fmpm::k_scan_apply<<<(unsigned)nbs, fmpm::kScanThreads, 0, s>>>(c->nchk, c->bsum, c->nblocks);
+  fmpm::k_block_chunk_write<<<gb, 256, 0, s>>>(c->count, c->nchk, c->nblocks, c->N, c->nb * c->nb * c->nb,
+                                               c->dchunk_start, c->dchunk_batch, c->dn_chunks);
+  LAUNCH_CHECK(c, "chunk table");
   return MPM_OK;
 }
 
@@ -218,7 +234,7 @@ int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hip
   a.grid_out = gout;
   a.write_vc = write_vc;
   ProfScope ps(c, s, MODE == fmpm::kFused ? 0 : (MODE == fmpm::kP2G ? 1 : 2));
-  fmpm::k_substep<MODE><<<c->n_chunks, kBlock, 0, s>>>(a);
+  fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);
   LAUNCH_CHECK(c, "k_substep");
   return MPM_OK;
 }
@@ -308,6 +324,9 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     }
   cs.push_back((int)n_particles);
   c->n_chunks = (int)cb.size();
+  c->nblocks = (int64_t)c->B * nb * nb * nb;
+  c->max_chunks = (n_particles + kBlock - 1) / kBlock + std::min<int64_t>(n_particles, c->nblocks) + 1;
+  c->grid_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(c->max_chunks, 256 * 8));
 
   const int64_t N = std::max<int64_t>(n_particles, 1);
   int rc = MPM_OK;
@@ -333,6 +352,10 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   rc = rc ? rc : alloc(c, &c->chunk_start, (int64_t)cs.size());
   rc = rc ? rc : alloc(c, &c->chunk_batch, (int64_t)std::max<size_t>(cb.size(), 1));
   rc = rc ? rc : alloc(c, &c->diag, 8);
+  rc = rc ? rc : alloc(c, &c->dchunk_start, c->max_chunks + 1);
+  rc = rc ? rc : alloc(c, &c->dchunk_batch, c->max_chunks + 1);
+  rc = rc ? rc : alloc(c, &c->dn_chunks, 1);
+  rc = rc ? rc : alloc(c, &c->nchk, c->nblocks);
   if (rc) {
     mpm_destroy(c);
     return rc;
@@ -341,6 +364,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   if (e == hipSuccess && !cb.empty())
     e = hipMemcpy(c->chunk_batch, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->diag, 0, 8 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->dn_chunks, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemset(c->grid[0], 0, (size_t)c->nodes * sizeof(float4));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {

@@ -27,7 +27,7 @@
 namespace fmpm {
 
 constexpr int kBlock = 256;         // threads per workgroup = particles per chunk
-constexpr int kTileCapMax = 2048;   // LDS tile nodes (4 float planes = 32 KiB)
+constexpr int kTileCapMax = 1024;   // LDS tile nodes (4 double planes = 32 KiB)
 constexpr int kMaxMaterials = 16;
 
 enum { kP2G = 0, kFused = 1, kG2P = 2 };
@@ -40,8 +40,9 @@ struct SubstepArgs {
   const float4* prm;
   const int* mat;
   int64_t N;  // plane stride
-  const int* chunk_start;
-  const int* chunk_batch;
+  const int* chunk_start;  // [n_chunks + 1]
+  const int* chunk_batch;  // [n_chunks]
+  const int* n_chunks;     // device scalar
   const float4* grid_in;
   float4* grid_out;
   int n;
@@ -64,35 +65,43 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
-// Box of base cells over the workgroup's valid particles.  out[0..2] = min,
-// out[3..5] = max.  Empty -> min > max.  red: LDS scratch of 6 * waves ints.
-__device__ __forceinline__ void block_box(bool valid, const int* b, int* red, int* out) {
+// Box of base cells over the workgroup's valid particles, plus the maxima
+// of NF non-negative floats.  out[0..2] = min, out[3..5] = max (empty ->
+// min > max); fmax_io[k] in: this lane's value, out: the workgroup maximum.
+// red: LDS scratch of (6 + NF) * waves ints.
+template <int NF = 0>
+__device__ __forceinline__ void block_box(bool valid, const int* b, int* red, int* out, float* fmax_io = nullptr) {
+  constexpr int NV = 6 + NF;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int v[6];
+  int v[NV];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     v[k] = valid ? b[k] : 0x3fffffff;
     v[k + 3] = valid ? -b[k] : 0x3fffffff;
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) v[k] = wave_min(v[k]);
+  for (int k = 0; k < NF; ++k) v[6 + k] = -__float_as_int(fmax_io[k]);  // order of non-negative floats
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_min(v[k]);
   __syncthreads();  // red may still be read by an earlier call
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) red[wave * 6 + k] = v[k];
+    for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
   }
   __syncthreads();
-  int r[6];
+  int r[NV];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) r[k] = red[k];
+  for (int k = 0; k < NV; ++k) r[k] = red[k];
   for (int w = 1; w < kBlock / 64; ++w)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r[k] = min(r[k], red[w * 6 + k]);
+    for (int k = 0; k < NV; ++k) r[k] = min(r[k], red[w * NV + k]);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     out[k] = r[k];
     out[k + 3] = -r[k + 3];
   }
+#pragma unroll
+  for (int k = 0; k < NF; ++k) fmax_io[k] = __int_as_float(-r[6 + k]);
 }
 
 // Base cell and fraction of one coordinate.  base = floor(x n - 0.5) is
@@ -148,11 +157,13 @@ __device__ __forceinline__ void count_event(unsigned long long* diag, int slot, 
 // --------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
-  __shared__ float tile[4 * kTileCapMax];
-  __shared__ int red[6 * (kBlock / 64)];
+  __shared__ double tile_d[4 * kTileCapMax];  // P2G: 4 double planes; G2P: 3 float planes
+  float* tile = reinterpret_cast<float*>(tile_d);
+  __shared__ int red[8 * (kBlock / 64)];
   __shared__ int box_s[6];
 
-  const int chunk = blockIdx.x;
+  const int n_chunks = *a.n_chunks;
+  for (int chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
   const int start = a.chunk_start[chunk], end = a.chunk_start[chunk + 1];
   const int i = start + (int)threadIdx.x;
   const bool live = i < end;
@@ -312,8 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
         for (int k = 0; k < 9; ++k) a.C[k * N + i] = Cp[k];
       }
     }
-    if (MODE == kG2P) return;
     __syncthreads();  // everyone is done reading the G2P tile
+    if (MODE == kG2P) continue;
   }
 
   // ---------------------------------------------------------------- P2G
@@ -339,11 +350,11 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
     bool in_grid = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
-    const bool valid = ok && in_grid;
     if (MODE == kP2G) count_event(a.diag, 1, live && !in_grid);
     // contribution to node o: w (m v + A (o - f) dx) = w (q + Ad o)
 #pragma unroll
     for (int r = 0; r < 3; ++r) q[r] = mass * vp[r] - (Ad[3 * r] * f1[0] + Ad[3 * r + 1] * f1[1] + Ad[3 * r + 2] * f1[2]);
+    const bool valid = ok && in_grid;
     int box[6];
     block_box(valid, b1, red, box);
     const int ex = box[3] - box[0] + 3, ey = box[4] - box[1] + 3, ez = box[5] - box[2] + 3;
@@ -351,12 +362,14 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
     const int T = empty ? 0 : ex * ey * ez;
     const bool use_lds = !empty && T <= cap;
     if (!empty && !use_lds && threadIdx.x == 0) atomicAdd(&a.diag[2], 1ull);
+    // The LDS tile accumulates in double: native LDS f64 atomic adds run far
+    // faster than f32 ones on this chip, and the sum is more accurate.
     if (use_lds) {
       for (int t = threadIdx.x; t < T; t += kBlock) {
-        tile[t] = 0.f;
-        tile[cap + t] = 0.f;
-        tile[2 * cap + t] = 0.f;
-        tile[3 * cap + t] = 0.f;
+        tile_d[t] = 0.0;
+        tile_d[cap + t] = 0.0;
+        tile_d[2 * cap + t] = 0.0;
+        tile_d[3 * cap + t] = 0.0;
       }
     }
     __syncthreads();
@@ -404,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
             if (use_lds) {
               const int t = row + r[2][kz];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) atomicAdd(&tile[c * cap + t], val[c]);
+              for (int c = 0; c < 4; ++c) atomicAdd(&tile_d[c * cap + t], (double)val[c]);
             } else {
               const int ix = b1[0] + r[0][kx], iy = b1[1] + r[1][ky], iz = b1[2] + r[2][kz];
               float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
@@ -418,18 +431,20 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
     __syncthreads();
     if (use_lds) {
       for (int t = threadIdx.x; t < T; t += kBlock) {
-        const float m = tile[3 * cap + t];
-        if (m == 0.0f) continue;
+        const double m = tile_d[3 * cap + t];
+        if (m == 0.0) continue;
         const int tk = t % ez, tq = t / ez;
         const int tj = tq % ey, ti = tq / ey;
         float* gp = (float*)&a.grid_out[gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk)];
-        atomicAdd(gp + 0, tile[t]);
-        atomicAdd(gp + 1, tile[cap + t]);
-        atomicAdd(gp + 2, tile[2 * cap + t]);
-        atomicAdd(gp + 3, m);
+        atomicAdd(gp + 0, (float)tile_d[t]);
+        atomicAdd(gp + 1, (float)tile_d[cap + t]);
+        atomicAdd(gp + 2, (float)tile_d[2 * cap + t]);
+        atomicAdd(gp + 3, (float)m);
       }
     }
+    __syncthreads();  // the tile is reused by the next chunk
   }
+  }  // chunk loop
 }
 
 
@@ -556,6 +571,37 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* data, con
 __global__ void k_place(const uint32_t* key, const uint32_t* slot, const uint32_t* off, int* perm, int64_t N) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) perm[off[key[i]] + slot[i]] = (int)i;
+}
+
+// Chunk table after a sort: each 4^3-cell block's particles (a contiguous
+// range of the sorted order) are cut into chunks of at most kBlock.
+// off = exclusive bin offsets (64 bins per block), nchk[b] = chunks of block b.
+__global__ void k_block_chunk_count(const uint32_t* off, int64_t nblocks, int64_t N, uint32_t* nchk) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  const uint32_t lo = off[b * 64];
+  const uint32_t hi = (b + 1 < nblocks) ? off[(b + 1) * 64] : (uint32_t)N;
+  nchk[b] = (hi - lo + kBlock - 1) / kBlock;
+}
+
+// base = exclusive scan of nchk (same array, scanned in place beforehand)
+__global__ void k_block_chunk_write(const uint32_t* off, const uint32_t* base, int64_t nblocks, int64_t N,
+                                    int blocks_per_scene, int* chunk_start, int* chunk_batch, int* n_chunks) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  const uint32_t lo = off[b * 64];
+  const uint32_t hi = (b + 1 < nblocks) ? off[(b + 1) * 64] : (uint32_t)N;
+  const uint32_t c0 = base[b];
+  const int scene = (int)(b / blocks_per_scene);
+  uint32_t c = c0;
+  for (uint32_t s = lo; s < hi; s += kBlock, ++c) {
+    chunk_start[c] = (int)s;
+    chunk_batch[c] = scene;
+  }
+  if (b == nblocks - 1) {
+    chunk_start[c] = (int)N;
+    *n_chunks = (int)c;
+  }
 }
 
 // out[c][j] = in[c][perm[j]] for `planes` planes of stride N
