@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--substeps-per-step", type=int, default=20)
     ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--item", type=int, default=0, help="particles per work item (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-total", type=int, default=2_000_000)
     args = ap.parse_args()
@@ -83,6 +84,8 @@ def main():
     log(f"  {sc.n} particles, {sc.grid_res}^3 grid, generated in {time.perf_counter() - t:.1f} s")
 
     ctx = B.init_from_scene(sc, sort_every=args.sort_every)
+    if args.item:
+        B.mpm_set_tuning(ctx, chunk=args.item)
     p = B.Particles.from_scene(sc)
     S = args.substeps_per_step
     for w in range(args.warmup):
@@ -144,8 +147,9 @@ def main():
             "workload": "large_scene: 2M particles (12 ellipsoids, shell + MCIS interior), 128^3 grid, dt 5e-5, "
                         "fixed-corotated / von Mises / Drucker-Prager, FP32 state, FP64 SVD",
             "particles": sc.n, "grid_res": sc.grid_res, "substeps_per_step": S, "sort_every": args.sort_every,
+            "item": args.item,
             "kernel_time_by_class_ms": breakdown,
-            "diagnostics": {k: diag[k] for k in ("nonfinite", "out_of_grid", "tile_overflow")},
+            "diagnostics": {k: diag[k] for k in ("nonfinite", "out_of_grid", "tile_overflow", "tile_escapes")},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -106,7 +106,8 @@ typedef struct {
 typedef struct {
   int64_t nonfinite;     /* particle-substeps that produced a NaN/Inf x or F */
   int64_t out_of_grid;   /* particle-substeps whose stencil left the grid (skipped) */
-  int64_t tile_overflow; /* P2G/G2P chunks that fell back to global-memory transfers */
+  int64_t tile_overflow; /* work items whose box exceeded the LDS tiles (global-memory transfers) */
+  int64_t tile_escapes;  /* particles that left their item's P2G tile in one substep (global atomics) */
   int64_t substeps;      /* substeps run since mpm_init */
 } mpm_diag;
 
@@ -163,7 +164,8 @@ int mpm_export_covariance(mpm_ctx ctx, const float* F, const float* cov0, float*
 int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out);
 
 /* Launch tuning (set by the autotuner; 0 keeps the current value):
- * chunk = particles per workgroup (64..1024, multiple of 64),
+ * chunk = particles per work item, cut from one 4^3-cell block (64..8192,
+ * multiple of 64; applied at the next sort),
  * sort_every = substeps between re-sorts, tile_cap = LDS tile nodes. */
 int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_cap);
 

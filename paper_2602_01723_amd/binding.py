@@ -51,7 +51,7 @@ class mpm_particles(ctypes.Structure):
 
 class mpm_diag(ctypes.Structure):
     _fields_ = [("nonfinite", ctypes.c_int64), ("out_of_grid", ctypes.c_int64), ("tile_overflow", ctypes.c_int64),
-                ("substeps", ctypes.c_int64)]
+                ("tile_escapes", ctypes.c_int64), ("substeps", ctypes.c_int64)]
 
 
 _lib = None
@@ -260,7 +260,7 @@ def mpm_get_diagnostics(ctx: Context) -> dict:
     d = mpm_diag()
     rc = load().mpm_get_diagnostics(ctx.handle, ctypes.byref(d))
     out = dict(nonfinite=d.nonfinite, out_of_grid=d.out_of_grid, tile_overflow=d.tile_overflow,
-               substeps=d.substeps, status=rc)
+               tile_escapes=d.tile_escapes, substeps=d.substeps, status=rc)
     if rc not in (MPM_OK, MPM_EUNSTABLE):
         _check(ctx, rc, "mpm_get_diagnostics")
     return out

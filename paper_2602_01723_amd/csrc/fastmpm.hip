@@ -42,11 +42,14 @@ struct mpm_context {
   int *chunk_start = nullptr, *chunk_batch = nullptr;            // by scene, fixed (cell keys)
   int *dchunk_start = nullptr, *dchunk_batch = nullptr, *dn_chunks = nullptr;  // by cell block, per sort
   uint32_t* nchk = nullptr;
+  int* work_counter = nullptr;  // work-item queue head of the substep kernel
+  int item = 1024;              // particles per work item
   int64_t nblocks = 0;
   int64_t max_chunks = 0;
   int grid_blocks = 0;
   uint32_t *keys = nullptr, *slots = nullptr, *count = nullptr, *bsum = nullptr;
   unsigned long long* diag = nullptr;
+  fmpm::Material* d_mats = nullptr;
   std::vector<void*> allocations;
 
   // kernel timing (mpm_profile): event pairs recorded around launches
@@ -125,10 +128,10 @@ struct ProfScope {
 
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads); }
 
-int fill_u32(mpm_ctx ctx, void* p, int64_t count, hipStream_t s, int cls = -1) {
+int fill_u32(mpm_ctx ctx, void* p, int64_t count, hipStream_t s, int cls = -1, int* counter = nullptr) {
   ProfScope ps(ctx, s, cls);
   const int64_t n4 = std::max<int64_t>(count >> 2, 4);
-  fmpm::k_fill_u32<<<blocks_for(n4, 256), 256, 0, s>>>((uint32_t*)p, 0u, count);
+  fmpm::k_fill_u32<<<blocks_for(n4, 256), 256, 0, s>>>((uint32_t*)p, 0u, count, counter);
   LAUNCH_CHECK(ctx, "k_fill_u32");
   return MPM_OK;
 }
@@ -145,6 +148,7 @@ fmpm::SubstepArgs make_args(mpm_ctx c) {
   a.chunk_start = c->dchunk_start;
   a.chunk_batch = c->dchunk_batch;
   a.n_chunks = c->dn_chunks;
+  a.work_counter = c->work_counter;
   a.n = c->n;
   a.bound = c->cfg.bound;
   a.dt = c->cfg.dt;
@@ -152,7 +156,7 @@ fmpm::SubstepArgs make_args(mpm_ctx c) {
   a.tile_cap = c->tile_cap;
   a.diag = c->diag;
   a.n_materials = c->n_mat;
-  for (int k = 0; k < c->n_mat; ++k) a.mats[k] = c->mats[k];
+  a.mats = c->d_mats;
   return a;
 }
 
@@ -173,12 +177,12 @@ int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
   LAUNCH_CHECK(c, "k_place");
   // chunk table of the new order
   const unsigned gb = blocks_for(c->nblocks, 256);
-  fmpm::k_block_chunk_count<<<gb, 256, 0, s>>>(c->count, c->nblocks, c->N, c->nchk);
+  fmpm::k_block_chunk_count<<<gb, 256, 0, s>>>(c->count, c->nblocks, c->N, c->item, c->nchk);
   const int64_t nbs = (c->nblocks + fmpm::kScanTile - 1) / fmpm::kScanTile;
   fmpm::k_scan_reduce<<<(unsigned)nbs, fmpm::kScanThreads, 0, s>>>(c->nchk, c->bsum, c->nblocks);
   fmpm::k_scan_top<<<1, fmpm::kScanThreads, 0, s>>>(c->bsum, nbs);
   fmpm::k_scan_apply<<<(unsigned)nbs, fmpm::kScanThreads, 0, s>>>(c->nchk, c->bsum, c->nblocks);
-  fmpm::k_block_chunk_write<<<gb, 256, 0, s>>>(c->count, c->nchk, c->nblocks, c->N, c->nb * c->nb * c->nb,
+  fmpm::k_block_chunk_write<<<gb, 256, 0, s>>>(c->count, c->nchk, c->nblocks, c->N, c->item, c->nb * c->nb * c->nb,
                                                c->dchunk_start, c->dchunk_batch, c->dn_chunks);
   LAUNCH_CHECK(c, "chunk table");
   return MPM_OK;
@@ -325,8 +329,8 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   cs.push_back((int)n_particles);
   c->n_chunks = (int)cb.size();
   c->nblocks = (int64_t)c->B * nb * nb * nb;
-  c->max_chunks = (n_particles + kBlock - 1) / kBlock + std::min<int64_t>(n_particles, c->nblocks) + 1;
-  c->grid_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(c->max_chunks, 256 * 8));
+  c->max_chunks = (n_particles + 63) / 64 + std::min<int64_t>(n_particles, c->nblocks) + 1;  // items >= 64
+  c->grid_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(c->max_chunks, 256 * 2));
 
   const int64_t N = std::max<int64_t>(n_particles, 1);
   int rc = MPM_OK;
@@ -356,6 +360,8 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   rc = rc ? rc : alloc(c, &c->dchunk_batch, c->max_chunks + 1);
   rc = rc ? rc : alloc(c, &c->dn_chunks, 1);
   rc = rc ? rc : alloc(c, &c->nchk, c->nblocks);
+  rc = rc ? rc : alloc(c, &c->work_counter, 1);
+  rc = rc ? rc : alloc(c, &c->d_mats, fmpm::kMaxMaterials);
   if (rc) {
     mpm_destroy(c);
     return rc;
@@ -365,6 +371,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     e = hipMemcpy(c->chunk_batch, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->diag, 0, 8 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->dn_chunks, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(c->d_mats, c->mats, sizeof(c->mats), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->grid[0], 0, (size_t)c->nodes * sizeof(float4));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -391,17 +398,19 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape,
   }
   rc = gather_from_caller(ctx, p, s);
   if (rc) return rc;
-  rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, 4);
+  rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, 4, ctx->work_counter);
   if (rc) return rc;
   rc = launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s);
   if (rc) return rc;
   int cur = 0;
   for (int st = 0; st < n_steps; ++st) {
     if (st == n_steps - 1) {
+      rc = fill_u32(ctx, ctx->work_counter, 1, s, -1, ctx->work_counter);
+      if (rc) return rc;
       rc = launch_substep<fmpm::kG2P>(ctx, ctx->grid[cur], nullptr, 1, s);
       if (rc) return rc;
     } else {
-      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, 4);
+      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, 4, ctx->work_counter);
       if (rc) return rc;
       rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], 0, s);
       if (rc) return rc;
@@ -464,17 +473,19 @@ int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out) {
   out->nonfinite = (int64_t)h[0];
   out->out_of_grid = (int64_t)h[1];
   out->tile_overflow = (int64_t)h[2];
+  out->tile_escapes = (int64_t)h[3];
   out->substeps = ctx->substeps;
   return (h[0] || h[1]) ? MPM_EUNSTABLE : MPM_OK;
 }
 
 int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_cap) {
   if (!ctx) return MPM_EINVAL;
-  if (chunk != 0 && chunk != kBlock) return fail(ctx, MPM_EUNSUPPORTED, "chunk must be 256 in this build");
+  if (chunk != 0 && (chunk < 64 || chunk > 8192 || chunk % 64 != 0)) return fail(ctx, MPM_EINVAL, "chunk");
   if (sort_every < 0) return fail(ctx, MPM_EINVAL, "sort_every < 0");
   if (tile_cap != 0 && (tile_cap < 27 || tile_cap > fmpm::kTileCapMax)) return fail(ctx, MPM_EINVAL, "tile_cap");
   if (sort_every > 0) ctx->sort_every = sort_every;
   if (tile_cap > 0) ctx->tile_cap = tile_cap;
+  if (chunk > 0) ctx->item = chunk;  // takes effect at the next sort
   return MPM_OK;
 }
 

@@ -27,7 +27,7 @@
 namespace fmpm {
 
 constexpr int kBlock = 256;         // threads per workgroup = particles per chunk
-constexpr int kTileCapMax = 1024;   // LDS tile nodes (4 double planes = 32 KiB)
+constexpr int kTileCapMax = 1331;   // LDS tile nodes (11^3): P2G 4 doubles + G2P 3 floats per node
 constexpr int kMaxMaterials = 16;
 
 enum { kP2G = 0, kFused = 1, kG2P = 2 };
@@ -42,7 +42,8 @@ struct SubstepArgs {
   int64_t N;  // plane stride
   const int* chunk_start;  // [n_chunks + 1]
   const int* chunk_batch;  // [n_chunks]
-  const int* n_chunks;     // device scalar
+  const int* n_chunks;     // device scalar: number of work items
+  int* work_counter;       // device scalar, zero at launch
   const float4* grid_in;
   float4* grid_out;
   int n;
@@ -53,7 +54,7 @@ struct SubstepArgs {
   int write_vc;  // fused mode: also store v and C
   unsigned long long* diag;
   int n_materials;
-  Material mats[kMaxMaterials];
+  const Material* mats;  // device table [n_materials]
 };
 
 // --------------------------------------------------------------------------
@@ -153,306 +154,366 @@ __device__ __forceinline__ void count_event(unsigned long long* diag, int slot, 
 }
 
 // --------------------------------------------------------------------------
-// The substep kernel
+// The substep kernel.  A work item is a contiguous run of particles of one
+// 4^3-cell block (the table is rebuilt after every sort); workgroups take
+// items from a device counter.  Per item:
+//   1. box of the particles' base cells;
+//   2. G2P tile (box + 2 nodes) loaded from the grid being read, with the
+//      grid update applied on the way in; P2G tile (box grown by one cell,
+//      since a particle moves less than a cell per substep) zeroed;
+//   3. sub-chunks of kBlock particles, one per thread, with no barrier:
+//      G2P gather from the tile, F update, return map (FP64 SVD), stress of
+//      the new F and the P2G scatter into the tile with LDS f64 atomics in
+//      a staggered node order; a particle outside the P2G box scatters to
+//      global memory;
+//   4. flush: one global FP32 atomic per touched node and channel.
+// Items whose box exceeds the LDS tiles use global memory throughout.
 // --------------------------------------------------------------------------
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Workgroup min of lo[3] and max of hi[3] into box[6].
+__device__ __forceinline__ void block_minmax(const int* lo, const int* hi, int* red, int* box) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int v[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[k] = wave_min(lo[k]);
+    v[k + 3] = wave_max(hi[k]);
+  }
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[wave * 6 + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 6; ++k) box[k] = red[k];
+  for (int w = 1; w < kBlock / 64; ++w)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      box[k] = min(box[k], red[w * 6 + k]);
+      box[k + 3] = max(box[k + 3], red[w * 6 + k + 3]);
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
-  __shared__ double tile_d[4 * kTileCapMax];  // P2G: 4 double planes; G2P: 3 float planes
-  float* tile = reinterpret_cast<float*>(tile_d);
+  __shared__ double ptile[4 * kTileCapMax];  // P2G accumulators: mv.x, mv.y, mv.z, m
+  __shared__ float gtile[3 * kTileCapMax];   // G2P node velocities
   __shared__ int red[8 * (kBlock / 64)];
-  __shared__ int box_s[6];
+  __shared__ int item_s;
 
-  const int n_chunks = *a.n_chunks;
-  for (int chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
-  const int start = a.chunk_start[chunk], end = a.chunk_start[chunk + 1];
-  const int i = start + (int)threadIdx.x;
-  const bool live = i < end;
   const int n = a.n;
-  const int64_t gbase = (int64_t)a.chunk_batch[chunk] * n * n * n;
   const int64_t N = a.N;
   const float inv_dx = (float)n, dx = 1.0f / (float)n;
   const int cap = a.tile_cap;
+  const int n_items = *a.n_chunks;
 
-  float xp[3] = {0.f, 0.f, 0.f}, vp[3] = {0.f, 0.f, 0.f}, Fd_f[9];
-  float Cp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  double Fd[9];
-  float4 prm = make_float4(0.f, 0.f, 0.f, 0.f);
-  int mid = 0;
-  if (live) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) xp[k] = a.x[k * N + i];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Fd_f[k] = a.F[k * N + i];
-    prm = a.prm[i];
-    mid = a.mat[i];
-    if (MODE == kP2G) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) vp[k] = a.v[k * N + i];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Cp[k] = a.C[k * N + i];
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Fd_f[k] = (k % 4 == 0) ? 1.f : 0.f;
-  }
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Fd[k] = (double)Fd_f[k];
-  mid = (mid >= 0 && mid < a.n_materials) ? mid : 0;
-  const Material mat = a.mats[mid];
-  const double mu = (double)prm.z, lam = (double)prm.w;
-
-  // SVD of the F whose stress enters P2G, kept for the stress
-  double U[3][3], sig[3], V[3][3];
-  bool ok = live;
-
-  // ---------------------------------------------------------------- G2P
-  if (MODE == kFused || MODE == kG2P) {
-    int b0[3];
-    float f0[3];
-    bool in_grid = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
-    const bool valid = live && in_grid;
-    count_event(a.diag, 1, live && !in_grid);
-    ok = valid;
-    int box[6];
-    block_box(valid, b0, red, box);
-    const int ex = box[3] - box[0] + 3, ey = box[4] - box[1] + 3, ez = box[5] - box[2] + 3;
-    const bool empty = box[0] > box[3];
-    const int T = empty ? 0 : ex * ey * ez;
-    const bool use_lds = !empty && T <= cap;
-    if (!empty && !use_lds && threadIdx.x == 0) atomicAdd(&a.diag[2], 1ull);
-    if (use_lds) {
-      for (int t = threadIdx.x; t < T; t += kBlock) {
-        const int tk = t % ez, tq = t / ez;
-        const int tj = tq % ey, ti = tq / ey;
-        const int ix = box[0] + ti, iy = box[1] + tj, iz = box[2] + tk;
-        const float4 g = a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz];
-        float vv[3];
-        grid_velocity(g, ix, iy, iz, a, vv);
-        tile[t] = vv[0];
-        tile[cap + t] = vv[1];
-        tile[2 * cap + t] = vv[2];
-      }
-    }
+  for (;;) {
+    __syncthreads();  // tiles and item_s are reused
+    if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1);
     __syncthreads();
-    if (valid) {
-      float wx[3], wy[3], wz[3];
-      bspline_w(f0[0], wx);
-      bspline_w(f0[1], wy);
-      bspline_w(f0[2], wz);
-      float vs[3] = {0.f, 0.f, 0.f};
-      float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // sum w v_a o_b
-      const int sz = ey * ez;
-      const int a0 = ((b0[0] - box[0]) * ey + (b0[1] - box[1])) * ez + (b0[2] - box[2]);
-#pragma unroll
-      for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
-        for (int oy = 0; oy < 3; ++oy) {
-          const float wxy = wx[ox] * wy[oy];
-          const int row = a0 + ox * sz + oy * ez;
-#pragma unroll
-          for (int oz = 0; oz < 3; ++oz) {
-            const float w = wxy * wz[oz];
-            float vi[3];
-            if (use_lds) {
-              vi[0] = tile[row + oz];
-              vi[1] = tile[cap + row + oz];
-              vi[2] = tile[2 * cap + row + oz];
-            } else {
-              const int ix = b0[0] + ox, iy = b0[1] + oy, iz = b0[2] + oz;
-              grid_velocity(a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, a, vi);
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const float wv = w * vi[c];
-              vs[c] += wv;
-              if (ox) M[c][0] += (float)ox * wv;
-              if (oy) M[c][1] += (float)oy * wv;
-              if (oz) M[c][2] += (float)oz * wv;
-            }
-          }
-        }
-      // C' = 4/dx^2 sum w v (x_i - x_p)^T = 4/dx (M - v f^T)
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Cp[3 * r + c] = 4.0f * inv_dx * (M[r][c] - vs[r] * f0[c]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        vp[k] = vs[k];
-        xp[k] = xp[k] + a.dt * vs[k];
-      }
-      // F_trial = (I + dt C') F, in double
-      double Ftr[9];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          double s = Fd[3 * r + c];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) s += (double)a.dt * (double)Cp[3 * r + k] * Fd[3 * k + c];
-          Ftr[3 * r + c] = s;
-        }
-      if (MODE == kFused || mat.plastic != 0) {
-        svd3(Ftr, U, sig, V);
-        double sig2[3];
-        return_map(mat, mu, lam, Ftr, U, sig, V, Fd, sig2);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) sig[k] = sig2[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Fd[k] = Ftr[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Fd_f[k] = (float)Fd[k];
-      bool fin = true;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) fin &= isfinite(xp[k]);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) fin &= isfinite(Fd_f[k]);
-      count_event(a.diag, 0, !fin);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) a.x[k * N + i] = xp[k];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) a.F[k * N + i] = Fd_f[k];
-      if (MODE == kG2P || a.write_vc) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) a.v[k * N + i] = vp[k];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) a.C[k * N + i] = Cp[k];
-      }
-    }
-    __syncthreads();  // everyone is done reading the G2P tile
-    if (MODE == kG2P) continue;
-  }
+    const int item = item_s;
+    if (item >= n_items) break;
+    const int start = a.chunk_start[item], end = a.chunk_start[item + 1];
+    const int64_t gbase = (int64_t)a.chunk_batch[item] * n * n * n;
 
-  // ---------------------------------------------------------------- P2G
-  if (MODE == kP2G || MODE == kFused) {
-    if (MODE == kP2G && ok) svd3(Fd, U, sig, V);
-    // A = m C - 4/dx^2 dt V0 tau, folded with dx for the node offsets
-    float q[3], Ad[9];
-    const float mass = prm.x;
-    {
-      double tau[9];
-      if (ok) {
-        kirchhoff(mat, mu, lam, Fd, U, sig, V, tau);
-      } else {
+    // 1. box of base cells
+    int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+      int b[3];
+      float f[3];
+      bool in = true;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) tau[k] = 0.0;
-      }
-      const float ks = 4.0f * inv_dx * inv_dx * a.dt * prm.y;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Ad[k] = (mass * Cp[k] - ks * (float)tau[k]) * dx;
-    }
-    int b1[3];
-    float f1[3];
-    bool in_grid = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
-    if (MODE == kP2G) count_event(a.diag, 1, live && !in_grid);
-    // contribution to node o: w (m v + A (o - f) dx) = w (q + Ad o)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) q[r] = mass * vp[r] - (Ad[3 * r] * f1[0] + Ad[3 * r + 1] * f1[1] + Ad[3 * r + 2] * f1[2]);
-    const bool valid = ok && in_grid;
-    int box[6];
-    block_box(valid, b1, red, box);
-    const int ex = box[3] - box[0] + 3, ey = box[4] - box[1] + 3, ez = box[5] - box[2] + 3;
-    const bool empty = box[0] > box[3];
-    const int T = empty ? 0 : ex * ey * ez;
-    const bool use_lds = !empty && T <= cap;
-    if (!empty && !use_lds && threadIdx.x == 0) atomicAdd(&a.diag[2], 1ull);
-    // The LDS tile accumulates in double: native LDS f64 atomic adds run far
-    // faster than f32 ones on this chip, and the sum is more accurate.
-    if (use_lds) {
-      for (int t = threadIdx.x; t < T; t += kBlock) {
-        tile_d[t] = 0.0;
-        tile_d[cap + t] = 0.0;
-        tile_d[2 * cap + t] = 0.0;
-        tile_d[3 * cap + t] = 0.0;
-      }
-    }
-    __syncthreads();
-    if (valid) {
-      float w[3][3];
-      bspline_w(f1[0], w[0]);
-      bspline_w(f1[1], w[1]);
-      bspline_w(f1[2], w[2]);
-      // staggered node order: lane group g visits offset (k + g_axis) mod 3 at step k
-      const int g = (threadIdx.x & 63) % 27;
-      const int gs[3] = {g / 9, (g / 3) % 3, g % 3};
-      int r[3][3];
-      float wr[3][3];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax)
+      for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
+      if (in) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          r[ax][k] = rot3(gs[ax], k);
-          wr[ax][k] = sel3(w[ax], r[ax][k]);
+          lo[k] = min(lo[k], b[k]);
+          hi[k] = max(hi[k], b[k]);
         }
-      const int sz = ey * ez;
-      const int a0 = ((b1[0] - box[0]) * ey + (b1[1] - box[1])) * ez + (b1[2] - box[2]);
+      }
+    }
+    int box[6];
+    block_minmax(lo, hi, red, box);
+    const bool empty = box[0] > box[3];
+    // G2P tile: nodes box.lo .. box.hi + 2
+    const int gx = box[3] - box[0] + 3, gy = box[4] - box[1] + 3, gz = box[5] - box[2] + 3;
+    const int GT = empty ? 0 : gx * gy * gz;
+    // P2G tile: base cells in [plo, phi] (the box grown by one cell where the
+    // particles have moved, clamped to the grid), nodes plo .. phi + 2
+    const int grow = (MODE == kP2G) ? 0 : 1;
+    int plo[3], phi[3];
 #pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        const float ox = (float)r[0][kx];
-        float vx[3];
+    for (int k = 0; k < 3; ++k) {
+      plo[k] = max(box[k] - grow, 0);
+      phi[k] = min(box[k + 3] + grow, n - 3);
+    }
+    const int px = phi[0] - plo[0] + 3, py = phi[1] - plo[1] + 3, pz = phi[2] - plo[2] + 3;
+    const int PT = empty ? 0 : px * py * pz;
+    const bool lds_g = (MODE != kP2G) && !empty && GT <= cap;
+    const bool lds_p = (MODE != kG2P) && !empty && PT <= cap;
+    if (threadIdx.x == 0 && !empty && (((MODE != kP2G) && !lds_g) || ((MODE != kG2P) && !lds_p)))
+      atomicAdd(&a.diag[2], 1ull);
+
+    // 2. tiles
+    if (lds_g) {
+      for (int t = threadIdx.x; t < GT; t += kBlock) {
+        const int tk = t % gz, tq = t / gz;
+        const int tj = tq % gy, ti = tq / gy;
+        const int ix = box[0] + ti, iy = box[1] + tj, iz = box[2] + tk;
+        float vv[3];
+        grid_velocity(a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, a, vv);
+        gtile[t] = vv[0];
+        gtile[kTileCapMax + t] = vv[1];
+        gtile[2 * kTileCapMax + t] = vv[2];
+      }
+    }
+    if (lds_p) {
+      for (int t = threadIdx.x; t < PT; t += kBlock) {
+        ptile[t] = 0.0;
+        ptile[kTileCapMax + t] = 0.0;
+        ptile[2 * kTileCapMax + t] = 0.0;
+        ptile[3 * kTileCapMax + t] = 0.0;
+      }
+    }
+    __syncthreads();
+
+    // 3. particles
+    for (int sub = start; sub < end; sub += kBlock) {
+      const int i = sub + (int)threadIdx.x;
+      if (i >= end) break;
+      float xp[3], vp[3] = {0.f, 0.f, 0.f};
+      float Cp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      double Fd[9];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) vx[c] = q[c] + Ad[3 * c] * ox;
+      for (int k = 0; k < 3; ++k) xp[k] = a.x[k * N + i];
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-          const float oy = (float)r[1][ky];
-          const float wxy = wr[0][kx] * wr[1][ky];
-          float vy[3];
+      for (int k = 0; k < 9; ++k) Fd[k] = (double)a.F[k * N + i];
+      const float4 prm = a.prm[i];
+      int mid = a.mat[i];
+      if (MODE == kP2G) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) vy[c] = vx[c] + Ad[3 * c + 1] * oy;
-          const int row = a0 + r[0][kx] * sz + r[1][ky] * ez;
+        for (int k = 0; k < 3; ++k) vp[k] = a.v[k * N + i];
 #pragma unroll
-          for (int kz = 0; kz < 3; ++kz) {
-            const float oz = (float)r[2][kz];
-            const float wgt = wxy * wr[2][kz];
-            float val[4];
+        for (int k = 0; k < 9; ++k) Cp[k] = a.C[k * N + i];
+      }
+      mid = (mid >= 0 && mid < a.n_materials) ? mid : 0;
+      const Material mat = a.mats[mid];
+      const double mu = (double)prm.z, lam = (double)prm.w;
+      double tau[9];
+      bool ok = true;
+
+      // ---------------------------------------------------------- G2P
+      if (MODE != kP2G) {
+        int b0[3];
+        float f0[3];
+        bool in_grid = true;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) val[c] = wgt * (vy[c] + Ad[3 * c + 2] * oz);
-            val[3] = wgt * mass;
-            if (use_lds) {
-              const int t = row + r[2][kz];
+        for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
+        ok = in_grid;
+        if (!in_grid) atomicAdd(&a.diag[1], 1ull);
+        if (ok) {
+          float wx[3], wy[3], wz[3];
+          bspline_w(f0[0], wx);
+          bspline_w(f0[1], wy);
+          bspline_w(f0[2], wz);
+          float vs[3] = {0.f, 0.f, 0.f};
+          float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // sum w v_a o_b
+          const int sz = gy * gz;
+          const int a0 = ((b0[0] - box[0]) * gy + (b0[1] - box[1])) * gz + (b0[2] - box[2]);
 #pragma unroll
-              for (int c = 0; c < 4; ++c) atomicAdd(&tile_d[c * cap + t], (double)val[c]);
-            } else {
-              const int ix = b1[0] + r[0][kx], iy = b1[1] + r[1][ky], iz = b1[2] + r[2][kz];
-              float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
+          for (int ox = 0; ox < 3; ++ox)
 #pragma unroll
-              for (int c = 0; c < 4; ++c) atomicAdd(gp + c, val[c]);
+            for (int oy = 0; oy < 3; ++oy) {
+              const float wxy = wx[ox] * wy[oy];
+              const int row = a0 + ox * sz + oy * gz;
+#pragma unroll
+              for (int oz = 0; oz < 3; ++oz) {
+                const float w = wxy * wz[oz];
+                float vi[3];
+                if (lds_g) {
+                  vi[0] = gtile[row + oz];
+                  vi[1] = gtile[kTileCapMax + row + oz];
+                  vi[2] = gtile[2 * kTileCapMax + row + oz];
+                } else {
+                  const int ix = b0[0] + ox, iy = b0[1] + oy, iz = b0[2] + oz;
+                  grid_velocity(a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, a, vi);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                  const float wv = w * vi[c];
+                  vs[c] += wv;
+                  if (ox) M[c][0] += (float)ox * wv;
+                  if (oy) M[c][1] += (float)oy * wv;
+                  if (oz) M[c][2] += (float)oz * wv;
+                }
+              }
+            }
+          // C' = 4/dx^2 sum w v (x_i - x_p)^T = 4/dx (M - v f^T)
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Cp[3 * r + c] = 4.0f * inv_dx * (M[r][c] - vs[r] * f0[c]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            vp[k] = vs[k];
+            xp[k] = xp[k] + a.dt * vs[k];
+          }
+          // F_trial = (I + dt C') F, in double
+          double Ftr[9];
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              double acc = Fd[3 * r + c];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) acc += (double)a.dt * (double)Cp[3 * r + k] * Fd[3 * k + c];
+              Ftr[3 * r + c] = acc;
+            }
+          update_and_stress(mat, mu, lam, Ftr, true, MODE == kFused, Fd, tau);
+          float Ff[9];
+          bool fin = true;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            Ff[k] = (float)Fd[k];
+            fin &= isfinite(Ff[k]);
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) fin &= isfinite(xp[k]);
+          if (!fin) {
+            atomicAdd(&a.diag[0], 1ull);
+            ok = false;
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) a.x[k * N + i] = xp[k];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) a.F[k * N + i] = Ff[k];
+          if (MODE == kG2P || a.write_vc) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a.v[k * N + i] = vp[k];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) a.C[k * N + i] = Cp[k];
+          }
+        }
+      }
+
+      // ---------------------------------------------------------- P2G
+      if (MODE != kG2P) {
+        int b1[3];
+        float f1[3];
+        bool in_grid = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
+        if (MODE == kP2G && !in_grid) atomicAdd(&a.diag[1], 1ull);
+        if (ok && in_grid) {
+          // A = m C - 4/dx^2 dt V0 tau, folded with dx for the node offsets
+          const float mass = prm.x;
+          float q[3], Ad[9];
+          {
+            if (MODE == kP2G) {
+              double Fs[9];
+#pragma unroll
+              for (int k = 0; k < 9; ++k) Fs[k] = Fd[k];
+              update_and_stress(mat, mu, lam, Fs, false, true, Fd, tau);
+            }
+            const float ks = 4.0f * inv_dx * inv_dx * a.dt * prm.y;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Ad[k] = (mass * Cp[k] - ks * (float)tau[k]) * dx;
+          }
+          // contribution to node o: w (m v + A (o - f) dx) = w (q + Ad o)
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            q[r] = mass * vp[r] - (Ad[3 * r] * f1[0] + Ad[3 * r + 1] * f1[1] + Ad[3 * r + 2] * f1[2]);
+          const bool in_tile = lds_p && b1[0] >= plo[0] && b1[0] <= phi[0] && b1[1] >= plo[1] &&
+                               b1[1] <= phi[1] && b1[2] >= plo[2] && b1[2] <= phi[2];
+          if (lds_p && !in_tile) atomicAdd(&a.diag[3], 1ull);
+          float w[3][3];
+          bspline_w(f1[0], w[0]);
+          bspline_w(f1[1], w[1]);
+          bspline_w(f1[2], w[2]);
+          // staggered node order: lane group g visits offset (k + g_axis) mod 3 at step k
+          const int g = (threadIdx.x & 63) % 27;
+          const int gs[3] = {g / 9, (g / 3) % 3, g % 3};
+          int r[3][3];
+          float wr[3][3];
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              r[ax][k] = rot3(gs[ax], k);
+              wr[ax][k] = sel3(w[ax], r[ax][k]);
+            }
+          const int sz = py * pz;
+          const int a1 = ((b1[0] - plo[0]) * py + (b1[1] - plo[1])) * pz + (b1[2] - plo[2]);
+#pragma unroll
+          for (int kx = 0; kx < 3; ++kx) {
+            const float ox = (float)r[0][kx];
+            float vx[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vx[c] = q[c] + Ad[3 * c] * ox;
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky) {
+              const float oy = (float)r[1][ky];
+              const float wxy = wr[0][kx] * wr[1][ky];
+              float vy[3];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) vy[c] = vx[c] + Ad[3 * c + 1] * oy;
+              const int row = a1 + r[0][kx] * sz + r[1][ky] * pz;
+#pragma unroll
+              for (int kz = 0; kz < 3; ++kz) {
+                const float oz = (float)r[2][kz];
+                const float wgt = wxy * wr[2][kz];
+                float val[4];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) val[c] = wgt * (vy[c] + Ad[3 * c + 2] * oz);
+                val[3] = wgt * mass;
+                if (in_tile) {
+                  const int t = row + r[2][kz];
+#pragma unroll
+                  for (int c = 0; c < 4; ++c) atomicAdd(&ptile[c * kTileCapMax + t], (double)val[c]);
+                } else {
+                  const int ix = b1[0] + r[0][kx], iy = b1[1] + r[1][ky], iz = b1[2] + r[2][kz];
+                  float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
+#pragma unroll
+                  for (int c = 0; c < 4; ++c) atomicAdd(gp + c, val[c]);
+                }
+              }
             }
           }
         }
       }
     }
-    __syncthreads();
-    if (use_lds) {
-      for (int t = threadIdx.x; t < T; t += kBlock) {
-        const double m = tile_d[3 * cap + t];
+
+    // 4. flush
+    if (lds_p) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < PT; t += kBlock) {
+        const double m = ptile[3 * kTileCapMax + t];
         if (m == 0.0) continue;
-        const int tk = t % ez, tq = t / ez;
-        const int tj = tq % ey, ti = tq / ey;
-        float* gp = (float*)&a.grid_out[gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk)];
-        atomicAdd(gp + 0, (float)tile_d[t]);
-        atomicAdd(gp + 1, (float)tile_d[cap + t]);
-        atomicAdd(gp + 2, (float)tile_d[2 * cap + t]);
+        const int tk = t % pz, tq = t / pz;
+        const int tj = tq % py, ti = tq / py;
+        float* gp = (float*)&a.grid_out[gbase + ((int64_t)(plo[0] + ti) * n + (plo[1] + tj)) * n + (plo[2] + tk)];
+        atomicAdd(gp + 0, (float)ptile[t]);
+        atomicAdd(gp + 1, (float)ptile[kTileCapMax + t]);
+        atomicAdd(gp + 2, (float)ptile[2 * kTileCapMax + t]);
         atomicAdd(gp + 3, (float)m);
       }
     }
-    __syncthreads();  // the tile is reused by the next chunk
   }
-  }  // chunk loop
 }
 
 
 // --------------------------------------------------------------------------
 // Fill, sort (counting sort by cell key), gather / scatter
 // --------------------------------------------------------------------------
-__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n, int* counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (counter && i == 0) *counter = 0;
   const int64_t n4 = n >> 2;
   if (i < n4) reinterpret_cast<uint4*>(p)[i] = make_uint4(v, v, v, v);
   const int64_t t = (n4 << 2) + i;
@@ -573,19 +634,20 @@ __global__ void k_place(const uint32_t* key, const uint32_t* slot, const uint32_
   if (i < N) perm[off[key[i]] + slot[i]] = (int)i;
 }
 
-// Chunk table after a sort: each 4^3-cell block's particles (a contiguous
-// range of the sorted order) are cut into chunks of at most kBlock.
+// Work-item table after a sort: each 4^3-cell block's particles (a
+// contiguous range of the sorted order) are cut into items of at most
+// `item` particles.
 // off = exclusive bin offsets (64 bins per block), nchk[b] = chunks of block b.
-__global__ void k_block_chunk_count(const uint32_t* off, int64_t nblocks, int64_t N, uint32_t* nchk) {
+__global__ void k_block_chunk_count(const uint32_t* off, int64_t nblocks, int64_t N, int item, uint32_t* nchk) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nblocks) return;
   const uint32_t lo = off[b * 64];
   const uint32_t hi = (b + 1 < nblocks) ? off[(b + 1) * 64] : (uint32_t)N;
-  nchk[b] = (hi - lo + kBlock - 1) / kBlock;
+  nchk[b] = (hi - lo + item - 1) / item;
 }
 
 // base = exclusive scan of nchk (same array, scanned in place beforehand)
-__global__ void k_block_chunk_write(const uint32_t* off, const uint32_t* base, int64_t nblocks, int64_t N,
+__global__ void k_block_chunk_write(const uint32_t* off, const uint32_t* base, int64_t nblocks, int64_t N, int item,
                                     int blocks_per_scene, int* chunk_start, int* chunk_batch, int* n_chunks) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nblocks) return;
@@ -594,7 +656,7 @@ __global__ void k_block_chunk_write(const uint32_t* off, const uint32_t* base, i
   const uint32_t c0 = base[b];
   const int scene = (int)(b / blocks_per_scene);
   uint32_t c = c0;
-  for (uint32_t s = lo; s < hi; s += kBlock, ++c) {
+  for (uint32_t s = lo; s < hi; s += item, ++c) {
     chunk_start[c] = (int)s;
     chunk_batch[c] = scene;
   }
