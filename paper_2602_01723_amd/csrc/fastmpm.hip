@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fastmpm.h"
+#include "mpm_adjoint.hpp"
 #include "mpm_kernels.hpp"
 
 using fmpm::kBlock;
@@ -58,6 +59,11 @@ struct mpm_context {
   std::vector<int> prof_cls;
   double prof_ms[MPM_PROFILE_CLASSES] = {0};
   int64_t prof_cnt[MPM_PROFILE_CLASSES] = {0};
+
+  // the last taped forward (mpm_step_n with a tape)
+  const void* tape_ptr = nullptr;
+  int32_t tape_n = -1;
+  int32_t tape_K = 0;
 
   int last_grid = -1;
   int64_t substeps = 0;
@@ -231,6 +237,70 @@ int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   return MPM_OK;
 }
 
+// Tape layout (floats; N particles, B n^3 grid nodes):
+//   checkpoints  n_ckpt x 24 N   state at substeps 0, K, 2K, ... in caller order
+//                                (x 3N, v 3N, C 9N, F 9N)
+//   segment      K x 24 N        recomputed states of one segment, sorted order
+//   adj, adjc    24 N each       state adjoint, sorted / caller order
+//   gl, gn       N each          parameter gradients of a segment, sorted order
+//   lnE, nu      N each          sorted copies of the parameters
+//   vhb          4 B n^3         adjoint of the grid velocity
+struct TapeLayout {
+  int64_t n_ckpt, K;
+  float *ckpt, *seg, *adj, *adjc, *gl, *gn, *lnE, *nu;
+  float4* vhb;
+  size_t bytes;
+};
+
+TapeLayout tape_layout(mpm_ctx c, int32_t n_steps, int32_t K, void* base) {
+  TapeLayout t{};
+  const int64_t N = std::max<int64_t>(c->N, 1);
+  t.K = K;
+  t.n_ckpt = std::max<int64_t>(1, (n_steps + K - 1) / K);
+  char* p = static_cast<char*>(base);
+  auto take = [&](int64_t floats) {
+    char* q = p;
+    p += ((floats * 4 + 255) / 256) * 256;
+    return reinterpret_cast<float*>(q);
+  };
+  t.ckpt = take(t.n_ckpt * 24 * N);
+  t.seg = take((int64_t)K * 24 * N);
+  t.adj = take(24 * N);
+  t.adjc = take(24 * N);
+  t.gl = take(N);
+  t.gn = take(N);
+  t.lnE = take(N);
+  t.nu = take(N);
+  t.vhb = reinterpret_cast<float4*>(take(4 * c->nodes));
+  t.bytes = (size_t)(p - static_cast<char*>(base));
+  return t;
+}
+
+bool adjoint_supported(mpm_ctx c) {
+  for (int k = 0; k < c->n_mat; ++k)
+    if (c->mats[k].elastic != MPM_ELASTIC_FCR || c->mats[k].plastic != MPM_PLASTIC_NONE) return false;
+  return true;
+}
+
+int copy_f32(mpm_ctx c, float* out, const float* in, int64_t count, hipStream_t s) {
+  if (count <= 0) return MPM_OK;
+  fmpm::k_copy_f32<<<blocks_for(count, 256), 256, 0, s>>>(out, in, count);
+  LAUNCH_CHECK(c, "k_copy_f32");
+  return MPM_OK;
+}
+
+// internal state (x, v, C, F planes) -> caller-order 24-plane block via pid
+int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
+  const unsigned g = blocks_for(c->N, 256);
+  const int64_t N = c->N;
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24, c->xs, c->pid, 3, N);
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24 + 3 * N, c->vs, c->pid, 3, N);
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24 + 6 * N, c->Cs, c->pid, 9, N);
+  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24 + 15 * N, c->Fs, c->pid, 9, N);
+  LAUNCH_CHECK(c, "scatter_state");
+  return MPM_OK;
+}
+
 template <int MODE>
 int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hipStream_t s) {
   fmpm::SubstepArgs a = make_args(c);
@@ -388,10 +458,29 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape,
   int rc = check_particles(ctx, p);
   if (rc) return rc;
   if (n_steps < 0) return fail(ctx, MPM_EINVAL, "n_steps < 0");
-  if (tape) return fail(ctx, MPM_EUNSUPPORTED, "tape not supported by this build");
-  (void)checkpoint_every;
+  if (tape && checkpoint_every < 1) return fail(ctx, MPM_EINVAL, "checkpoint_every < 1 with a tape");
+  if (tape && !adjoint_supported(ctx))
+    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers fixed-corotated materials without plasticity");
   hipStream_t s = (hipStream_t)stream;
   ctx->last_stream = s;
+  TapeLayout tl{};
+  const int64_t N = ctx->N;
+  if (tape) {
+    tl = tape_layout(ctx, n_steps, checkpoint_every, tape);
+    ctx->tape_ptr = tape;
+    ctx->tape_n = n_steps;
+    ctx->tape_K = checkpoint_every;
+    if (N > 0) {  // checkpoint 0: the caller's state as given
+      rc = copy_f32(ctx, tl.ckpt, p->x, 3 * N, s);
+      rc = rc ? rc : copy_f32(ctx, tl.ckpt + 3 * N, p->v, 3 * N, s);
+      rc = rc ? rc : copy_f32(ctx, tl.ckpt + 6 * N, p->C, 9 * N, s);
+      rc = rc ? rc : copy_f32(ctx, tl.ckpt + 15 * N, p->F, 9 * N, s);
+      if (rc) return rc;
+    }
+  } else {
+    ctx->tape_ptr = nullptr;
+    ctx->tape_n = -1;
+  }
   if (n_steps == 0 || ctx->N == 0) {
     ctx->substeps += n_steps;
     return MPM_OK;
@@ -412,9 +501,14 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape,
     } else {
       rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, 4, ctx->work_counter);
       if (rc) return rc;
-      rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], 0, s);
+      const bool ckpt = tape && (st + 1) % checkpoint_every == 0;
+      rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], ckpt ? 1 : 0, s);
       if (rc) return rc;
       cur = 1 - cur;
+      if (ckpt) {
+        rc = scatter_state(ctx, tl.ckpt + ((st + 1) / checkpoint_every) * 24 * N, s);
+        if (rc) return rc;
+      }
       if (ctx->sort_every > 0 && (st + 1) % ctx->sort_every == 0) {
         rc = resort_internal(ctx, s);
         if (rc) return rc;
@@ -432,17 +526,133 @@ int mpm_substep(mpm_ctx ctx, const mpm_particles* p, void* stream) {
 
 int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes) {
   if (!ctx || !bytes || n_steps < 0 || checkpoint_every < 1) return MPM_EINVAL;
-  *bytes = 0;
-  return fail(ctx, MPM_EUNSUPPORTED, "tape not supported by this build");
+  *bytes = tape_layout(ctx, n_steps, checkpoint_every, nullptr).bytes;
+  return MPM_OK;
 }
 
 int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t n_steps, const float* g_x,
                  const float* g_v, const float* g_C, const float* g_F, float* g_log_E, float* g_nu, float* g_x0,
                  float* g_v0, float* g_C0, float* g_F0, void* stream) {
-  (void)p; (void)tape; (void)n_steps; (void)g_x; (void)g_v; (void)g_C; (void)g_F; (void)g_log_E; (void)g_nu;
-  (void)g_x0; (void)g_v0; (void)g_C0; (void)g_F0; (void)stream;
   if (!ctx) return MPM_EINVAL;
-  return fail(ctx, MPM_EUNSUPPORTED, "backward not supported by this build");
+  if (!p || !tape || !g_log_E || !g_nu) return fail(ctx, MPM_EINVAL, "NULL argument");
+  if (ctx->N > 0 && (!p->mass || !p->vol0 || !p->log_E || !p->nu || !p->mat_id))
+    return fail(ctx, MPM_EINVAL, "a parameter array is NULL");
+  if (!adjoint_supported(ctx))
+    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers fixed-corotated materials without plasticity");
+  if (tape != ctx->tape_ptr || n_steps != ctx->tape_n)
+    return fail(ctx, MPM_ESTATE, "tape does not hold the last taped mpm_step_n of this length");
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  const int64_t N = ctx->N;
+  const int K = ctx->tape_K;
+  TapeLayout tl = tape_layout(ctx, n_steps, K, const_cast<void*>(tape));
+  if (N == 0) return MPM_OK;
+  int rc = fill_u32(ctx, g_log_E, N, s);
+  rc = rc ? rc : fill_u32(ctx, g_nu, N, s);
+  // caller-order adjoint of the final state
+  const float* gin[4] = {g_x, g_v, g_C, g_F};
+  const int64_t off[4] = {0, 3 * N, 6 * N, 15 * N};
+  const int64_t cnt[4] = {3 * N, 3 * N, 9 * N, 9 * N};
+  for (int k = 0; k < 4 && !rc; ++k)
+    rc = gin[k] ? copy_f32(ctx, tl.adjc + off[k], gin[k], cnt[k], s) : fill_u32(ctx, tl.adjc + off[k], cnt[k], s);
+  if (rc) return rc;
+  const unsigned gp = blocks_for(N, 256);
+  for (int64_t seg = tl.n_ckpt - 1; seg >= 0 && n_steps > 0; --seg) {
+    const int k0 = (int)(seg * K);
+    const int L = std::min(K, n_steps - k0);
+    if (L <= 0) continue;
+    const float* ck = tl.ckpt + seg * 24 * N;
+    // (1) sort the checkpoint, gather state and parameters into sorted order
+    rc = sort_keys(ctx, ck, s);
+    if (rc) return rc;
+    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->xs, ck, ctx->perm, 3, N);
+    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->vs, ck + 3 * N, ctx->perm, 3, N);
+    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->Cs, ck + 6 * N, ctx->perm, 9, N);
+    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->Fs, ck + 15 * N, ctx->perm, 9, N);
+    fmpm::k_gather_params<<<gp, 256, 0, s>>>(ctx->prm, ctx->mat, ctx->pid, p->mass, p->vol0, p->log_E, p->nu,
+                                              p->mat_id, ctx->perm, N);
+    fmpm::k_gather_lnE_nu<<<gp, 256, 0, s>>>(tl.lnE, tl.nu, p->log_E, p->nu, ctx->perm, N);
+    LAUNCH_CHECK(ctx, "backward gather");
+    // (2) recompute the segment: slot j holds the state of substep k0 + j
+    auto slot = [&](int j) { return tl.seg + (int64_t)j * 24 * N; };
+    rc = copy_f32(ctx, slot(0), ctx->xs, 3 * N, s);
+    rc = rc ? rc : copy_f32(ctx, slot(0) + 3 * N, ctx->vs, 3 * N, s);
+    rc = rc ? rc : copy_f32(ctx, slot(0) + 6 * N, ctx->Cs, 9 * N, s);
+    rc = rc ? rc : copy_f32(ctx, slot(0) + 15 * N, ctx->Fs, 9 * N, s);
+    rc = rc ? rc : fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, -1, ctx->work_counter);
+    rc = rc ? rc : launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s);
+    if (rc) return rc;
+    int cur = 0;
+    for (int j = 0; j + 1 < L; ++j) {
+      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, -1, ctx->work_counter);
+      rc = rc ? rc : launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], 1, s);
+      if (rc) return rc;
+      cur = 1 - cur;
+      rc = copy_f32(ctx, slot(j + 1), ctx->xs, 3 * N, s);
+      rc = rc ? rc : copy_f32(ctx, slot(j + 1) + 3 * N, ctx->vs, 3 * N, s);
+      rc = rc ? rc : copy_f32(ctx, slot(j + 1) + 6 * N, ctx->Cs, 9 * N, s);
+      rc = rc ? rc : copy_f32(ctx, slot(j + 1) + 15 * N, ctx->Fs, 9 * N, s);
+      if (rc) return rc;
+    }
+    // (3) adjoint of the segment's final state, in sorted order
+    fmpm::k_gather_or_zero<<<gp, 256, 0, s>>>(tl.adj, tl.adjc, ctx->perm, 24, N);
+    LAUNCH_CHECK(ctx, "adjoint gather");
+    rc = fill_u32(ctx, tl.gl, N, s);
+    rc = rc ? rc : fill_u32(ctx, tl.gn, N, s);
+    if (rc) return rc;
+    // (4) reverse the substeps of the segment
+    for (int j = L - 1; j >= 0; --j) {
+      const float* st = slot(j);
+      fmpm::SubstepArgs a = make_args(ctx);
+      a.x = const_cast<float*>(st);
+      a.v = const_cast<float*>(st + 3 * N);
+      a.C = const_cast<float*>(st + 6 * N);
+      a.F = const_cast<float*>(st + 15 * N);
+      a.grid_out = ctx->grid[0];
+      rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, -1, ctx->work_counter);
+      if (rc) return rc;
+      fmpm::k_substep<fmpm::kP2G><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
+      LAUNCH_CHECK(ctx, "backward P2G");
+      rc = fill_u32(ctx, tl.vhb, 4 * ctx->nodes, s);
+      if (rc) return rc;
+      fmpm::AdjArgs b{};
+      b.x = st;
+      b.v = st + 3 * N;
+      b.C = st + 6 * N;
+      b.F = st + 15 * N;
+      b.prm = ctx->prm;
+      b.lnE = tl.lnE;
+      b.nu = tl.nu;
+      b.N = N;
+      b.chunk_start = ctx->chunk_start;
+      b.chunk_batch = ctx->chunk_batch;
+      b.grid = ctx->grid[0];
+      b.vhb = tl.vhb;
+      b.ax = tl.adj;
+      b.av = tl.adj + 3 * N;
+      b.aC = tl.adj + 6 * N;
+      b.aF = tl.adj + 15 * N;
+      b.g_lnE = tl.gl;
+      b.g_nu = tl.gn;
+      b.n = ctx->n;
+      b.bound = ctx->cfg.bound;
+      b.dt = ctx->cfg.dt;
+      for (int k = 0; k < 3; ++k) b.g[k] = ctx->cfg.gravity[k];
+      fmpm::k_adj_g2p<<<ctx->n_chunks, kBlock, 0, s>>>(b);
+      LAUNCH_CHECK(ctx, "k_adj_g2p");
+      fmpm::k_adj_p2g<<<ctx->n_chunks, kBlock, 0, s>>>(b);
+      LAUNCH_CHECK(ctx, "k_adj_p2g");
+    }
+    // (5) back to caller order
+    fmpm::k_scatter_planes<<<gp, 256, 0, s>>>(tl.adjc, tl.adj, ctx->pid, 24, N);
+    fmpm::k_scatter_add<<<gp, 256, 0, s>>>(g_log_E, tl.gl, ctx->pid, 1, N);
+    fmpm::k_scatter_add<<<gp, 256, 0, s>>>(g_nu, tl.gn, ctx->pid, 1, N);
+    LAUNCH_CHECK(ctx, "adjoint scatter");
+  }
+  float* gout[4] = {g_x0, g_v0, g_C0, g_F0};
+  for (int k = 0; k < 4 && !rc; ++k)
+    if (gout[k]) rc = copy_f32(ctx, gout[k], tl.adjc + off[k], cnt[k], s);
+  return rc;
 }
 
 int mpm_grid_state(mpm_ctx ctx, float* m, float* mv, float* v, void* stream) {

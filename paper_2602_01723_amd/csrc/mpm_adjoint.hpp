@@ -1,0 +1,421 @@
+// Reverse-mode (adjoint) kernels of the MLS-MPM substep for elastic
+// particles with identity plasticity and the fixed-corotated model
+// (included once, by fastmpm.hip after mpm_kernels.hpp).
+//
+// Forward substep k on state s_k = (x, v, C, F), per particle p and node i:
+//   tau_p = 2 mu (F - R) F^T + lam J (J - 1) I            (App. B.1, Corotated)
+//   A_p   = m_p C_p - D dt V_p tau_p,  D = 4 / dx^2
+//   m_i   = sum_p w_ip m_p,  mv_i = sum_p w_ip (m_p v_p + A_p (x_i - x_p))
+//   vh_i  = mv_i / m_i + dt g   (active nodes; 0 on walls and empty nodes)
+//   v'_p  = sum_i w_ip vh_i,  C'_p = D sum_i w_ip vh_i (x_i - x_p)^T
+//   x'_p  = x_p + dt v'_p,    F'_p = (I + dt C'_p) F_p
+// with w_ip the quadratic B-spline weights of x_p.
+//
+// Reverse, given the adjoints (xb', vb', Cb', Fb') of s_{k+1}:
+//   k_adj_g2p  (particle-parallel, scatter):  Fb = (I + dt C')^T Fb',
+//     Cbt = Cb' + dt Fb' F^T, vbt = vb' + dt xb', xb = xb';
+//     vhb_i += w (vbt + D Cbt dpos)  (global FP32 atomics);
+//     xb += [vh_i . vbt + D vh_i^T Cbt dpos] grad_x w - D w Cbt^T vh_i
+//   k_adj_p2g  (particle-parallel, gather):  per node
+//     mvb_i = vhb_i / m_i, mb_i = -vhb_i . (mv_i / m_i) / m_i  (active nodes),
+//     wb = mb_i m_p + mvb_i . (m_p v_p + A_p dpos),  vb += m_p w mvb_i,
+//     Ab += w mvb_i dpos^T,  xb += wb grad_x w - w A_p^T mvb_i;
+//   then Cb = m_p Ab, taub = -D dt V_p Ab, and the stress adjoint (FP64)
+//     Fb += 2 mu (taub F + taub^T (F - R) - R [c]x) + lam (2J - 1) J tr(taub) F^-T,
+//     c = (tr(S) I - S)^-1 axial(R^T M - M^T R), M = taub F, S = R^T F,
+//     mub = <taub, 2 (F - R) F^T>, lamb = J (J - 1) tr(taub),
+//   and the parameter gradients
+//     g_logE += mub mu + lamb lam,
+//     g_nu   += -mub mu / (1 + nu) + lamb E (1 + 2 nu^2) / ((1 + nu)(1 - 2 nu))^2.
+#pragma once
+
+#include "mpm_kernels.hpp"
+
+namespace fmpm {
+
+struct AdjArgs {
+  // state s_k of the substep being reversed (internal order, plane stride N)
+  const float* x;
+  const float* v;
+  const float* C;
+  const float* F;
+  const float4* prm;   // mass, vol0, mu, lam
+  const float* lnE;    // log E (internal order)
+  const float* nu;     // Poisson ratio (internal order)
+  int64_t N;
+  const int* chunk_start;  // per-scene chunks of kBlock particles
+  const int* chunk_batch;
+  const float4* grid;  // (mv, m) of substep k
+  float4* vhb;         // adjoint of the grid velocity (xyz), zeroed before k_adj_g2p
+  // adjoint state: in = adjoint of s_{k+1}, out = adjoint of s_k
+  float* ax;
+  float* av;
+  float* aC;
+  float* aF;
+  float* g_lnE;        // accumulated parameter gradients (internal order)
+  float* g_nu;
+  int n;
+  int bound;
+  float dt;
+  float g[3];
+};
+
+__device__ __forceinline__ void bspline_dw(float f, float* dw) {
+  dw[0] = f - 1.5f;          // d/df 0.5 (1.5 - f)^2
+  dw[1] = -2.0f * (f - 1.0f);  // d/df 0.75 - (f - 1)^2
+  dw[2] = f - 0.5f;          // d/df 0.5 (f - 0.5)^2
+}
+
+__device__ __forceinline__ bool grid_active(float m, int ix, int iy, int iz, int n, int bd) {
+  const bool wall = ix < bd || iy < bd || iz < bd || ix >= n - bd || iy >= n - bd || iz >= n - bd;
+  return (m > 0.0f) && !wall;
+}
+
+// Polar rotation of F (det F > 0 expected), SVD fallback.
+__device__ __forceinline__ void polar_rotation(const double* F, double* R) {
+  if (polar_rotation_newton(F, R)) return;
+  double U[3][3], V[3][3], sg[3];
+  svd3(F, U, sg, V);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) R[3 * i + j] = U[i][0] * V[j][0] + U[i][1] * V[j][1] + U[i][2] * V[j][2];
+}
+
+// Adjoint of the fixed-corotated Kirchhoff stress: Fb += dL/dF, mub, lamb.
+__device__ __forceinline__ void tau_fcr_adjoint(const double* F, const double* R, double mu, double lam,
+                                                const double* tb, double* Fb, double& mub, double& lamb) {
+  const double J = det3(F);
+  double trtb = tb[0] + tb[4] + tb[8];
+  // mub = <tb, 2 (F - R) F^T>
+  double P[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) P[k] = F[k] - R[k];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      s += tb[3 * i + j] * (P[3 * i] * F[3 * j] + P[3 * i + 1] * F[3 * j + 1] + P[3 * i + 2] * F[3 * j + 2]);
+  mub = 2.0 * s;
+  lamb = J * (J - 1.0) * trtb;
+  // M = tb F, S = R^T F
+  double M[9], S[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      M[3 * i + j] = tb[3 * i] * F[j] + tb[3 * i + 1] * F[3 + j] + tb[3 * i + 2] * F[6 + j];
+      S[3 * i + j] = R[i] * F[j] + R[3 + i] * F[3 + j] + R[6 + i] * F[6 + j];
+    }
+  // Y = R^T M; a = axial(Y - Y^T)
+  double Y[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Y[3 * i + j] = R[i] * M[j] + R[3 + i] * M[3 + j] + R[6 + i] * M[6 + j];
+  const double av[3] = {Y[7] - Y[5], Y[2] - Y[6], Y[3] - Y[1]};
+  // K = tr(S) I - S (symmetrised), c = K^-1 a
+  const double trS = S[0] + S[4] + S[8];
+  double K[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) K[3 * i + j] = ((i == j) ? trS : 0.0) - 0.5 * (S[3 * i + j] + S[3 * j + i]);
+  double cof[9];
+  cof[0] = K[4] * K[8] - K[5] * K[7];
+  cof[1] = K[5] * K[6] - K[3] * K[8];
+  cof[2] = K[3] * K[7] - K[4] * K[6];
+  cof[3] = K[2] * K[7] - K[1] * K[8];
+  cof[4] = K[0] * K[8] - K[2] * K[6];
+  cof[5] = K[1] * K[6] - K[0] * K[7];
+  cof[6] = K[1] * K[5] - K[2] * K[4];
+  cof[7] = K[2] * K[3] - K[0] * K[5];
+  cof[8] = K[0] * K[4] - K[1] * K[3];
+  const double detK = K[0] * cof[0] + K[1] * cof[1] + K[2] * cof[2];
+  const double idet = (detK != 0.0) ? 1.0 / detK : 0.0;
+  // K^-1 = cof^T / det (K symmetric, so cof symmetric as well)
+  double c[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) c[i] = (cof[i] * av[0] + cof[3 + i] * av[1] + cof[6 + i] * av[2]) * idet;
+  // [c]x and R [c]x
+  const double cx[9] = {0.0, -c[2], c[1], c[2], 0.0, -c[0], -c[1], c[0], 0.0};
+  // F^-T = cof(F) / J
+  double cf[9];
+  cf[0] = F[4] * F[8] - F[5] * F[7];
+  cf[1] = F[5] * F[6] - F[3] * F[8];
+  cf[2] = F[3] * F[7] - F[4] * F[6];
+  cf[3] = F[2] * F[7] - F[1] * F[8];
+  cf[4] = F[0] * F[8] - F[2] * F[6];
+  cf[5] = F[1] * F[6] - F[0] * F[7];
+  cf[6] = F[1] * F[5] - F[2] * F[4];
+  cf[7] = F[2] * F[3] - F[0] * F[5];
+  cf[8] = F[0] * F[4] - F[1] * F[3];
+  // J F^-T = cof(F); term lam (2J - 1) tr(tb) J F^-T
+  const double kv = lam * (2.0 * J - 1.0) * trtb;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double tbF = M[3 * i + j];
+      const double tbtP = tb[i] * P[j] + tb[3 + i] * P[3 + j] + tb[6 + i] * P[6 + j];  // (tb^T P)_ij
+      const double Rc = R[3 * i] * cx[j] + R[3 * i + 1] * cx[3 + j] + R[3 * i + 2] * cx[6 + j];
+      Fb[3 * i + j] += 2.0 * mu * (tbF + tbtP - Rc) + kv * cf[3 * i + j];
+    }
+}
+
+// --------------------------------------------------------------------------
+// Reverse of G2P (and of the x, F updates)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a) {
+  const int chunk = blockIdx.x;
+  const int i = a.chunk_start[chunk] + (int)threadIdx.x;
+  if (i >= a.chunk_start[chunk + 1]) return;
+  const int n = a.n;
+  const int64_t N = a.N;
+  const int64_t gbase = (int64_t)a.chunk_batch[chunk] * n * n * n;
+  const float inv_dx = (float)n, dx = 1.0f / (float)n, D = 4.0f * inv_dx * inv_dx;
+  float xp[3], Fp[9], xb[3], vb[3], Cb[9], Fbo[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    xp[k] = a.x[k * N + i];
+    xb[k] = a.ax[k * N + i];
+    vb[k] = a.av[k * N + i];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Fp[k] = a.F[k * N + i];
+    Cb[k] = a.aC[k * N + i];
+    Fbo[k] = a.aF[k * N + i];
+  }
+  int b[3];
+  float f[3];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ok &= cell_of(xp[k], n, b[k], f[k]);
+  if (!ok) return;  // skipped in the forward pass as well
+  float w[3][3], dw[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    bspline_w(f[k], w[k]);
+    bspline_dw(f[k], dw[k]);
+  }
+  // recompute C' of the forward pass
+  float vh[27][3];
+  float vs[3] = {0.f, 0.f, 0.f}, B[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  SubstepArgs ga{};
+  ga.n = n;
+  ga.bound = a.bound;
+  ga.dt = a.dt;
+  ga.g[0] = a.g[0];
+  ga.g[1] = a.g[1];
+  ga.g[2] = a.g[2];
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+    const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
+    grid_velocity(a.grid[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, ga, vh[o]);
+    const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+    const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      vs[r] += wt * vh[o][r];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) B[r][c] += wt * vh[o][r] * dp[c];
+    }
+  }
+  float Cn[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Cn[3 * r + c] = D * B[r][c];
+  // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb',  Cbt = Cb' + dt Fb' F^T
+  float Fb[9], Cbt[9], vbt[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float s = Fbo[3 * r + c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s += a.dt * Cn[3 * k + r] * Fbo[3 * k + c];
+      Fb[3 * r + c] = s;
+      float t = Cb[3 * r + c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t += a.dt * Fbo[3 * r + k] * Fp[3 * c + k];
+      Cbt[3 * r + c] = t;
+    }
+  // x' = x + dt v'
+#pragma unroll
+  for (int k = 0; k < 3; ++k) vbt[k] = vb[k] + a.dt * xb[k];
+  float xo[3] = {xb[0], xb[1], xb[2]};
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+    const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
+    const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+    const float gw[3] = {inv_dx * dw[0][ox] * w[1][oy] * w[2][oz], inv_dx * w[0][ox] * dw[1][oy] * w[2][oz],
+                         inv_dx * w[0][ox] * w[1][oy] * dw[2][oz]};
+    const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+    float cd[3];  // Cbt dpos
+#pragma unroll
+    for (int r = 0; r < 3; ++r) cd[r] = Cbt[3 * r] * dp[0] + Cbt[3 * r + 1] * dp[1] + Cbt[3 * r + 2] * dp[2];
+    float* gp = (float*)&a.vhb[gbase + ((int64_t)ix * n + iy) * n + iz];
+    float wb = 0.f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float gval = vbt[r] + D * cd[r];
+      atomicAdd(gp + r, wt * gval);
+      wb += vh[o][r] * gval;
+    }
+    // dpos = x_i - x_p: xb -= D w Cbt^T vh
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float ctv = Cbt[c] * vh[o][0] + Cbt[3 + c] * vh[o][1] + Cbt[6 + c] * vh[o][2];
+      xo[c] += wb * gw[c] - D * wt * ctv;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a.ax[k * N + i] = xo[k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) a.aF[k * N + i] = Fb[k];
+}
+
+// --------------------------------------------------------------------------
+// Reverse of the grid update and of P2G, stress and Lame parameters
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
+  const int chunk = blockIdx.x;
+  const int i = a.chunk_start[chunk] + (int)threadIdx.x;
+  if (i >= a.chunk_start[chunk + 1]) return;
+  const int n = a.n;
+  const int64_t N = a.N;
+  const int64_t gbase = (int64_t)a.chunk_batch[chunk] * n * n * n;
+  const float inv_dx = (float)n, dx = 1.0f / (float)n, D = 4.0f * inv_dx * inv_dx;
+  float xp[3], vp[3], Cp[9], xb[3];
+  double Fd[9], Fb[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    xp[k] = a.x[k * N + i];
+    vp[k] = a.v[k * N + i];
+    xb[k] = a.ax[k * N + i];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Cp[k] = a.C[k * N + i];
+    Fd[k] = (double)a.F[k * N + i];
+    Fb[k] = (double)a.aF[k * N + i];
+  }
+  const float4 prm = a.prm[i];
+  const float mass = prm.x;
+  const double mu = (double)prm.z, lam = (double)prm.w;
+  int b[3];
+  float f[3];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ok &= cell_of(xp[k], n, b[k], f[k]);
+  if (!ok) return;  // skipped in the forward pass: the adjoint passes through
+  float vb[3] = {0.f, 0.f, 0.f}, Cb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  {
+    double R[9], tau[9];
+    polar_rotation(Fd, R);
+    tau_fixed_corotated_R(Fd, R, mu, lam, tau);
+    const float ks = D * a.dt * prm.y;
+    float A[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = mass * Cp[k] - ks * (float)tau[k];
+    float w[3][3], dw[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      bspline_w(f[k], w[k]);
+      bspline_dw(f[k], dw[k]);
+    }
+    float Ab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+      const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
+      const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
+      const float4 gm = a.grid[node];
+      if (!grid_active(gm.w, ix, iy, iz, n, a.bound)) continue;
+      const float4 gb = a.vhb[node];
+      const float im = 1.0f / gm.w;
+      const float mvb[3] = {gb.x * im, gb.y * im, gb.z * im};
+      const float mb = -(gb.x * gm.x + gb.y * gm.y + gb.z * gm.z) * im * im;
+      const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+      const float gw[3] = {inv_dx * dw[0][ox] * w[1][oy] * w[2][oz], inv_dx * w[0][ox] * dw[1][oy] * w[2][oz],
+                           inv_dx * w[0][ox] * w[1][oy] * dw[2][oz]};
+      const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+      float wb = mb * mass;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float mom = mass * vp[r] + A[3 * r] * dp[0] + A[3 * r + 1] * dp[1] + A[3 * r + 2] * dp[2];
+        wb += mvb[r] * mom;
+        vb[r] += mass * wt * mvb[r];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Ab[3 * r + c] += wt * mvb[r] * dp[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float atm = A[c] * mvb[0] + A[3 + c] * mvb[1] + A[6 + c] * mvb[2];
+        xb[c] += wb * gw[c] - wt * atm;
+      }
+    }
+    // A = m C - ks tau
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Cb[k] = mass * Ab[k];
+    double tb[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tb[k] = -(double)ks * (double)Ab[k];
+    double mub = 0.0, lamb = 0.0;
+    tau_fcr_adjoint(Fd, R, mu, lam, tb, Fb, mub, lamb);
+    const double E = exp((double)a.lnE[i]);
+    const double nv = (double)a.nu[i];
+    const double den = (1.0 + nv) * (1.0 - 2.0 * nv);
+    a.g_lnE[i] += (float)(mub * mu + lamb * lam);
+    a.g_nu[i] += (float)(-mub * mu / (1.0 + nv) + lamb * E * (1.0 + 2.0 * nv * nv) / (den * den));
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a.ax[k * N + i] = xb[k];
+    a.av[k * N + i] = vb[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    a.aC[k * N + i] = Cb[k];
+    a.aF[k * N + i] = (float)Fb[k];
+  }
+}
+
+// Gather `planes` planes by perm (out[c][j] = in[c][perm[j]]); NULL in -> zeros.
+__global__ void k_gather_or_zero(float* out, const float* in, const int* perm, int planes, int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int64_t s = perm[j];
+  for (int c = 0; c < planes; ++c) out[c * N + j] = in ? in[c * N + s] : 0.0f;
+}
+
+// out[c][pid[j]] += in[c][j]
+__global__ void k_scatter_add(float* out, const float* in, const int* pid, int planes, int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int64_t d = pid[j];
+  for (int c = 0; c < planes; ++c) out[c * N + d] += in[c * N + j];
+}
+
+// log E and nu of each sorted slot
+__global__ void k_gather_lnE_nu(float* lnE, float* nu, const float* log_E_in, const float* nu_in, const int* perm,
+                                int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int s = perm[j];
+  lnE[j] = log_E_in[s];
+  nu[j] = nu_in[s];
+}
+
+// plain copy of `count` floats
+__global__ void k_copy_f32(float* out, const float* in, int64_t count) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < count) out[j] = in[j];
+}
+
+}  // namespace fmpm

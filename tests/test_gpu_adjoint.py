@@ -1,0 +1,153 @@
+"""Hand-written HIP adjoint (mpm_backward) vs the FP64 oracle's autograd
+adjoint, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mpm_oracle as O
+from paper_2602_01723_amd import binding as B
+from paper_2602_01723_amd import scenes
+from tests.parity import rel_err
+
+pytestmark = pytest.mark.gpu
+
+FCR = [dict(elastic=0, plastic=0, yield_stress=0.0, friction_deg=0.0)]
+
+
+def elastic_case(seed, N=1500, n=32, dt=2e-4, spread=0.3):
+    rng = np.random.default_rng(seed)
+    x, v, C, F = scenes.random_state(rng, N, n, spread=spread, vel=0.5, cgrad=5.0, fdev=0.03)
+    mass = (rng.uniform(0.5, 2.0, N) * 1e-5).astype(np.float32)
+    vol0 = (mass / 1000.0).astype(np.float32)
+    log_E = np.log(rng.uniform(1e4, 1e5, N)).astype(np.float32)
+    nu = rng.uniform(0.2, 0.4, N).astype(np.float32)
+    mat = np.zeros(N, np.int32)
+    return dict(x=x, v=v, C=C, F=F, mass=mass, vol0=vol0, log_E=log_E, nu=nu, mat_id=mat, n=n, dt=dt)
+
+
+def gpu_adjoint(d, steps, K, cot, mats=FCR):
+    N = len(d["mass"])
+    ctx = B.mpm_init(d["n"], d["dt"], mats, N)
+    p = B.Particles.from_arrays(d["x"], d["v"], d["C"], d["F"], d["mass"], d["vol0"], d["log_E"], d["nu"],
+                                d["mat_id"])
+    nbytes = B.mpm_tape_size(ctx, steps, K)
+    tape = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device="cuda")
+    B.mpm_step_n(ctx, p, steps, tape=tape, checkpoint_every=K)
+    final = p.state_numpy()
+    dev = lambda a, c: torch.tensor(np.ascontiguousarray(a.reshape(N, c).T)).cuda()
+    g = [dev(cot[0], 3), dev(cot[1], 3), dev(cot[2], 9), dev(cot[3], 9)]
+    out = {k: torch.empty(N, device="cuda") for k in ("g_log_E", "g_nu")}
+    s0 = {k: torch.empty(c, N, device="cuda") for k, c in (("g_x0", 3), ("g_v0", 3), ("g_C0", 9), ("g_F0", 9))}
+    B.mpm_backward(ctx, p, tape, steps, *g, out["g_log_E"], out["g_nu"], s0["g_x0"], s0["g_v0"], s0["g_C0"],
+                   s0["g_F0"])
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res.update({k: v.cpu().numpy().T.reshape(N, -1) for k, v in s0.items()})
+    return res, final, ctx
+
+
+def oracle_adjoint(d, steps, cot):
+    params = O.Params(d["mass"], d["vol0"], d["log_E"], d["nu"], d["mat_id"], FCR, d["n"], d["dt"])
+    s0 = tuple(torch.as_tensor(np.asarray(a, np.float64)) for a in (d["x"], d["v"], d["C"], d["F"]))
+    cots = tuple(torch.as_tensor(np.asarray(c, np.float64)) for c in cot)
+    return O.adjoint(s0, params, steps, cots, want_state0=True)
+
+
+def random_cotangents(rng, N):
+    return (rng.normal(0, 1, (N, 3)).astype(np.float32), rng.normal(0, 1e-2, (N, 3)).astype(np.float32),
+            rng.normal(0, 1e-4, (N, 3, 3)).astype(np.float32), rng.normal(0, 1e-2, (N, 3, 3)).astype(np.float32))
+
+
+@pytest.mark.parametrize("steps,K", [(1, 1), (10, 4), (12, 12)])
+def test_adjoint_matches_oracle(steps, K):
+    d = elastic_case(1)
+    N = len(d["mass"])
+    cot = random_cotangents(np.random.default_rng(2), N)
+    res, final, _ = gpu_adjoint(d, steps, K, cot)
+    ref = oracle_adjoint(d, steps, cot)
+    errs = {}
+    for k, rk in (("g_log_E", "g_logE"), ("g_nu", "g_nu"), ("g_x0", "g_x0"), ("g_v0", "g_v0"),
+                  ("g_C0", "g_C0"), ("g_F0", "g_F0")):
+        r = ref[rk].numpy().reshape(N, -1)
+        errs[k] = rel_err(res[k].reshape(N, -1), r, 0.0)
+    # totals over particles (the per-instance gradient a material fit uses)
+    errs["sum_g_log_E"] = abs(res["g_log_E"].sum() - ref["g_logE"].sum().item()) / abs(ref["g_logE"].sum().item())
+    print(steps, K, errs, flush=True)
+    bad = {k: e for k, e in errs.items() if not e <= 2e-3}
+    assert not bad, errs
+
+
+def test_adjoint_independent_of_checkpoint_interval():
+    d = elastic_case(3, N=800)
+    cot = random_cotangents(np.random.default_rng(4), 800)
+    a, _, _ = gpu_adjoint(d, 9, 1, cot)
+    b, _, _ = gpu_adjoint(d, 9, 9, cot)
+    for k in ("g_log_E", "g_nu", "g_x0", "g_F0"):
+        assert rel_err(a[k], b[k], 0.0) < 1e-4, k
+
+
+def test_backward_errors():
+    d = elastic_case(5, N=100)
+    ctx = B.mpm_init(d["n"], d["dt"], FCR, 100)
+    p = B.Particles.from_arrays(d["x"], d["v"], d["C"], d["F"], d["mass"], d["vol0"], d["log_E"], d["nu"],
+                                d["mat_id"])
+    g = torch.zeros(100, device="cuda")
+    tape = torch.empty(B.mpm_tape_size(ctx, 4, 2) // 4 + 64, device="cuda")
+    with pytest.raises(B.MPMError) as e:  # no taped forward yet
+        B.mpm_backward(ctx, p, tape, 4, g_log_E=g, g_nu=g)
+    assert e.value.status == B.MPM_ESTATE
+    B.mpm_step_n(ctx, p, 4, tape=tape, checkpoint_every=2)
+    with pytest.raises(B.MPMError) as e:  # length differs from the taped run
+        B.mpm_backward(ctx, p, tape, 3, g_log_E=g, g_nu=g)
+    assert e.value.status == B.MPM_ESTATE
+    plastic = [dict(elastic=1, plastic=1, yield_stress=1e3, friction_deg=0.0)]
+    ctx2 = B.mpm_init(d["n"], d["dt"], plastic, 100)
+    with pytest.raises(B.MPMError) as e:
+        B.mpm_step_n(ctx2, p, 2, tape=tape, checkpoint_every=1)
+    assert e.value.status == B.MPM_EUNSUPPORTED
+
+
+def test_loss_gradient_matches_finite_differences_on_gpu():
+    """Position-MSE loss of a colliding pair against a trajectory with other
+    (E, nu): d loss / d log E of each instance by the adjoint vs central
+    differences of the GPU forward (h = 1e-2 in log E; the pair collides
+    after about 80 substeps)."""
+    sc = scenes.make_scene("colliding_pair", n_total=6000, grid_res=32, n_substeps=100, dt=2e-4,
+                           E=(2e5, 5e4), nu=(0.25, 0.35))
+    steps, K = 100, 20
+    N = sc.n
+    ctx = B.init_from_scene(sc)
+    tgt = B.Particles.from_scene(sc)
+    B.mpm_step_n(ctx, tgt, steps)
+    x_target = tgt.x.clone()
+    base_logE = np.full(N, math.log(1e5), np.float32)
+    base_nu = np.full(N, 0.3, np.float32)
+
+    def loss_and_grad(logE, nu, want_grad):
+        p = B.Particles.from_arrays(sc.x, sc.v, sc.C, sc.F, sc.mass, sc.vol0, logE, nu, sc.mat_id)
+        tape = None
+        if want_grad:
+            tape = torch.empty(B.mpm_tape_size(ctx, steps, K) // 4 + 64, device="cuda")
+        B.mpm_step_n(ctx, p, steps, tape=tape, checkpoint_every=K if want_grad else 0)
+        diff = (p.x - x_target).double()
+        L = float((diff ** 2).mean())
+        if not want_grad:
+            return L, None
+        gx = (2.0 * diff / (3 * N)).float().contiguous()
+        gl = torch.empty(N, device="cuda")
+        gn = torch.empty(N, device="cuda")
+        B.mpm_backward(ctx, p, tape, steps, g_x=gx, g_log_E=gl, g_nu=gn)
+        return L, (gl.cpu().numpy(), gn.cpu().numpy())
+
+    L0, (gl, gn) = loss_and_grad(base_logE, base_nu, True)
+    h = 1e-2
+    for inst in (0, 1):
+        sel = sc.inst_id == inst
+        lp, _ = loss_and_grad(base_logE + h * sel, base_nu, False)
+        lm, _ = loss_and_grad(base_logE - h * sel, base_nu, False)
+        fd = (lp - lm) / (2 * h)
+        an = float(gl[sel].sum())
+        print("instance", inst, "adjoint", an, "fd", fd, flush=True)
+        assert abs(an - fd) <= 2e-2 * abs(fd) + 1e-12
