@@ -163,11 +163,50 @@ int mpm_export_covariance(mpm_ctx ctx, const float* F, const float* cov0, float*
 /* Synchronises the context's last stream and reads the device counters. */
 int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out);
 
-/* Launch tuning (set by the autotuner; 0 keeps the current value):
- * chunk = particles per work item, cut from one 4^3-cell block (64..8192,
- * multiple of 64; applied at the next sort),
- * sort_every = substeps between re-sorts, tile_cap = LDS tile nodes. */
-int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_cap);
+/* Launch tuning.  chunk = particles per work item, cut from one 4^3-cell
+ * block (64..8192, multiple of 64; applied at the next sort); sort_every =
+ * substeps between re-sorts; tile_cap = LDS tile nodes (27..1331);
+ * workgroups = width of the persistent substep kernel.  In mpm_set_tuning a
+ * zero field keeps the current value; ms_per_substep is an output of
+ * mpm_autotune only. */
+typedef struct {
+  int32_t chunk;
+  int32_t sort_every;
+  int32_t tile_cap;
+  int32_t workgroups;
+  double ms_per_substep;
+} mpm_tuning;
+
+int mpm_set_tuning(mpm_ctx ctx, const mpm_tuning* t);
+int mpm_get_tuning(mpm_ctx ctx, mpm_tuning* t);
+
+/* Autotuner: times trial runs of trial_steps (>= 2) substeps of the given
+ * particles for candidate settings (coordinate descent over chunk, then
+ * workgroups, then sort_every) with HIP events on `stream`, applies the
+ * fastest and returns it in *best.  Synchronous.  The trial runs work on the
+ * context's internal copies: the caller's arrays are only read. */
+int mpm_autotune(mpm_ctx ctx, const mpm_particles* p, int32_t trial_steps, void* stream, mpm_tuning* best);
+
+/* Graph capture.  Between mpm_graph_begin and mpm_graph_end every call on
+ * this context that takes `stream` (which must be the same non-null stream)
+ * is recorded instead of run; mpm_graph_end returns an executable hipGraph
+ * that mpm_graph_launch replays on the same buffers (the context and every
+ * buffer must outlive it).  Used to run a whole evaluation of a batch of
+ * candidates (one context with n_batch scenes): mpm_step_n with a tape,
+ * mpm_position_loss_grad, mpm_backward, in one launch.  Host-side argument
+ * checks still run at capture time. */
+typedef struct mpm_graph_s* mpm_graph;
+int mpm_graph_begin(mpm_ctx ctx, void* stream);
+int mpm_graph_end(mpm_ctx ctx, void* stream, mpm_graph* out);
+int mpm_graph_launch(mpm_graph g, void* stream);
+int mpm_graph_destroy(mpm_graph g);
+
+/* Cotangent of the position loss L = sum_p weight_p |x_p - x*_p|^2 used by
+ * the differentiation workloads (weight_p = 1 / (3 N_scene) gives the mean
+ * squared error per scene): g_x = 2 weight (x - x*), all [3][N] / [N]
+ * device arrays. */
+int mpm_position_loss_grad(mpm_ctx ctx, const float* x, const float* x_target, const float* weight, float* g_x,
+                           void* stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, by class: 0 fused G2P+P2G substep kernel, 1 P2G-only kernel,

@@ -23,7 +23,9 @@ MPM_ABI_VERSION = 1
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_tape_size",
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
-            "mpm_set_tuning", "mpm_profile", "mpm_profile_read", "mpm_destroy")
+            "mpm_set_tuning", "mpm_get_tuning", "mpm_autotune", "mpm_graph_begin", "mpm_graph_end",
+            "mpm_graph_launch", "mpm_graph_destroy", "mpm_position_loss_grad", "mpm_profile", "mpm_profile_read",
+            "mpm_destroy")
 PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io", "unused",
                    "other_fill")
 
@@ -47,6 +49,14 @@ class mpm_material(ctypes.Structure):
 
 class mpm_particles(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("x", "v", "C", "F", "mass", "vol0", "log_E", "nu", "mat_id")]
+
+
+class mpm_tuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("tile_cap", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("ms_per_substep", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class mpm_diag(ctypes.Structure):
@@ -79,7 +89,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_grid_state": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mpm_export_covariance": (ctypes.c_int, [vp, vp, vp, vp, i64, vp]),
         "mpm_get_diagnostics": (ctypes.c_int, [vp, ctypes.POINTER(mpm_diag)]),
-        "mpm_set_tuning": (ctypes.c_int, [vp, i32, i32, i32]),
+        "mpm_set_tuning": (ctypes.c_int, [vp, ctypes.POINTER(mpm_tuning)]),
+        "mpm_get_tuning": (ctypes.c_int, [vp, ctypes.POINTER(mpm_tuning)]),
+        "mpm_autotune": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), i32, vp, ctypes.POINTER(mpm_tuning)]),
+        "mpm_graph_begin": (ctypes.c_int, [vp, vp]),
+        "mpm_graph_end": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp)]),
+        "mpm_position_loss_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "mpm_graph_launch": (ctypes.c_int, [vp, vp]),
+        "mpm_graph_destroy": (ctypes.c_int, [vp]),
         "mpm_profile": (ctypes.c_int, [vp, i32]),
         "mpm_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
         "mpm_destroy": (ctypes.c_int, [vp]),
@@ -266,8 +283,65 @@ def mpm_get_diagnostics(ctx: Context) -> dict:
     return out
 
 
-def mpm_set_tuning(ctx: Context, chunk=0, sort_every=0, tile_cap=0):
-    _check(ctx, load().mpm_set_tuning(ctx.handle, int(chunk), int(sort_every), int(tile_cap)), "mpm_set_tuning")
+def mpm_set_tuning(ctx: Context, chunk=0, sort_every=0, tile_cap=0, workgroups=0):
+    t = mpm_tuning(int(chunk), int(sort_every), int(tile_cap), int(workgroups), 0.0)
+    _check(ctx, load().mpm_set_tuning(ctx.handle, ctypes.byref(t)), "mpm_set_tuning")
+
+
+def mpm_get_tuning(ctx: Context) -> dict:
+    t = mpm_tuning()
+    _check(ctx, load().mpm_get_tuning(ctx.handle, ctypes.byref(t)), "mpm_get_tuning")
+    return t.as_dict()
+
+
+def mpm_autotune(ctx: Context, p: Particles, trial_steps: int = 8, stream=None) -> dict:
+    """Run the library's autotuner on these particles (caller arrays untouched)."""
+    s = p.as_struct()
+    t = mpm_tuning()
+    _check(ctx, load().mpm_autotune(ctx.handle, ctypes.byref(s), int(trial_steps), _stream(stream), ctypes.byref(t)),
+           "mpm_autotune")
+    return t.as_dict()
+
+
+class Graph:
+    """A captured evaluation (forward, optionally backward); see mpm_graph_capture."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep  # buffers and context the graph refers to
+
+    def launch(self, stream=None):
+        rc = load().mpm_graph_launch(self.handle, _stream(stream))
+        if rc != MPM_OK:
+            raise MPMError(rc, "mpm_graph_launch failed")
+
+    def close(self):
+        if self.handle:
+            load().mpm_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpm_graph_begin(ctx: Context, stream):
+    """Start recording this context's calls on `stream` (a torch.cuda.Stream)."""
+    _check(ctx, load().mpm_graph_begin(ctx.handle, _stream(stream)), "mpm_graph_begin")
+
+
+def mpm_graph_end(ctx: Context, stream, keep=()) -> Graph:
+    """Stop recording; `keep` lists the tensors the graph refers to (held alive)."""
+    h = ctypes.c_void_p()
+    _check(ctx, load().mpm_graph_end(ctx.handle, _stream(stream), ctypes.byref(h)), "mpm_graph_end")
+    return Graph(h, (ctx,) + tuple(keep))
+
+
+def mpm_position_loss_grad(ctx: Context, x, x_target, weight, g_x, stream=None):
+    rc = load().mpm_position_loss_grad(ctx.handle, _ptr(x), _ptr(x_target), _ptr(weight), _ptr(g_x), _stream(stream))
+    _check(ctx, rc, "mpm_position_loss_grad")
 
 
 def mpm_profile(ctx: Context, enable: bool = True):

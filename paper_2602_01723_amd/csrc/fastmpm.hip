@@ -60,6 +60,8 @@ struct mpm_context {
   double prof_ms[MPM_PROFILE_CLASSES] = {0};
   int64_t prof_cnt[MPM_PROFILE_CLASSES] = {0};
 
+  bool capturing = false;  // between mpm_graph_begin and mpm_graph_end
+  bool prof_saved = false;
   // the last taped forward (mpm_step_n with a tape)
   const void* tape_ptr = nullptr;
   int32_t tape_n = -1;
@@ -308,7 +310,7 @@ int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hip
   a.grid_out = gout;
   a.write_vc = write_vc;
   ProfScope ps(c, s, MODE == fmpm::kFused ? 0 : (MODE == fmpm::kP2G ? 1 : 2));
-  fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);
+  fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);  // persistent: items from the queue
   LAUNCH_CHECK(c, "k_substep");
   return MPM_OK;
 }
@@ -452,11 +454,14 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   return MPM_OK;
 }
 
-int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, int32_t checkpoint_every,
-               void* stream) {
-  if (!ctx) return MPM_EINVAL;
-  int rc = check_particles(ctx, p);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace {
+// The substep loop of mpm_step_n; with write_back = false the caller's
+// arrays are only read (the autotuner times trial runs this way).
+int run_steps(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, int32_t checkpoint_every,
+              void* stream, bool write_back) {
+  int rc = MPM_OK;
   if (n_steps < 0) return fail(ctx, MPM_EINVAL, "n_steps < 0");
   if (tape && checkpoint_every < 1) return fail(ctx, MPM_EINVAL, "checkpoint_every < 1 with a tape");
   if (tape && !adjoint_supported(ctx))
@@ -517,7 +522,18 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape,
   }
   ctx->last_grid = cur;
   ctx->substeps += n_steps;
-  return scatter_to_caller(ctx, p, s);
+  return write_back ? scatter_to_caller(ctx, p, s) : MPM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, int32_t checkpoint_every,
+               void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  int rc = check_particles(ctx, p);
+  if (rc) return rc;
+  return run_steps(ctx, p, n_steps, tape, checkpoint_every, stream, true);
 }
 
 int mpm_substep(mpm_ctx ctx, const mpm_particles* p, void* stream) {
@@ -688,14 +704,169 @@ int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out) {
   return (h[0] || h[1]) ? MPM_EUNSTABLE : MPM_OK;
 }
 
-int mpm_set_tuning(mpm_ctx ctx, int32_t chunk, int32_t sort_every, int32_t tile_cap) {
+int mpm_set_tuning(mpm_ctx ctx, const mpm_tuning* t) {
+  if (!ctx || !t) return MPM_EINVAL;
+  if (t->chunk != 0 && (t->chunk < 64 || t->chunk > 8192 || t->chunk % 64 != 0)) return fail(ctx, MPM_EINVAL, "chunk");
+  if (t->sort_every < 0) return fail(ctx, MPM_EINVAL, "sort_every < 0");
+  if (t->tile_cap != 0 && (t->tile_cap < 27 || t->tile_cap > fmpm::kTileCapMax)) return fail(ctx, MPM_EINVAL, "tile_cap");
+  if (t->workgroups != 0 && (t->workgroups < 1 || t->workgroups > 65536)) return fail(ctx, MPM_EINVAL, "workgroups");
+  if (t->sort_every > 0) ctx->sort_every = t->sort_every;
+  if (t->tile_cap > 0) ctx->tile_cap = t->tile_cap;
+  if (t->chunk > 0) ctx->item = t->chunk;  // takes effect at the next sort
+  if (t->workgroups > 0) ctx->grid_blocks = t->workgroups;
+  return MPM_OK;
+}
+
+int mpm_get_tuning(mpm_ctx ctx, mpm_tuning* t) {
+  if (!ctx || !t) return MPM_EINVAL;
+  t->chunk = ctx->item;
+  t->sort_every = ctx->sort_every;
+  t->tile_cap = ctx->tile_cap;
+  t->workgroups = ctx->grid_blocks;
+  t->ms_per_substep = 0.0;
+  return MPM_OK;
+}
+
+int mpm_autotune(mpm_ctx ctx, const mpm_particles* p, int32_t trial_steps, void* stream, mpm_tuning* best) {
+  if (!ctx || !best) return MPM_EINVAL;
+  int rc = check_particles(ctx, p);
+  if (rc) return rc;
+  if (trial_steps < 2) return fail(ctx, MPM_EINVAL, "trial_steps < 2");
+  hipStream_t s = (hipStream_t)stream;
+  mpm_tuning cur{};
+  mpm_get_tuning(ctx, &cur);
+  if (ctx->N == 0) {
+    *best = cur;
+    return MPM_OK;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  const bool prof = ctx->prof_on;
+  ctx->prof_on = false;
+  const int64_t saved_substeps = ctx->substeps;
+  // time one setting: a warm-up run, then the timed run (both on internal copies)
+  auto trial = [&](const mpm_tuning& t, double* ms) -> int {
+    int r = mpm_set_tuning(ctx, &t);
+    r = r ? r : run_steps(ctx, p, trial_steps, nullptr, 0, stream, false);
+    if (r) return r;
+    if (hipEventRecord(e0, s) != hipSuccess) return MPM_EDEVICE;
+    r = run_steps(ctx, p, trial_steps, nullptr, 0, stream, false);
+    if (r) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return MPM_EDEVICE;
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return MPM_EDEVICE;
+    *ms = f / trial_steps;
+    return MPM_OK;
+  };
+  mpm_tuning bt = cur;
+  double bms = 0.0;
+  rc = trial(bt, &bms);
+  // coordinate descent: work-item size, then workgroups, then sort interval
+  const int chunks[] = {256, 512, 1024, 2048};
+  const int wgs[] = {256, 512, 768, 1024, 2048};
+  const int sorts[] = {2, 4, 8, 16, 32, 64};
+  for (int c : chunks) {
+    if (rc) break;
+    mpm_tuning t = bt;
+    t.chunk = c;
+    double ms;
+    rc = trial(t, &ms);
+    if (!rc && ms < bms) { bt = t; bms = ms; }
+  }
+  for (int w : wgs) {
+    if (rc) break;
+    mpm_tuning t = bt;
+    t.workgroups = w;
+    double ms;
+    rc = trial(t, &ms);
+    if (!rc && ms < bms) { bt = t; bms = ms; }
+  }
+  for (int so : sorts) {
+    if (rc) break;
+    if (so > trial_steps) break;
+    mpm_tuning t = bt;
+    t.sort_every = so;
+    double ms;
+    rc = trial(t, &ms);
+    if (!rc && ms < bms) { bt = t; bms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->prof_on = prof;
+  ctx->substeps = saved_substeps;
+  if (rc) {
+    mpm_set_tuning(ctx, &cur);
+    return rc;
+  }
+  bt.ms_per_substep = bms;
+  mpm_set_tuning(ctx, &bt);
+  *best = bt;
+  return MPM_OK;
+}
+
+struct mpm_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int mpm_graph_begin(mpm_ctx ctx, void* stream) {
   if (!ctx) return MPM_EINVAL;
-  if (chunk != 0 && (chunk < 64 || chunk > 8192 || chunk % 64 != 0)) return fail(ctx, MPM_EINVAL, "chunk");
-  if (sort_every < 0) return fail(ctx, MPM_EINVAL, "sort_every < 0");
-  if (tile_cap != 0 && (tile_cap < 27 || tile_cap > fmpm::kTileCapMax)) return fail(ctx, MPM_EINVAL, "tile_cap");
-  if (sort_every > 0) ctx->sort_every = sort_every;
-  if (tile_cap > 0) ctx->tile_cap = tile_cap;
-  if (chunk > 0) ctx->item = chunk;  // takes effect at the next sort
+  if (!stream) return fail(ctx, MPM_EINVAL, "capture needs a non-null stream");
+  if (ctx->capturing) return fail(ctx, MPM_ESTATE, "already capturing");
+  ctx->prof_saved = ctx->prof_on;
+  ctx->prof_on = false;  // no event records inside a graph
+  HIP_TRY(ctx, hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;
+  return MPM_OK;
+}
+
+int mpm_graph_end(mpm_ctx ctx, void* stream, mpm_graph* out) {
+  if (!ctx || !out) return MPM_EINVAL;
+  *out = nullptr;
+  if (!ctx->capturing) return fail(ctx, MPM_ESTATE, "not capturing");
+  ctx->capturing = false;
+  ctx->prof_on = ctx->prof_saved;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture((hipStream_t)stream, &graph);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(ctx, "hipStreamEndCapture", e);
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(ctx, "hipGraphInstantiate", e);
+  }
+  mpm_graph g = new mpm_graph_s();
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return MPM_OK;
+}
+
+int mpm_position_loss_grad(mpm_ctx ctx, const float* x, const float* x_target, const float* weight, float* g_x,
+                           void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (ctx->N == 0) return MPM_OK;
+  if (!x || !x_target || !weight || !g_x) return fail(ctx, MPM_EINVAL, "NULL array");
+  fmpm::k_position_loss_grad<<<blocks_for(ctx->N, 256), 256, 0, (hipStream_t)stream>>>(x, x_target, weight, g_x,
+                                                                                       ctx->N);
+  LAUNCH_CHECK(ctx, "k_position_loss_grad");
+  return MPM_OK;
+}
+
+int mpm_graph_launch(mpm_graph g, void* stream) {
+  if (!g) return MPM_EINVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? MPM_OK : MPM_EDEVICE;
+}
+
+int mpm_graph_destroy(mpm_graph g) {
+  if (!g) return MPM_EINVAL;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
   return MPM_OK;
 }
 

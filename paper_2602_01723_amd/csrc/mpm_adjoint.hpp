@@ -412,6 +412,15 @@ __global__ void k_gather_lnE_nu(float* lnE, float* nu, const float* log_E_in, co
   nu[j] = nu_in[s];
 }
 
+// cotangent of L = sum_p w_p |x_p - x*_p|^2: g_x = 2 w_p (x_p - x*_p)
+__global__ void k_position_loss_grad(const float* x, const float* xt, const float* w, float* gx, int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const float s = 2.0f * w[j];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gx[c * N + j] = s * (x[c * N + j] - xt[c * N + j]);
+}
+
 // plain copy of `count` floats
 __global__ void k_copy_f32(float* out, const float* in, int64_t count) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

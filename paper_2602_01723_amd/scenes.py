@@ -347,9 +347,11 @@ def colliding_pair(seed=3, n_total=200_000, grid_res=64, dt=1e-4, n_substeps=200
 def candidate_batch(seed=4, n_batch=64, grid_res=48, dt=1e-4, n_substeps=100,
                     n_min=10_000, n_max=100_000) -> Scene:
     """n_batch independent candidates, each a single fixed-corotated
-    ellipsoid (half shell, half interior) on its own grid, dropped at
-    1 m/s onto the floor; per-candidate E (log-uniform 1e4..1e6) and
-    nu (uniform 0.2..0.4), and hidden target parameters drawn alike."""
+    ellipsoid (half shell, half interior) on its own grid, falling at
+    1.5 m/s with its lowest point 0.1 cell above the sticky floor band, so
+    it lands within the first substeps and its deformation depends on E;
+    per-candidate E (log-uniform 1e4..1e6) and nu (uniform 0.2..0.4), and
+    hidden target parameters drawn alike."""
     rng = np.random.default_rng(seed)
     dx = 1.0 / grid_res
     parts = []
@@ -360,7 +362,7 @@ def candidate_batch(seed=4, n_batch=64, grid_res=48, dt=1e-4, n_substeps=100,
         axes = rng.uniform(0.08, 0.2, 3)
         rot = haar_rotation(rng)
         half = np.sqrt(((rot * axes[None, :]) ** 2).sum(1))
-        centre = (0.5, 4 * dx + half[1], 0.5)
+        centre = (0.5, 3.6 * dx + half[1], 0.5)
         ns = n_c // 2
         pts, sh = ellipsoid_instance(rng, centre, axes, rot, ns, n_c - ns)
         E = math.exp(rng.uniform(math.log(1e4), math.log(1e6)))
@@ -368,7 +370,7 @@ def candidate_batch(seed=4, n_batch=64, grid_res=48, dt=1e-4, n_substeps=100,
         tgt_logE.append(rng.uniform(math.log(1e4), math.log(1e6)))
         tgt_nu.append(rng.uniform(0.2, 0.4))
         parts.append(dict(pts=pts, is_shell=sh, vol=_ellipsoid_volume(axes) / len(pts),
-                          log_E=math.log(E), nu=nu, mat=0, inst=b, v0=(0.0, -1.0, 0.0)))
+                          log_E=math.log(E), nu=nu, mat=0, inst=b, v0=(0.0, -1.5, 0.0)))
         offsets.append(offsets[-1] + n_c)
     sc = _finish("candidate_batch", grid_res, dt, n_substeps, [_material(ELASTIC_FCR)], parts, rng,
                  offsets=offsets)
