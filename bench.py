@@ -33,8 +33,100 @@ BYTES_PER_PARTICLE = 116
 BYTES_PER_ACTIVE_NODE = 32
 
 
+KERNEL_SOURCES = ("paper_2602_01723_amd/csrc/mpm_kernels.hpp", "paper_2602_01723_amd/csrc/mpm_math.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_substep_large_scene_traffic.json")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_particles):
+    """HBM bytes per fused-kernel launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for
+    a plain copy of known size), or None if the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("particles") != n_particles:
+        return None
+    f_scale = t["copy_bytes"] / (t["copy_fetch_kib"] * 1024.0)
+    w_scale = t["copy_bytes"] / (t["copy_write_kib"] * 1024.0)
+    return t["fused_fetch_kib"] * 1024.0 * f_scale + t["fused_write_kib"] * 1024.0 * w_scale
+
+
+def copy_probe():
+    """A plain 256 MiB device copy, the calibration point of the HBM counters."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
+    """Forward + adjoint of n_batch candidates (own 48^3 grid each): one
+    hipGraph for the whole batch against per-candidate eager solves."""
+    import numpy as np
+    import torch
+
+    from paper_2602_01723_amd import batch as BT
+    from paper_2602_01723_amd import scenes
+    sc = scenes.make_scene("candidate_batch", n_batch=n_batch, n_substeps=steps)
+    tl = BT.per_particle(sc.extras["target_log_E"], sc.batch_offsets)
+    tn = BT.per_particle(sc.extras["target_nu"], sc.batch_offsets)
+    xt = BT.target_positions(sc, steps, tl, tn)
+    ev = BT.Evaluation(sc, steps, K, xt)
+    ev.run_eager()
+    torch.cuda.synchronize()
+    ev.capture()
+    ev.run_graph()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ev.run_graph()
+        torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    gl_b, _ = ev.gradients()
+    log(f"  batched: {t_batched * 1e3:.1f} ms per evaluation of {n_batch} candidates")
+    plain = BT.plain_evaluations(sc, steps, K, xt)
+    plain[0].run_eager()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pe in plain:
+        pe.run_eager()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"  plain: {t_plain * 1e3:.1f} ms for {n_batch} sequential solves")
+    diffs = []
+    for b, pe in enumerate(plain):
+        lo, hi = sc.batch_offsets[b], sc.batch_offsets[b + 1]
+        g1, _ = pe.gradients()
+        sb, sp = float(gl_b[lo:hi].sum()), float(g1.sum())
+        diffs.append(abs(sb - sp) / max(abs(sp), 1e-30))
+    return {
+        "workload": f"{n_batch} candidates, one fixed-corotated ellipsoid each on its own {sc.grid_res}^3 grid, "
+                    f"{int(np.diff(sc.batch_offsets).min())}-{int(np.diff(sc.batch_offsets).max())} particles, "
+                    f"{steps} substeps forward + adjoint, checkpoint every {K}",
+        "particles": sc.n, "substeps": steps,
+        "batched_grads_per_s": n_batch / t_batched, "plain_grads_per_s": n_batch / t_plain,
+        "speedup": t_plain / t_batched, "batched_ms": t_batched * 1e3, "plain_ms": t_plain * 1e3,
+        "fwd_bwd_particle_substeps_per_s": sc.n * steps / t_batched,
+        "max_rel_diff_candidate_grad_logE": max(diffs), "median_rel_diff_candidate_grad_logE": float(np.median(diffs)),
+    }
 
 
 def cpu_baseline(sc, n_sub=2):
@@ -62,6 +154,7 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--item", type=int, default=0, help="particles per work item (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched vs plain fwd+bwd comparison")
     ap.add_argument("--n-total", type=int, default=2_000_000)
     args = ap.parse_args()
 
@@ -78,6 +171,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    copy_probe()
     log("generating workload ...")
     t = time.perf_counter()
     sc = scenes.make_scene("large_scene", n_total=args.n_total)
@@ -116,13 +210,22 @@ def main():
     fused_avg_s = fused_ms / max(fused_n, 1) / 1e3
     bytes_launch = BYTES_PER_PARTICLE * sc.n + BYTES_PER_ACTIVE_NODE * active
     achieved = bytes_launch / fused_avg_s / 1e9 if fused_n else None
+    traffic = measured_traffic(sc.n)
     roofline = dict(bound="hbm", kernel="k_substep<fused>", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None,
+                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=traffic,
                     bytes_per_launch=bytes_launch, avg_launch_us=fused_avg_s * 1e6, launches=fused_n,
                     active_nodes=active)
     breakdown = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]}
     log("  kernel time by class:", json.dumps(breakdown))
     log("  diagnostics:", diag)
+
+    del ctx, p
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batched:
+        log("batched vs plain forward + adjoint ...")
+        batched = batched_vs_plain()
+        log(f"  {batched['batched_grads_per_s']:.2f} vs {batched['plain_grads_per_s']:.2f} candidate gradients/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -153,6 +256,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_fwd_bwd": batched,
     }
     print(json.dumps(out), flush=True)
 
