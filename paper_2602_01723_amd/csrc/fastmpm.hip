@@ -629,7 +629,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       if (rc) return rc;
       fmpm::k_substep<fmpm::kP2G><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(ctx, "backward P2G");
-      rc = fill_u32(ctx, tl.vhb, 4 * ctx->nodes, s);
+      rc = fill_u32(ctx, tl.vhb, 4 * ctx->nodes, s, -1, ctx->work_counter);
       if (rc) return rc;
       fmpm::AdjArgs b{};
       b.x = st;
@@ -654,7 +654,8 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       b.bound = ctx->cfg.bound;
       b.dt = ctx->cfg.dt;
       for (int k = 0; k < 3; ++k) b.g[k] = ctx->cfg.gravity[k];
-      fmpm::k_adj_g2p<<<ctx->n_chunks, kBlock, 0, s>>>(b);
+      fmpm::AdjItems items{ctx->dchunk_start, ctx->dchunk_batch, ctx->dn_chunks, ctx->work_counter, ctx->tile_cap};
+      fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       LAUNCH_CHECK(ctx, "k_adj_g2p");
       fmpm::k_adj_p2g<<<ctx->n_chunks, kBlock, 0, s>>>(b);
       LAUNCH_CHECK(ctx, "k_adj_p2g");

@@ -165,44 +165,30 @@ __device__ __forceinline__ void tau_fcr_adjoint(const double* F, const double* R
 }
 
 // --------------------------------------------------------------------------
-// Reverse of G2P (and of the x, F updates)
+// Reverse of G2P (and of the x, F updates).  Same work items as the forward
+// substep kernel: per item the node velocities of the stencil box are read
+// into an LDS tile (grid update folded in) and the velocity adjoint
+// accumulates in an LDS f64 tile (staggered node order), flushed with one
+// global FP32 atomic per node and channel.  Items whose box exceeds the
+// tile use global memory.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a) {
-  const int chunk = blockIdx.x;
-  const int i = a.chunk_start[chunk] + (int)threadIdx.x;
-  if (i >= a.chunk_start[chunk + 1]) return;
+struct AdjItems {
+  const int* item_start;  // [n_items + 1]
+  const int* item_batch;
+  const int* n_items;
+  int* counter;           // zero at launch
+  int tile_cap;
+};
+
+__global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
+  __shared__ double ptile[3 * kTileCapMax];
+  __shared__ float gtile[3 * kTileCapMax];
+  __shared__ int red[8 * (kBlock / 64)];
+  __shared__ int item_s;
   const int n = a.n;
   const int64_t N = a.N;
-  const int64_t gbase = (int64_t)a.chunk_batch[chunk] * n * n * n;
   const float inv_dx = (float)n, dx = 1.0f / (float)n, D = 4.0f * inv_dx * inv_dx;
-  float xp[3], Fp[9], xb[3], vb[3], Cb[9], Fbo[9];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    xp[k] = a.x[k * N + i];
-    xb[k] = a.ax[k * N + i];
-    vb[k] = a.av[k * N + i];
-  }
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    Fp[k] = a.F[k * N + i];
-    Cb[k] = a.aC[k * N + i];
-    Fbo[k] = a.aF[k * N + i];
-  }
-  int b[3];
-  float f[3];
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) ok &= cell_of(xp[k], n, b[k], f[k]);
-  if (!ok) return;  // skipped in the forward pass as well
-  float w[3][3], dw[3][3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    bspline_w(f[k], w[k]);
-    bspline_dw(f[k], dw[k]);
-  }
-  // recompute C' of the forward pass
-  float vh[27][3];
-  float vs[3] = {0.f, 0.f, 0.f}, B[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  const int n_items = *it.n_items;
   SubstepArgs ga{};
   ga.n = n;
   ga.bound = a.bound;
@@ -210,74 +196,182 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a) {
   ga.g[0] = a.g[0];
   ga.g[1] = a.g[1];
   ga.g[2] = a.g[2];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = atomicAdd(it.counter, 1);
+    __syncthreads();
+    const int item = item_s;
+    if (item >= n_items) break;
+    const int start = it.item_start[item], end = it.item_start[item + 1];
+    const int64_t gbase = (int64_t)it.item_batch[item] * n * n * n;
+    int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+      int b[3];
+      float f[3];
+      bool in = true;
 #pragma unroll
-  for (int o = 0; o < 27; ++o) {
-    const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
-    const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-    grid_velocity(a.grid[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, ga, vh[o]);
-    const float wt = w[0][ox] * w[1][oy] * w[2][oz];
-    const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+      for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
+      if (in) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      vs[r] += wt * vh[o][r];
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = min(lo[k], b[k]);
+          hi[k] = max(hi[k], b[k]);
+        }
+      }
+    }
+    int box[6];
+    block_minmax(lo, hi, red, box);
+    const bool empty = box[0] > box[3];
+    const int gx = box[3] - box[0] + 3, gy = box[4] - box[1] + 3, gz = box[5] - box[2] + 3;
+    const int GT = empty ? 0 : gx * gy * gz;
+    const bool lds = !empty && GT <= it.tile_cap;
+    if (lds) {
+      for (int t = threadIdx.x; t < GT; t += kBlock) {
+        const int tk = t % gz, tq = t / gz;
+        const int tj = tq % gy, ti = tq / gy;
+        const int ix = box[0] + ti, iy = box[1] + tj, iz = box[2] + tk;
+        float vv[3];
+        grid_velocity(a.grid[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, ga, vv);
+        gtile[t] = vv[0];
+        gtile[kTileCapMax + t] = vv[1];
+        gtile[2 * kTileCapMax + t] = vv[2];
+        ptile[t] = 0.0;
+        ptile[kTileCapMax + t] = 0.0;
+        ptile[2 * kTileCapMax + t] = 0.0;
+      }
+    }
+    __syncthreads();
+    const int sz = gy * gz;
+    for (int sub = start; sub < end; sub += kBlock) {
+      const int i = sub + (int)threadIdx.x;
+      if (i >= end) break;
+      float xp[3], Fp[9], xb[3], vb[3], Cb[9], Fbo[9];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) B[r][c] += wt * vh[o][r] * dp[c];
+      for (int k = 0; k < 3; ++k) {
+        xp[k] = a.x[k * N + i];
+        xb[k] = a.ax[k * N + i];
+        vb[k] = a.av[k * N + i];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        Fp[k] = a.F[k * N + i];
+        Cb[k] = a.aC[k * N + i];
+        Fbo[k] = a.aF[k * N + i];
+      }
+      int b[3];
+      float f[3];
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ok &= cell_of(xp[k], n, b[k], f[k]);
+      if (!ok) continue;  // skipped in the forward pass: the adjoint passes through
+      float w[3][3], dw[3][3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        bspline_w(f[k], w[k]);
+        bspline_dw(f[k], dw[k]);
+      }
+      const int a0 = ((b[0] - box[0]) * gy + (b[1] - box[1])) * gz + (b[2] - box[2]);
+      // C' of the forward pass from the stencil's node velocities
+      auto node_v = [&](int ox, int oy, int oz, float* out) {
+        if (lds) {
+          const int t = a0 + ox * sz + oy * gz + oz;
+          out[0] = gtile[t];
+          out[1] = gtile[kTileCapMax + t];
+          out[2] = gtile[2 * kTileCapMax + t];
+        } else {
+          const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
+          grid_velocity(a.grid[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, ga, out);
+        }
+      };
+      float B[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+        float vo[3];
+        node_v(ox, oy, oz, vo);
+        const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+        const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) B[r][c] += wt * vo[r] * dp[c];
+      }
+      float Fb[9], Cbt[9], vbt[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float s = Fbo[3 * r + c];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) s += a.dt * D * B[k][r] * Fbo[3 * k + c];
+          Fb[3 * r + c] = s;
+          float t = Cb[3 * r + c];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) t += a.dt * Fbo[3 * r + k] * Fp[3 * c + k];
+          Cbt[3 * r + c] = t;
+        }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) vbt[k] = vb[k] + a.dt * xb[k];
+      // staggered node order (lanes of one cell hit different nodes)
+      const int g = (threadIdx.x & 63) % 27;
+      float xo[3] = {xb[0], xb[1], xb[2]};
+#pragma unroll 1
+      for (int k = 0; k < 27; ++k) {
+        int o = k + g;
+        o = (o >= 27) ? o - 27 : o;
+        const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+        float vho[3];
+        node_v(ox, oy, oz, vho);
+        const float wx = sel3(w[0], ox), wy = sel3(w[1], oy), wz = sel3(w[2], oz);
+        const float wt = wx * wy * wz;
+        const float gw[3] = {inv_dx * sel3(dw[0], ox) * wy * wz, inv_dx * wx * sel3(dw[1], oy) * wz,
+                             inv_dx * wx * wy * sel3(dw[2], oz)};
+        const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+        float cd[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) cd[r] = Cbt[3 * r] * dp[0] + Cbt[3 * r + 1] * dp[1] + Cbt[3 * r + 2] * dp[2];
+        float wb = 0.f, gv[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const float gval = vbt[r] + D * cd[r];
+          gv[r] = wt * gval;
+          wb += vho[r] * gval;
+        }
+        if (lds) {
+          const int t = a0 + ox * sz + oy * gz + oz;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) atomicAdd(&ptile[r * kTileCapMax + t], (double)gv[r]);
+        } else {
+          const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
+          float* gp = (float*)&a.vhb[gbase + ((int64_t)ix * n + iy) * n + iz];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) atomicAdd(gp + r, gv[r]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float ctv = Cbt[c] * vho[0] + Cbt[3 + c] * vho[1] + Cbt[6 + c] * vho[2];
+          xo[c] += wb * gw[c] - D * wt * ctv;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a.ax[k * N + i] = xo[k];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a.aF[k * N + i] = Fb[k];
+    }
+    if (lds) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < GT; t += kBlock) {
+        const double v0 = ptile[t], v1 = ptile[kTileCapMax + t], v2 = ptile[2 * kTileCapMax + t];
+        if (v0 == 0.0 && v1 == 0.0 && v2 == 0.0) continue;
+        const int tk = t % gz, tq = t / gz;
+        const int tj = tq % gy, ti = tq / gy;
+        float* gp = (float*)&a.vhb[gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk)];
+        atomicAdd(gp + 0, (float)v0);
+        atomicAdd(gp + 1, (float)v1);
+        atomicAdd(gp + 2, (float)v2);
+      }
     }
   }
-  float Cn[9];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Cn[3 * r + c] = D * B[r][c];
-  // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb',  Cbt = Cb' + dt Fb' F^T
-  float Fb[9], Cbt[9], vbt[3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float s = Fbo[3 * r + c];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s += a.dt * Cn[3 * k + r] * Fbo[3 * k + c];
-      Fb[3 * r + c] = s;
-      float t = Cb[3 * r + c];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) t += a.dt * Fbo[3 * r + k] * Fp[3 * c + k];
-      Cbt[3 * r + c] = t;
-    }
-  // x' = x + dt v'
-#pragma unroll
-  for (int k = 0; k < 3; ++k) vbt[k] = vb[k] + a.dt * xb[k];
-  float xo[3] = {xb[0], xb[1], xb[2]};
-#pragma unroll
-  for (int o = 0; o < 27; ++o) {
-    const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
-    const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-    const float wt = w[0][ox] * w[1][oy] * w[2][oz];
-    const float gw[3] = {inv_dx * dw[0][ox] * w[1][oy] * w[2][oz], inv_dx * w[0][ox] * dw[1][oy] * w[2][oz],
-                         inv_dx * w[0][ox] * w[1][oy] * dw[2][oz]};
-    const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
-    float cd[3];  // Cbt dpos
-#pragma unroll
-    for (int r = 0; r < 3; ++r) cd[r] = Cbt[3 * r] * dp[0] + Cbt[3 * r + 1] * dp[1] + Cbt[3 * r + 2] * dp[2];
-    float* gp = (float*)&a.vhb[gbase + ((int64_t)ix * n + iy) * n + iz];
-    float wb = 0.f;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const float gval = vbt[r] + D * cd[r];
-      atomicAdd(gp + r, wt * gval);
-      wb += vh[o][r] * gval;
-    }
-    // dpos = x_i - x_p: xb -= D w Cbt^T vh
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float ctv = Cbt[c] * vh[o][0] + Cbt[3 + c] * vh[o][1] + Cbt[6 + c] * vh[o][2];
-      xo[c] += wb * gw[c] - D * wt * ctv;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) a.ax[k * N + i] = xo[k];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) a.aF[k * N + i] = Fb[k];
 }
 
 // --------------------------------------------------------------------------
