@@ -198,15 +198,21 @@ int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
 
 int gather_from_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   ProfScope ps(c, s, 5);
-  int rc = sort_keys(c, p->x, s);
-  if (rc) return rc;
   const unsigned g = blocks_for(c->N, 256);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->xs, p->x, c->perm, 3, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->vs, p->v, c->perm, 3, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Cs, p->C, c->perm, 9, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Fs, p->F, c->perm, 9, c->N);
+  // positions in the previous call's sorted order (nearly sorted now), then
+  // the sort of those; perm = pid o perm2 maps sorted slots to caller indices
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->xs2, p->x, c->pid, 3, c->N);
+  LAUNCH_CHECK(c, "pre-permute");
+  int rc = sort_keys(c, c->xs2, s);
+  if (rc) return rc;
+  int* perm = reinterpret_cast<int*>(c->slots);  // free after k_place
+  fmpm::k_compose<<<g, 256, 0, s>>>(c->pid, c->perm, perm, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->xs, p->x, perm, 3, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->vs, p->v, perm, 3, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Cs, p->C, perm, 9, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Fs, p->F, perm, 9, c->N);
   fmpm::k_gather_params<<<g, 256, 0, s>>>(c->prm, c->mat, c->pid, p->mass, p->vol0, p->log_E, p->nu, p->mat_id,
-                                          c->perm, c->N);
+                                          perm, c->N);
   LAUNCH_CHECK(c, "gather");
   return MPM_OK;
 }
@@ -231,10 +237,13 @@ int resort_internal(mpm_ctx c, hipStream_t s) {
 int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   ProfScope ps(c, s, 5);
   const unsigned g = blocks_for(c->N, 256);
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->x, c->xs, c->pid, 3, c->N);
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->v, c->vs, c->pid, 3, c->N);
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->C, c->Cs, c->pid, 9, c->N);
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(p->F, c->Fs, c->pid, 9, c->N);
+  // gather through the inverse permutation: coalesced writes, random reads
+  int* inv = reinterpret_cast<int*>(c->keys);
+  fmpm::k_invert<<<g, 256, 0, s>>>(c->pid, inv, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->x, c->xs, inv, 3, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->v, c->vs, inv, 3, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->C, c->Cs, inv, 9, c->N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->F, c->Fs, inv, 9, c->N);
   LAUNCH_CHECK(c, "scatter");
   return MPM_OK;
 }
@@ -444,6 +453,10 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   if (e == hipSuccess) e = hipMemset(c->diag, 0, 8 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->dn_chunks, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(c->d_mats, c->mats, sizeof(c->mats), hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_particles > 0) {
+    fmpm::k_iota<<<blocks_for(n_particles, 256), 256>>>(c->pid, n_particles);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipMemset(c->grid[0], 0, (size_t)c->nodes * sizeof(float4));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {

@@ -529,19 +529,37 @@ __global__ void k_cell_keys(const float* x, int64_t N, const int* chunk_start, c
                             uint32_t* key, uint32_t* slot, uint32_t* count) {
   const int chunk = blockIdx.x;
   const int i = chunk_start[chunk] + (int)threadIdx.x;
-  if (i >= chunk_start[chunk + 1]) return;
-  int c[3];
+  const bool live = i < chunk_start[chunk + 1];
+  uint32_t k = 0xffffffffu;
+  if (live) {
+    int c[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double t = (double)x[k * N + i] * (double)n - 0.5;
-    int b = (t >= 0.0) ? (t < (double)(n - 1) ? (int)floor(t) : n - 1) : 0;  // NaN -> 0
-    c[k] = b;
+    for (int a = 0; a < 3; ++a) {
+      const double t = (double)x[a * N + i] * (double)n - 0.5;
+      c[a] = (t >= 0.0) ? (t < (double)(n - 1) ? (int)floor(t) : n - 1) : 0;  // NaN -> 0
+    }
+    const uint32_t blk = ((uint32_t)(c[0] >> 2) * nb + (uint32_t)(c[1] >> 2)) * nb + (uint32_t)(c[2] >> 2);
+    const uint32_t mort = spread2(c[0] & 3) << 2 | spread2(c[1] & 3) << 1 | spread2(c[2] & 3);
+    k = (uint32_t)chunk_batch[chunk] * (uint32_t)(nb * nb * nb * 64) + blk * 64u + mort;
   }
-  const uint32_t blk = ((uint32_t)(c[0] >> 2) * nb + (uint32_t)(c[1] >> 2)) * nb + (uint32_t)(c[2] >> 2);
-  const uint32_t mort = spread2(c[0] & 3) << 2 | spread2(c[1] & 3) << 1 | spread2(c[2] & 3);
-  const uint32_t k = (uint32_t)chunk_batch[chunk] * (uint32_t)(nb * nb * nb * 64) + blk * 64u + mort;
-  key[i] = k;
-  slot[i] = atomicAdd(&count[k], 1u);
+  // runs of equal keys in consecutive lanes take one atomic per run (the
+  // input is mostly in cell order already)
+  const int lane = threadIdx.x & 63;
+  const uint32_t prev = __shfl_up(k, 1);
+  const bool head = live && (lane == 0 || prev != k);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long livem = __ballot(live);
+  const unsigned long long below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1);
+  const int my_head = 63 - __clzll(heads & below);                                  // head of my run
+  const unsigned long long after = (lane == 63) ? 0ull : (heads & ~below);          // heads above me
+  const int next = after ? (__ffsll((long long)after) - 1) : (64 - __clzll(livem));  // end of my run
+  uint32_t base = 0;
+  if (head) base = atomicAdd(&count[k], (uint32_t)(next - lane));
+  base = __shfl(base, my_head);
+  if (live) {
+    key[i] = k;
+    slot[i] = base + (uint32_t)(lane - my_head);
+  }
 }
 
 // exclusive scan over K uint32 in three passes (tiles of 4096 = 1024 threads x 4)
@@ -697,6 +715,23 @@ __global__ void k_gather_params(float4* prm, int* mat, int* pid, const float* ma
   prm[j] = make_float4(mass[s], vol0[s], (float)mu, (float)la);
   mat[j] = mat_id[s];
   pid[j] = s;
+}
+
+// inv[pid[j]] = j
+__global__ void k_invert(const int* pid, int* inv, int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) inv[pid[j]] = (int)j;
+}
+
+// perm_out[j] = outer[perm_in[j]]
+__global__ void k_compose(const int* outer, const int* perm_in, int* perm_out, int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) perm_out[j] = outer[perm_in[j]];
+}
+
+__global__ void k_iota(int* p, int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) p[j] = (int)j;
 }
 
 // out[c][pid[j]] = in[c][j]
