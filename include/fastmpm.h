@@ -141,7 +141,7 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps,
 int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes);
 
 /* Reverse of the n_steps substeps taped by the last mpm_step_n call with
- * the same tape (elastic models with identity plasticity).  Inputs: the
+ * the same tape (both elastic models, identity plasticity only; det F > 0).  Inputs: the
  * adjoints of the final x, v, C, F (device [3][N], [3][N], [9][N], [9][N];
  * any may be NULL = zero).  Outputs (overwritten): g_log_E[N], g_nu[N] and,
  * when non-NULL, the adjoints of the initial state g_x0, g_v0, g_C0, g_F0.

@@ -150,6 +150,10 @@ fmpm::SubstepArgs make_args(mpm_ctx c) {
   a.v = c->vs;
   a.C = c->Cs;
   a.F = c->Fs;
+  a.xo = c->xs;
+  a.vo = c->vs;
+  a.Co = c->Cs;
+  a.Fo = c->Fs;
   a.prm = c->prm;
   a.mat = c->mat;
   a.N = c->N;
@@ -289,7 +293,7 @@ TapeLayout tape_layout(mpm_ctx c, int32_t n_steps, int32_t K, void* base) {
 
 bool adjoint_supported(mpm_ctx c) {
   for (int k = 0; k < c->n_mat; ++k)
-    if (c->mats[k].elastic != MPM_ELASTIC_FCR || c->mats[k].plastic != MPM_PLASTIC_NONE) return false;
+    if (c->mats[k].plastic != MPM_PLASTIC_NONE) return false;
   return true;
 }
 
@@ -478,7 +482,7 @@ int run_steps(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, 
   if (n_steps < 0) return fail(ctx, MPM_EINVAL, "n_steps < 0");
   if (tape && checkpoint_every < 1) return fail(ctx, MPM_EINVAL, "checkpoint_every < 1 with a tape");
   if (tape && !adjoint_supported(ctx))
-    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers fixed-corotated materials without plasticity");
+    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers the elastic models without plasticity");
   hipStream_t s = (hipStream_t)stream;
   ctx->last_stream = s;
   TapeLayout tl{};
@@ -567,7 +571,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
   if (ctx->N > 0 && (!p->mass || !p->vol0 || !p->log_E || !p->nu || !p->mat_id))
     return fail(ctx, MPM_EINVAL, "a parameter array is NULL");
   if (!adjoint_supported(ctx))
-    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers fixed-corotated materials without plasticity");
+    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers the elastic models without plasticity");
   if (tape != ctx->tape_ptr || n_steps != ctx->tape_n)
     return fail(ctx, MPM_ESTATE, "tape does not hold the last taped mpm_step_n of this length");
   hipStream_t s = (hipStream_t)stream;
@@ -594,34 +598,47 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     // (1) sort the checkpoint, gather state and parameters into sorted order
     rc = sort_keys(ctx, ck, s);
     if (rc) return rc;
-    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->xs, ck, ctx->perm, 3, N);
-    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->vs, ck + 3 * N, ctx->perm, 3, N);
-    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->Cs, ck + 6 * N, ctx->perm, 9, N);
-    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(ctx->Fs, ck + 15 * N, ctx->perm, 9, N);
+    auto slot = [&](int j) { return tl.seg + (int64_t)j * 24 * N; };
+    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(slot(0), ck, ctx->perm, 24, N);
     fmpm::k_gather_params<<<gp, 256, 0, s>>>(ctx->prm, ctx->mat, ctx->pid, p->mass, p->vol0, p->log_E, p->nu,
                                               p->mat_id, ctx->perm, N);
     fmpm::k_gather_lnE_nu<<<gp, 256, 0, s>>>(tl.lnE, tl.nu, p->log_E, p->nu, ctx->perm, N);
     LAUNCH_CHECK(ctx, "backward gather");
-    // (2) recompute the segment: slot j holds the state of substep k0 + j
-    auto slot = [&](int j) { return tl.seg + (int64_t)j * 24 * N; };
-    rc = copy_f32(ctx, slot(0), ctx->xs, 3 * N, s);
-    rc = rc ? rc : copy_f32(ctx, slot(0) + 3 * N, ctx->vs, 3 * N, s);
-    rc = rc ? rc : copy_f32(ctx, slot(0) + 6 * N, ctx->Cs, 9 * N, s);
-    rc = rc ? rc : copy_f32(ctx, slot(0) + 15 * N, ctx->Fs, 9 * N, s);
-    rc = rc ? rc : fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, -1, ctx->work_counter);
-    rc = rc ? rc : launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s);
+    // (2) recompute the segment: slot j holds the state of substep k0 + j;
+    // the fused kernel reads slot j and writes slot j + 1
+    auto args_for = [&](int j_in, int j_out) {
+      fmpm::SubstepArgs a = make_args(ctx);
+      float* si = slot(j_in);
+      float* so = slot(j_out);
+      a.x = si;
+      a.v = si + 3 * N;
+      a.C = si + 6 * N;
+      a.F = si + 15 * N;
+      a.xo = so;
+      a.vo = so + 3 * N;
+      a.Co = so + 6 * N;
+      a.Fo = so + 15 * N;
+      return a;
+    };
+    rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, -1, ctx->work_counter);
     if (rc) return rc;
+    {
+      fmpm::SubstepArgs a = args_for(0, 0);
+      a.grid_out = ctx->grid[0];
+      fmpm::k_substep<fmpm::kP2G><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
+      LAUNCH_CHECK(ctx, "recompute P2G");
+    }
     int cur = 0;
     for (int j = 0; j + 1 < L; ++j) {
       rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, -1, ctx->work_counter);
-      rc = rc ? rc : launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], 1, s);
       if (rc) return rc;
+      fmpm::SubstepArgs a = args_for(j, j + 1);
+      a.grid_in = ctx->grid[cur];
+      a.grid_out = ctx->grid[1 - cur];
+      a.write_vc = 1;
+      fmpm::k_substep<fmpm::kFused><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
+      LAUNCH_CHECK(ctx, "recompute substep");
       cur = 1 - cur;
-      rc = copy_f32(ctx, slot(j + 1), ctx->xs, 3 * N, s);
-      rc = rc ? rc : copy_f32(ctx, slot(j + 1) + 3 * N, ctx->vs, 3 * N, s);
-      rc = rc ? rc : copy_f32(ctx, slot(j + 1) + 6 * N, ctx->Cs, 9 * N, s);
-      rc = rc ? rc : copy_f32(ctx, slot(j + 1) + 15 * N, ctx->Fs, 9 * N, s);
-      if (rc) return rc;
     }
     // (3) adjoint of the segment's final state, in sorted order
     fmpm::k_gather_or_zero<<<gp, 256, 0, s>>>(tl.adj, tl.adjc, ctx->perm, 24, N);
@@ -632,11 +649,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     // (4) reverse the substeps of the segment
     for (int j = L - 1; j >= 0; --j) {
       const float* st = slot(j);
-      fmpm::SubstepArgs a = make_args(ctx);
-      a.x = const_cast<float*>(st);
-      a.v = const_cast<float*>(st + 3 * N);
-      a.C = const_cast<float*>(st + 6 * N);
-      a.F = const_cast<float*>(st + 15 * N);
+      fmpm::SubstepArgs a = args_for(j, j);
       a.grid_out = ctx->grid[0];
       rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, -1, ctx->work_counter);
       if (rc) return rc;
@@ -663,6 +676,9 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       b.aF = tl.adj + 15 * N;
       b.g_lnE = tl.gl;
       b.g_nu = tl.gn;
+      b.mat = ctx->mat;
+      b.mats = ctx->d_mats;
+      b.n_materials = ctx->n_mat;
       b.n = ctx->n;
       b.bound = ctx->cfg.bound;
       b.dt = ctx->cfg.dt;

@@ -1,5 +1,5 @@
 // Reverse-mode (adjoint) kernels of the MLS-MPM substep for elastic
-// particles with identity plasticity and the fixed-corotated model
+// particles with identity plasticity (fixed-corotated and Hencky models)
 // (included once, by fastmpm.hip after mpm_kernels.hpp).
 //
 // Forward substep k on state s_k = (x, v, C, F), per particle p and node i:
@@ -54,6 +54,9 @@ struct AdjArgs {
   float* aF;
   float* g_lnE;        // accumulated parameter gradients (internal order)
   float* g_nu;
+  const int* mat;      // material id (internal order)
+  const Material* mats;
+  int n_materials;
   int n;
   int bound;
   float dt;
@@ -162,6 +165,80 @@ __device__ __forceinline__ void tau_fcr_adjoint(const double* F, const double* R
       const double Rc = R[3 * i] * cx[j] + R[3 * i + 1] * cx[3 + j] + R[3 * i + 2] * cx[6 + j];
       Fb[3 * i + j] += 2.0 * mu * (tbF + tbtP - Rc) + kv * cf[3 * i + j];
     }
+}
+
+// Adjoint of the Hencky stress tau = mu L + (lam/2) tr(L) I, L = log(F F^T)
+// = 2 U diag(eps) U^T:  with G = mu sym(taub) + (lam/2) tr(taub) I and the
+// divided differences D_ij of log at lambda = sigma^2 (D_ii = 1/lambda_i),
+//   bb = U (D o (U^T G U)) U^T,  Fb += 2 bb F,
+//   mub = <taub, 2 U diag(eps) U^T>,  lamb = tr(taub) sum(eps).
+__device__ __forceinline__ void tau_hencky_adjoint(const double* F, const double U[3][3], const double* sig,
+                                                   double mu, double lam, const double* tb, double* Fb, double& mub,
+                                                   double& lamb) {
+  double e[3], l[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    e[k] = log(fmax(sig[k], kSigmaMin));
+    l[k] = sig[k] * sig[k];
+  }
+  const double trtb = tb[0] + tb[4] + tb[8];
+  // mub = <taub, 2 U diag(e) U^T>
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s += tb[3 * i + j] * (U[i][0] * e[0] * U[j][0] + U[i][1] * e[1] * U[j][1] + U[i][2] * e[2] * U[j][2]);
+  mub = 2.0 * s;
+  lamb = trtb * (e[0] + e[1] + e[2]);
+  // G in the eigenbasis: H = U^T G U
+  double G[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) G[3 * i + j] = mu * 0.5 * (tb[3 * i + j] + tb[3 * j + i]) + ((i == j) ? 0.5 * lam * trtb : 0.0);
+  double H[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double h = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) h += U[a][i] * G[3 * a + b] * U[b][j];
+      H[3 * i + j] = h;
+    }
+  // D o H
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double d;
+      if (i == j) {
+        d = 1.0 / l[i];
+      } else {
+        const double dl = l[i] - l[j];
+        d = (fabs(dl) > 1e-6 * fmax(l[i], l[j])) ? 2.0 * (e[i] - e[j]) / dl : 2.0 / (l[i] + l[j]);
+      }
+      H[3 * i + j] *= d;
+    }
+  // bb = U H U^T, Fb += 2 bb F
+  double bb[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t += U[i][a] * H[3 * a + b] * U[j][b];
+      bb[3 * i + j] = t;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Fb[3 * i + j] += 2.0 * (bb[3 * i] * F[j] + bb[3 * i + 1] * F[3 + j] + bb[3 * i + 2] * F[6 + j]);
 }
 
 // --------------------------------------------------------------------------
@@ -410,9 +487,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
   if (!ok) return;  // skipped in the forward pass: the adjoint passes through
   float vb[3] = {0.f, 0.f, 0.f}, Cb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   {
-    double R[9], tau[9];
-    polar_rotation(Fd, R);
-    tau_fixed_corotated_R(Fd, R, mu, lam, tau);
+    int mid = a.mat[i];
+    mid = (mid >= 0 && mid < a.n_materials) ? mid : 0;
+    const bool fcr = a.mats[mid].elastic == 0;
+    double R[9], tau[9], U[3][3], V[3][3], sg[3];
+    if (fcr) {
+      polar_rotation(Fd, R);
+      tau_fixed_corotated_R(Fd, R, mu, lam, tau);
+    } else {
+      svd3(Fd, U, sg, V);
+      double e[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) e[k] = log(fmax(sg[k], kSigmaMin));
+      tau_hencky_eps(U, e, mu, lam, tau);
+    }
     const float ks = D * a.dt * prm.y;
     float A[9];
 #pragma unroll
@@ -461,7 +549,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) tb[k] = -(double)ks * (double)Ab[k];
     double mub = 0.0, lamb = 0.0;
-    tau_fcr_adjoint(Fd, R, mu, lam, tb, Fb, mub, lamb);
+    if (fcr)
+      tau_fcr_adjoint(Fd, R, mu, lam, tb, Fb, mub, lamb);
+    else
+      tau_hencky_adjoint(Fd, U, sg, mu, lam, tb, Fb, mub, lamb);
     const double E = exp((double)a.lnE[i]);
     const double nv = (double)a.nu[i];
     const double den = (1.0 + nv) * (1.0 - 2.0 * nv);

@@ -33,10 +33,16 @@ constexpr int kMaxMaterials = 16;
 enum { kP2G = 0, kFused = 1, kG2P = 2 };
 
 struct SubstepArgs {
+  // particle state read by the kernel (plane stride N) ...
   float* x;
   float* v;
   float* C;
   float* F;
+  // ... and where it writes the new state (the same arrays, or other ones)
+  float* xo;
+  float* vo;
+  float* Co;
+  float* Fo;
   const float4* prm;
   const int* mat;
   int64_t N;  // plane stride
@@ -390,14 +396,14 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
             ok = false;
           }
 #pragma unroll
-          for (int k = 0; k < 3; ++k) a.x[k * N + i] = xp[k];
+          for (int k = 0; k < 3; ++k) a.xo[k * N + i] = xp[k];
 #pragma unroll
-          for (int k = 0; k < 9; ++k) a.F[k * N + i] = Ff[k];
+          for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = Ff[k];
           if (MODE == kG2P || a.write_vc) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) a.v[k * N + i] = vp[k];
+            for (int k = 0; k < 3; ++k) a.vo[k * N + i] = vp[k];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) a.C[k * N + i] = Cp[k];
+            for (int k = 0; k < 9; ++k) a.Co[k * N + i] = Cp[k];
           }
         }
       }

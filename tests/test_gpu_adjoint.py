@@ -14,16 +14,18 @@ from tests.parity import rel_err
 pytestmark = pytest.mark.gpu
 
 FCR = [dict(elastic=0, plastic=0, yield_stress=0.0, friction_deg=0.0)]
+HENCKY = [dict(elastic=1, plastic=0, yield_stress=0.0, friction_deg=0.0)]
+MIXED = FCR + HENCKY
 
 
-def elastic_case(seed, N=1500, n=32, dt=2e-4, spread=0.3):
+def elastic_case(seed, N=1500, n=32, dt=2e-4, spread=0.3, n_mat=1):
     rng = np.random.default_rng(seed)
     x, v, C, F = scenes.random_state(rng, N, n, spread=spread, vel=0.5, cgrad=5.0, fdev=0.03)
     mass = (rng.uniform(0.5, 2.0, N) * 1e-5).astype(np.float32)
     vol0 = (mass / 1000.0).astype(np.float32)
     log_E = np.log(rng.uniform(1e4, 1e5, N)).astype(np.float32)
     nu = rng.uniform(0.2, 0.4, N).astype(np.float32)
-    mat = np.zeros(N, np.int32)
+    mat = rng.integers(0, n_mat, N).astype(np.int32)
     return dict(x=x, v=v, C=C, F=F, mass=mass, vol0=vol0, log_E=log_E, nu=nu, mat_id=mat, n=n, dt=dt)
 
 
@@ -48,8 +50,8 @@ def gpu_adjoint(d, steps, K, cot, mats=FCR):
     return res, final, ctx
 
 
-def oracle_adjoint(d, steps, cot):
-    params = O.Params(d["mass"], d["vol0"], d["log_E"], d["nu"], d["mat_id"], FCR, d["n"], d["dt"])
+def oracle_adjoint(d, steps, cot, mats=FCR):
+    params = O.Params(d["mass"], d["vol0"], d["log_E"], d["nu"], d["mat_id"], mats, d["n"], d["dt"])
     s0 = tuple(torch.as_tensor(np.asarray(a, np.float64)) for a in (d["x"], d["v"], d["C"], d["F"]))
     cots = tuple(torch.as_tensor(np.asarray(c, np.float64)) for c in cot)
     return O.adjoint(s0, params, steps, cots, want_state0=True)
@@ -60,13 +62,14 @@ def random_cotangents(rng, N):
             rng.normal(0, 1e-4, (N, 3, 3)).astype(np.float32), rng.normal(0, 1e-2, (N, 3, 3)).astype(np.float32))
 
 
-@pytest.mark.parametrize("steps,K", [(1, 1), (10, 4), (12, 12)])
-def test_adjoint_matches_oracle(steps, K):
-    d = elastic_case(1)
+@pytest.mark.parametrize("steps,K,mats", [(1, 1, FCR), (10, 4, FCR), (12, 12, FCR), (1, 1, HENCKY),
+                                          (10, 4, HENCKY), (10, 3, MIXED)])
+def test_adjoint_matches_oracle(steps, K, mats):
+    d = elastic_case(1, n_mat=len(mats))
     N = len(d["mass"])
     cot = random_cotangents(np.random.default_rng(2), N)
-    res, final, _ = gpu_adjoint(d, steps, K, cot)
-    ref = oracle_adjoint(d, steps, cot)
+    res, final, _ = gpu_adjoint(d, steps, K, cot, mats)
+    ref = oracle_adjoint(d, steps, cot, mats)
     errs = {}
     for k, rk in (("g_log_E", "g_logE"), ("g_nu", "g_nu"), ("g_x0", "g_x0"), ("g_v0", "g_v0"),
                   ("g_C0", "g_C0"), ("g_F0", "g_F0")):
@@ -74,7 +77,7 @@ def test_adjoint_matches_oracle(steps, K):
         errs[k] = rel_err(res[k].reshape(N, -1), r, 0.0)
     # totals over particles (the per-instance gradient a material fit uses)
     errs["sum_g_log_E"] = abs(res["g_log_E"].sum() - ref["g_logE"].sum().item()) / abs(ref["g_logE"].sum().item())
-    print(steps, K, errs, flush=True)
+    print(steps, K, [m["elastic"] for m in mats], errs, flush=True)
     bad = {k: e for k, e in errs.items() if not e <= 2e-3}
     assert not bad, errs
 
@@ -102,7 +105,7 @@ def test_backward_errors():
     with pytest.raises(B.MPMError) as e:  # length differs from the taped run
         B.mpm_backward(ctx, p, tape, 3, g_log_E=g, g_nu=g)
     assert e.value.status == B.MPM_ESTATE
-    plastic = [dict(elastic=1, plastic=1, yield_stress=1e3, friction_deg=0.0)]
+    plastic = [dict(elastic=1, plastic=1, yield_stress=1e3, friction_deg=0.0)]  # no plastic adjoint yet
     ctx2 = B.mpm_init(d["n"], d["dt"], plastic, 100)
     with pytest.raises(B.MPMError) as e:
         B.mpm_step_n(ctx2, p, 2, tape=tape, checkpoint_every=1)
