@@ -322,7 +322,21 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
         ok = in_grid;
-        if (!in_grid) atomicAdd(&a.diag[1], 1ull);
+        if (!in_grid) {
+          atomicAdd(&a.diag[1], 1ull);
+          if (a.xo != a.x) {  // skipped: carry the state over unchanged
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a.xo[k * N + i] = xp[k];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = (float)Fd[k];
+            if (a.write_vc) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) a.vo[k * N + i] = a.v[k * N + i];
+#pragma unroll
+              for (int k = 0; k < 9; ++k) a.Co[k * N + i] = a.C[k * N + i];
+            }
+          }
+        }
         if (ok) {
           float wx[3], wy[3], wz[3];
           bspline_w(f0[0], wx);
@@ -432,9 +446,18 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
             for (int k = 0; k < 9; ++k) Ad[k] = (mass * Cp[k] - ks * (float)tau[k]) * dx;
           }
           // contribution to node o: w (m v + A (o - f) dx) = w (q + Ad o)
+          bool fin = isfinite(mass);
 #pragma unroll
-          for (int r = 0; r < 3; ++r)
+          for (int r = 0; r < 3; ++r) {
             q[r] = mass * vp[r] - (Ad[3 * r] * f1[0] + Ad[3 * r + 1] * f1[1] + Ad[3 * r + 2] * f1[2]);
+            fin &= isfinite(q[r]);
+          }
+#pragma unroll
+          for (int k = 0; k < 9; ++k) fin &= isfinite(Ad[k]);
+          if (!fin) {  // never let a bad particle reach the grid
+            atomicAdd(&a.diag[0], 1ull);
+            continue;
+          }
           const bool in_tile = lds_p && b1[0] >= plo[0] && b1[0] <= phi[0] && b1[1] >= plo[1] &&
                                b1[1] <= phi[1] && b1[2] >= plo[2] && b1[2] <= phi[2];
           if (lds_p && !in_tile) atomicAdd(&a.diag[3], 1ull);
