@@ -26,6 +26,7 @@
 
 namespace fmpm {
 
+constexpr int kPadX = 3;            // P2G tile x-stride padding (nodes), spreads LDS banks
 constexpr int kBlock = 256;         // threads per workgroup = particles per chunk
 constexpr int kTileCapMax = 1331;   // LDS tile nodes (11^3): P2G 4 doubles + G2P 3 floats per node
 constexpr int kMaxMaterials = 16;
@@ -260,7 +261,10 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
       phi[k] = min(box[k + 3] + grow, n - 3);
     }
     const int px = phi[0] - plo[0] + 3, py = phi[1] - plo[1] + 3, pz = phi[2] - plo[2] + 3;
-    const int PT = empty ? 0 : px * py * pz;
+    // x stride padded by kPadX nodes: with the plain py*pz stride the nodes a
+    // wave scatters to fall on few LDS banks (x-neighbours share a bank)
+    const int SX = py * pz + kPadX;
+    const int PT = empty ? 0 : (px - 1) * SX + (py - 1) * pz + pz;
     const bool lds_g = (MODE != kP2G) && !empty && GT <= cap;
     const bool lds_p = (MODE != kG2P) && !empty && PT <= cap;
     if (threadIdx.x == 0 && !empty && (((MODE != kP2G) && !lds_g) || ((MODE != kG2P) && !lds_p)))
@@ -477,8 +481,8 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
               r[ax][k] = rot3(gs[ax], k);
               wr[ax][k] = sel3(w[ax], r[ax][k]);
             }
-          const int sz = py * pz;
-          const int a1 = ((b1[0] - plo[0]) * py + (b1[1] - plo[1])) * pz + (b1[2] - plo[2]);
+          const int sz = SX;
+          const int a1 = (b1[0] - plo[0]) * SX + (b1[1] - plo[1]) * pz + (b1[2] - plo[2]);
 #pragma unroll
           for (int kx = 0; kx < 3; ++kx) {
             const float ox = (float)r[0][kx];
@@ -524,8 +528,9 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
       for (int t = threadIdx.x; t < PT; t += kBlock) {
         const double m = ptile[3 * kTileCapMax + t];
         if (m == 0.0) continue;
-        const int tk = t % pz, tq = t / pz;
-        const int tj = tq % py, ti = tq / py;
+        const int ti = t / SX, tr = t - ti * SX;
+        const int tj = tr / pz, tk = tr - tj * pz;
+        if (tj >= py) continue;  // padding
         float* gp = (float*)&a.grid_out[gbase + ((int64_t)(plo[0] + ti) * n + (plo[1] + tj)) * n + (plo[2] + tk)];
         atomicAdd(gp + 0, (float)ptile[t]);
         atomicAdd(gp + 1, (float)ptile[kTileCapMax + t]);
