@@ -66,6 +66,45 @@ def measured_traffic(n_particles):
     return t["fused_fetch_kib"] * 1024.0 * f_scale + t["fused_write_kib"] * 1024.0 * w_scale
 
 
+PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
+               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched")
+
+
+def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
+    """Summarise two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, in
+    KiB per dispatch) of PMC_COMMAND into TRAFFIC_FILE: the 256 MiB
+    calibration copy (largest copy-kernel dispatch) and the mean over the
+    fused-kernel dispatches, stamped with the hash of the kernel sources."""
+    import csv
+
+    def read(path, counter):
+        copy, fused = 0.0, []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                if r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
+                    copy = max(copy, v)
+                elif "k_substep<1>" in r["Kernel_Name"]:
+                    fused.append(v)
+        if not fused or copy <= 0:
+            raise SystemExit(f"{path}: no {counter} rows for the copy and the fused kernel")
+        return copy, sum(fused) / len(fused), len(fused)
+
+    cf, ff, nf = read(fetch_csv, "FETCH_SIZE")
+    cw, fw, nw = read(write_csv, "WRITE_SIZE")
+    t = {"kernel": "k_substep<1> (fused G2P + return map + stress + P2G)",
+         "workload": "large_scene, 2,000,000 particles, 128^3", "particles": n_particles,
+         "kernel_source_hash": kernel_source_hash(), "fused_fetch_kib": ff, "fused_write_kib": fw,
+         "dispatches": min(nf, nw), "copy_bytes": 256 * 1024 * 1024, "copy_fetch_kib": cf, "copy_write_kib": cw,
+         "command_fetch": PMC_COMMAND.format(c="FETCH_SIZE"), "command_write": PMC_COMMAND.format(c="WRITE_SIZE")}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+        fh.write("\n")
+    return t
+
+
 def copy_probe():
     """A plain 256 MiB device copy, the calibration point of the HBM counters."""
     import torch
@@ -156,11 +195,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs plain fwd+bwd comparison")
     ap.add_argument("--n-total", type=int, default=2_000_000)
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
     args = ap.parse_args()
+    if args.write_traffic:
+        print(json.dumps(write_traffic(*args.write_traffic, n_particles=args.n_total)))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the workload would shard by scene or by grid slab; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the workload would shard by scene or by grid slab)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

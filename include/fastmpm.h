@@ -56,7 +56,7 @@ typedef enum {
   MPM_EDEVICE = -3,      /* a HIP runtime call failed */
   MPM_ESTATE = -4,       /* call out of order (e.g. backward without a taped forward) */
   MPM_EUNSTABLE = -5,    /* device counters saw NaN/Inf or a stencil leaving the grid */
-  MPM_EUNSUPPORTED = -6  /* valid request this build does not implement */
+  MPM_EUNSUPPORTED = -6  /* valid request the library does not implement */
 } mpm_status;
 
 /* Elastic models (App. A.2 / B.1).

@@ -24,7 +24,7 @@ X <- (X + X^-T) / 2 instead of an SVD, whose derivative is undefined at
 repeated singular values (e.g. F = I).  It is restricted to the elastic
 (identity-plasticity) models and to det F > 0.
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
   * grid nodes sit at i*dx, i in [0, n); base = floor(x/dx - 0.5) per axis,
     computed exactly (x is a float32 value, the product is exact in float64);
   * sticky walls: v_i = 0 where any node index is < bound or >= n - bound;
