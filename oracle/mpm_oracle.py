@@ -8,15 +8,17 @@ What it computes, step by step, in float64 with plain PyTorch CPU ops:
 
   O0  Lame parameters from (log E, nu)                       App. B.1 (Lame relations)
   O1  clear the grid
-  O2  Kirchhoff stress tau = P F^T of the particle's model    App. A.2 (fixed corotated, StVK/Hencky);
-                                                              App. B.1 (Corotated, SigmaElasticity)
+  O2  Kirchhoff stress tau = P F^T of the particle's model    App. A.2 (fixed corotated, StVK/Hencky,
+                                                              Neo-Hookean); App. B.1 (Corotated,
+                                                              SigmaElasticity, StVK, Fluid, Volume)
   O3  P2G: quadratic B-spline weights, APIC affine momentum  Sec. 4.2 momentum-exchange equation;
       with the MLS stress term                                App. A.1 (P2G)
   O4  grid update: normalise, gravity, sticky walls          App. A.1 (grid update)
   O5  G2P: v, C (with the 4/dx^2 factor), x                  App. A.1 (G2P)
   O6  F_trial = (I + dt C') F                                 MLS-MPM reading of App. A.1's grad-v update
   O7  plastic return map applied after the stress            App. A.2 (identity, Drucker-Prager,
-                                                              von Mises); App. B.2 (ordering); Alg. 1
+                                                              von Mises, fluid); App. B.2 (sigma,
+                                                              ordering); Alg. 1
 
 The adjoint is torch autograd through the same steps (``adjoint``), with the
 polar factor of the fixed-corotated model computed by the Newton iteration
@@ -34,7 +36,14 @@ Readings of points the paper leaves open:
   * log of singular values is taken of max(sigma, 1e-4);
   * Drucker-Prager: delta_gamma = |eps_hat| + (3 lam + 2 mu)/(2 mu) tr(eps) alpha,
     alpha = sqrt(2/3) 2 sin(phi) / (3 - sin(phi)), zero cohesion (Klar et al. 2016);
-  * the elastic model paired with von Mises and Drucker-Prager is Hencky.
+  * the elastic model paired with von Mises and Drucker-Prager is Hencky;
+  * StVK (App. B.1) is the standard Green-Lagrange model in Kirchhoff form,
+    tau = F (2 mu E + lam tr(E) I) F^T: the printed 2 mu F E + lam J (J - 1) I
+    is neither symmetric nor P F^T;
+  * log J (Neo-Hookean) and J^(1 - gamma) (volume model, gamma = 2) take
+    J = max(det F, 1e-4), the floor the singular values get;
+  * fluid and sigma plasticity set F to the real cube root of (the clamped)
+    det F times I, so an inverted F keeps its negative determinant.
 
 Array conventions: x, v [N,3]; C, F [N,3,3]; grid arrays flattened over
 (ix, iy, iz) with iz fastest, m [n^3], mv / v [n^3, 3].
@@ -49,8 +58,12 @@ import torch
 F64 = torch.float64
 SIGMA_MIN = 1e-4
 
-ELASTIC_FCR, ELASTIC_HENCKY = 0, 1
-PLASTIC_NONE, PLASTIC_VON_MISES, PLASTIC_DRUCKER_PRAGER = 0, 1, 2
+J_MIN = 1e-4
+SIGMA_J_RANGE = (0.05, 1.2)  # App. B.2, sigma plasticity
+VOLUME_GAMMA = 2.0           # App. B.1, volume elasticity
+
+ELASTIC_FCR, ELASTIC_HENCKY, ELASTIC_NEO_HOOKEAN, ELASTIC_STVK, ELASTIC_FLUID, ELASTIC_VOLUME = 0, 1, 2, 3, 4, 5
+PLASTIC_NONE, PLASTIC_VON_MISES, PLASTIC_DRUCKER_PRAGER, PLASTIC_FLUID, PLASTIC_SIGMA = 0, 1, 2, 3, 4
 
 
 def as64(a) -> torch.Tensor:
@@ -115,14 +128,53 @@ def tau_hencky(F, mu, lam):
     return _diag_sandwich(U, d, U)
 
 
+def _eye_times(s):
+    return s[:, None, None] * torch.eye(3, dtype=s.dtype)
+
+
+def tau_neo_hookean(F, mu, lam):
+    """App. A.2: P = mu (F - F^-T) + lam log(J) F^-T, so tau = P F^T =
+    mu (F F^T - I) + lam log(J) I."""
+    J = torch.linalg.det(F)
+    b = F @ F.transpose(-1, -2)
+    eye = torch.eye(3, dtype=F.dtype)
+    return mu[:, None, None] * (b - eye) + _eye_times(lam * torch.log(torch.clamp(J, min=J_MIN)))
+
+
+def tau_stvk(F, mu, lam):
+    """Green-Lagrange StVK: E = (F^T F - I)/2, P = F (2 mu E + lam tr(E) I),
+    tau = P F^T (App. B.1, read as the standard model)."""
+    eye = torch.eye(3, dtype=F.dtype)
+    E = 0.5 * (F.transpose(-1, -2) @ F - eye)
+    S = 2.0 * mu[:, None, None] * E + _eye_times(lam * E.diagonal(dim1=-2, dim2=-1).sum(-1))
+    return F @ S @ F.transpose(-1, -2)
+
+
+def tau_fluid(F, mu, lam):
+    """App. B.1 fluid elasticity (mu = 0): tau = lam J (J - 1) I."""
+    J = torch.linalg.det(F)
+    return _eye_times(lam * J * (J - 1.0))
+
+
+def tau_volume(F, mu, lam):
+    """App. B.1 volume elasticity: tau = kappa (J - J^(1 - gamma)) I with
+    kappa = 2/3 mu + lam, gamma = 2."""
+    J = torch.linalg.det(F)
+    kappa = 2.0 / 3.0 * mu + lam
+    return _eye_times(kappa * (J - torch.clamp(J, min=J_MIN) ** (1.0 - VOLUME_GAMMA)))
+
+
+TAU = {ELASTIC_FCR: tau_fixed_corotated, ELASTIC_HENCKY: tau_hencky, ELASTIC_NEO_HOOKEAN: tau_neo_hookean,
+       ELASTIC_STVK: tau_stvk, ELASTIC_FLUID: tau_fluid, ELASTIC_VOLUME: tau_volume}
+
+
 def kirchhoff_stress(F, mu, lam, mat_id, materials: Sequence[Dict]):
     tau = torch.zeros_like(F)
     for k, mat in enumerate(materials):
         sel = mat_id == k
         if not bool(sel.any()):
             continue
-        fn = tau_fixed_corotated if mat["elastic"] == ELASTIC_FCR else tau_hencky
-        tau[sel] = fn(F[sel], mu[sel], lam[sel])
+        tau[sel] = TAU[mat["elastic"]](F[sel], mu[sel], lam[sel])
     return tau
 
 
@@ -170,6 +222,21 @@ def return_drucker_prager(F, mu, lam, friction_deg):
     return out
 
 
+def _real_cbrt(J):
+    return torch.sign(J) * torch.abs(J) ** (1.0 / 3.0)
+
+
+def return_fluid(F):
+    """App. A.2 fluid plasticity: F' = J^(1/3) I, J = det F."""
+    return _eye_times(_real_cbrt(torch.linalg.det(F)))
+
+
+def return_sigma(F):
+    """App. B.2 sigma plasticity: J clamped to [0.05, 1.2], F' = J^(1/3) I."""
+    J = torch.clamp(torch.linalg.det(F), min=SIGMA_J_RANGE[0], max=SIGMA_J_RANGE[1])
+    return _eye_times(_real_cbrt(J))
+
+
 def plasticity(F, mu, lam, mat_id, materials: Sequence[Dict]):
     out = F.clone()
     for k, mat in enumerate(materials):
@@ -180,6 +247,10 @@ def plasticity(F, mu, lam, mat_id, materials: Sequence[Dict]):
             out[sel] = return_von_mises(F[sel], mu[sel], mat["yield_stress"])
         elif mat["plastic"] == PLASTIC_DRUCKER_PRAGER:
             out[sel] = return_drucker_prager(F[sel], mu[sel], lam[sel], mat["friction_deg"])
+        elif mat["plastic"] == PLASTIC_FLUID:
+            out[sel] = return_fluid(F[sel])
+        elif mat["plastic"] == PLASTIC_SIGMA:
+            out[sel] = return_sigma(F[sel])
         else:
             raise ValueError(f"unknown plastic model {mat['plastic']}")
     return out
@@ -400,7 +471,10 @@ def _kirchhoff_differentiable(F, mu, lam, mat_id, materials):
             continue
         if mat["plastic"] != PLASTIC_NONE:
             raise NotImplementedError("the adjoint oracle covers the elastic models only")
-        fn = _tau_fcr_differentiable if mat["elastic"] == ELASTIC_FCR else _tau_hencky_differentiable
+        # the closed-form models are differentiable as written; the polar and
+        # log factors get SVD-free forms
+        fn = {ELASTIC_FCR: _tau_fcr_differentiable, ELASTIC_HENCKY: _tau_hencky_differentiable}.get(
+            mat["elastic"], TAU[mat["elastic"]])
         tau = tau.index_put((sel.nonzero()[:, 0],), fn(F[sel], mu[sel], lam[sel]))
     return tau
 

@@ -251,17 +251,48 @@ def _energy_hencky(F, mu, lam):
     return mu * np.sum(e * e) + 0.5 * lam * e.sum() ** 2
 
 
-@pytest.mark.parametrize("model", ["fcr", "hencky"])
+def _energy_neo_hookean(F, mu, lam):
+    lnJ = np.log(np.linalg.det(F))
+    return 0.5 * mu * (np.sum(F * F) - 3.0) - mu * lnJ + 0.5 * lam * lnJ ** 2
+
+
+def _energy_stvk(F, mu, lam):
+    E = 0.5 * (F.T @ F - np.eye(3))
+    return mu * np.sum(E * E) + 0.5 * lam * np.trace(E) ** 2
+
+
+def _energy_fluid(F, mu, lam):
+    return 0.5 * lam * (np.linalg.det(F) - 1.0) ** 2
+
+
+def _energy_volume(F, mu, lam):
+    # d/dJ of kappa (J + 1/J - 2) is kappa (1 - J^-2); times J: kappa (J - 1/J)
+    J = np.linalg.det(F)
+    return (2.0 / 3.0 * mu + lam) * (J + 1.0 / J - 2.0)
+
+
+ENERGY_MODELS = {
+    "fcr": (_energy_fcr, O.tau_fixed_corotated), "hencky": (_energy_hencky, O.tau_hencky),
+    "neo_hookean": (_energy_neo_hookean, O.tau_neo_hookean), "stvk": (_energy_stvk, O.tau_stvk),
+    "fluid": (_energy_fluid, O.tau_fluid), "volume": (_energy_volume, O.tau_volume)}
+
+
+@pytest.mark.parametrize("model", sorted(ENERGY_MODELS))
 def test_stress_is_energy_derivative(model):
     """tau = (dPsi/dF) F^T, with dPsi/dF from central differences of the
     textbook energies (fixed corotated: mu|F-R|^2 + lam/2 (J-1)^2;
-    Hencky: mu|log S|^2 + lam/2 tr(log S)^2)."""
+    Hencky: mu|log S|^2 + lam/2 tr(log S)^2; Neo-Hookean (Bonet & Wood):
+    mu/2 (|F|^2 - 3) - mu log J + lam/2 (log J)^2; StVK: mu|E|^2 + lam/2 tr(E)^2;
+    fluid: lam/2 (J - 1)^2; volume: kappa (J + 1/J - 2))."""
     rng = np.random.default_rng(5)
     mu, lam = 3.0e4, 5.0e4
-    energy = _energy_fcr if model == "fcr" else _energy_hencky
-    fn = O.tau_fixed_corotated if model == "fcr" else O.tau_hencky
-    for _ in range(10):
+    energy, fn = ENERGY_MODELS[model]
+    done = 0
+    while done < 10:
         F = np.eye(3) + rng.normal(0, 0.2, (3, 3))
+        if np.linalg.det(F) < 0.2:
+            continue
+        done += 1
         h = 1e-6
         P = np.zeros((3, 3))
         for i in range(3):
@@ -289,9 +320,12 @@ def test_first_piola_forms_of_appendix_A2():
     FT = F.transpose(-1, -2)
     assert torch.allclose(P_fcr @ FT, O.tau_fixed_corotated(F, mu, lam), rtol=1e-10, atol=1e-8)
     assert torch.allclose(P_h @ FT, O.tau_hencky(F, mu, lam), rtol=1e-10, atol=1e-8)
+    P_nh = mu[:, None, None] * (F - FinvT) + (lam * torch.log(J))[:, None, None] * FinvT
+    assert torch.allclose(P_nh @ FT, O.tau_neo_hookean(F, mu, lam), rtol=1e-10, atol=1e-8)
 
 
-@pytest.mark.parametrize("fn", [O.tau_fixed_corotated, O.tau_hencky])
+@pytest.mark.parametrize("fn", [O.tau_fixed_corotated, O.tau_hencky, O.tau_neo_hookean, O.tau_stvk, O.tau_fluid,
+                                O.tau_volume])
 def test_stress_rest_objectivity_linearity(fn):
     rng = np.random.default_rng(8)
     mu, lam = O.lame(torch.tensor([math.log(1e5)] * 40, dtype=F64), torch.tensor([0.3] * 40, dtype=F64))
@@ -313,7 +347,7 @@ def test_lame_matches_uniaxial_linear_elasticity():
     mu, lam = O.lame(torch.tensor([math.log(E)]), torch.tensor([nu], dtype=F64))
     e = 1e-7
     F = torch.diag(torch.tensor([1 + e, 1 - nu * e, 1 - nu * e], dtype=F64))[None]
-    for fn in (O.tau_fixed_corotated, O.tau_hencky):
+    for fn in (O.tau_fixed_corotated, O.tau_hencky, O.tau_neo_hookean, O.tau_stvk):
         t = fn(F, mu, lam)[0]
         assert abs(t[0, 0].item() / e - E) < 1e-5 * E
         assert abs(t[1, 1].item() / e) < 1e-5 * E
@@ -329,6 +363,28 @@ def test_diagonal_closed_forms():
     hen = torch.diag(2 * mu * torch.log(s) + lam * torch.log(s).sum())
     assert torch.allclose(O.tau_fixed_corotated(F, mu, lam)[0], fcr, atol=1e-9)
     assert torch.allclose(O.tau_hencky(F, mu, lam)[0], hen, atol=1e-9)
+    nh = torch.diag(mu * (s * s - 1) + lam * torch.log(J))
+    gl = 0.5 * (s * s - 1)
+    stvk = torch.diag(s * s * (2 * mu * gl + lam * gl.sum()))
+    kappa = 2.0 / 3.0 * mu + lam
+    assert torch.allclose(O.tau_neo_hookean(F, mu, lam)[0], nh, atol=1e-9)
+    assert torch.allclose(O.tau_stvk(F, mu, lam)[0], stvk, atol=1e-9)
+    assert torch.allclose(O.tau_fluid(F, mu, lam)[0], torch.eye(3, dtype=F64) * lam * J * (J - 1), atol=1e-9)
+    assert torch.allclose(O.tau_volume(F, mu, lam)[0], torch.eye(3, dtype=F64) * kappa * (J - 1 / J), atol=1e-9)
+
+
+def test_volume_model_small_strain_bulk_response():
+    """kappa (J - 1/J) ~ 2 kappa (J - 1) near J = 1: pressure linear in the
+    volume change, no shear response, and the J floor only below 1e-4."""
+    mu, lam = torch.tensor([1.0e4], dtype=F64), torch.tensor([2.0e4], dtype=F64)
+    kappa = 2.0 / 3.0 * 1.0e4 + 2.0e4
+    e = 1e-7
+    t = O.tau_volume(torch.diag(torch.tensor([1 + e, 1.0, 1.0], dtype=F64))[None], mu, lam)[0]
+    assert abs(t[0, 0].item() / e - 2 * kappa) < 1e-5 * kappa and abs(t[0, 1].item()) == 0.0
+    shear = torch.tensor([[1.0, 0.3, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]], dtype=F64)[None]  # J = 1
+    assert torch.allclose(O.tau_volume(shear, mu, lam), torch.zeros(1, 3, 3, dtype=F64), atol=1e-9)
+    tiny = torch.diag(torch.tensor([1e-5, 1.0, 1.0], dtype=F64))[None]
+    assert abs(O.tau_volume(tiny, mu, lam)[0, 0, 0].item() - kappa * (1e-5 - 1e4)) < 1e-6 * kappa * 1e4
 
 
 # --------------------------------------------------------------------------
@@ -399,6 +455,30 @@ def test_drucker_prager_return():
     assert torch.allclose(O.return_drucker_prager(F1, mu, lam, phi), F1, atol=1e-12)
 
 
+def test_fluid_and_sigma_return_maps():
+    """Fluid plasticity keeps det F and drops every deviatoric part; sigma
+    plasticity does the same with det F clamped to [0.05, 1.2]."""
+    rng = np.random.default_rng(13)
+    F = torch.tensor(np.eye(3) + rng.normal(0, 0.4, (300, 3, 3)))
+    J = torch.linalg.det(F)
+    assert bool((J < 0).any()) and bool((J > 1.2).any()) and bool(((J > 0) & (J < 0.05)).any())
+    eye = torch.eye(3, dtype=F64)
+    f = O.return_fluid(F)
+    assert torch.allclose(torch.linalg.det(f), J, rtol=1e-12, atol=1e-15)
+    assert torch.allclose(f - f[:, :1, :1] * eye, torch.zeros_like(f), atol=0)
+    s = O.return_sigma(F)
+    Jc = torch.clamp(J, 0.05, 1.2)
+    assert torch.allclose(torch.linalg.det(s), Jc, rtol=1e-12)
+    inside = (J >= 0.05) & (J <= 1.2)
+    assert torch.equal(s[inside], f[inside])
+    mats = [dict(elastic=0, plastic=O.PLASTIC_FLUID, yield_stress=0.0, friction_deg=0.0),
+            dict(elastic=0, plastic=O.PLASTIC_SIGMA, yield_stress=0.0, friction_deg=0.0)]
+    mid = torch.tensor(rng.integers(0, 2, 300))
+    mu = torch.full((300,), 1e4, dtype=F64)
+    out = O.plasticity(F, mu, mu, mid, mats)
+    assert torch.equal(out[mid == 0], f[mid == 0]) and torch.equal(out[mid == 1], s[mid == 1])
+
+
 # --------------------------------------------------------------------------
 # Adjoint oracle: differentiable pieces and finite differences
 # --------------------------------------------------------------------------
@@ -426,7 +506,7 @@ def _small_elastic_scene(rng, N=150, n=16, dt=2e-4, mats=None, mat_id=None):
     return (x, v, C, F), p
 
 
-@pytest.mark.parametrize("elastic", [0, 1])
+@pytest.mark.parametrize("elastic", [0, 1, 2, 3, 4, 5])
 def test_adjoint_matches_central_differences(elastic):
     rng = np.random.default_rng(12)
     mats = [dict(elastic=elastic, plastic=0, yield_stress=0.0, friction_deg=0.0)]
