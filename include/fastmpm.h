@@ -59,19 +59,39 @@ typedef enum {
   MPM_EUNSUPPORTED = -6  /* valid request the library does not implement */
 } mpm_status;
 
-/* Elastic models (App. A.2 / B.1).
- *   FCR:    tau = 2 mu (F - R) F^T + lam J (J - 1) I, R the rotation of F = R S.
- *   HENCKY: tau = U diag(2 mu eps + lam tr(eps)) U^T, eps = log(max(sigma, 1e-4)),
- *           F = U diag(sigma) V^T with U, V rotations.  */
-enum { MPM_ELASTIC_FCR = 0, MPM_ELASTIC_HENCKY = 1 };
+/* Elastic models (App. A.2 / B.1); J = det F, J+ = max(J, 1e-4).
+ *   FCR:         tau = 2 mu (F - R) F^T + lam J (J - 1) I, R the rotation of F = R S.
+ *   HENCKY:      tau = U diag(2 mu eps + lam tr(eps)) U^T, eps = log(max(sigma, 1e-4)),
+ *                F = U diag(sigma) V^T with U, V rotations.
+ *   NEO_HOOKEAN: tau = mu (F F^T - I) + lam log(J+) I          (P = mu (F - F^-T) + lam log J F^-T).
+ *   STVK:        tau = F (2 mu E + lam tr(E) I) F^T, E = (F^T F - I) / 2 (Green-Lagrange).
+ *   FLUID:       tau = lam J (J - 1) I                          (mu unused).
+ *   VOLUME:      tau = kappa (J - 1 / J+) I, kappa = 2/3 mu + lam (Mie-Grueneisen form, gamma = 2).  */
+enum {
+  MPM_ELASTIC_FCR = 0,
+  MPM_ELASTIC_HENCKY = 1,
+  MPM_ELASTIC_NEO_HOOKEAN = 2,
+  MPM_ELASTIC_STVK = 3,
+  MPM_ELASTIC_FLUID = 4,
+  MPM_ELASTIC_VOLUME = 5
+};
 
 /* Plastic return maps (App. A.2 / B.2), applied to F after the stress.
  *   NONE:            F' = F.
  *   VON_MISES:       project the log-strain deviator onto |eps_hat| = yield/(2 mu).
  *   DRUCKER_PRAGER:  tension (tr eps > 0) -> F' = U V^T; else
  *                    dgamma = |eps_hat| + (3 lam + 2 mu)/(2 mu) tr(eps) alpha,
- *                    alpha = sqrt(2/3) 2 sin(phi)/(3 - sin(phi)), zero cohesion.  */
-enum { MPM_PLASTIC_NONE = 0, MPM_PLASTIC_VON_MISES = 1, MPM_PLASTIC_DRUCKER_PRAGER = 2 };
+ *                    alpha = sqrt(2/3) 2 sin(phi)/(3 - sin(phi)), zero cohesion.
+ *   FLUID:           F' = cbrt(J) I (real cube root: an inverted F keeps det < 0).
+ *   SIGMA:           F' = cbrt(clamp(J, 0.05, 1.2)) I.
+ * VON_MISES and DRUCKER_PRAGER take an FP64 SVD of F; FLUID and SIGMA only det F.  */
+enum {
+  MPM_PLASTIC_NONE = 0,
+  MPM_PLASTIC_VON_MISES = 1,
+  MPM_PLASTIC_DRUCKER_PRAGER = 2,
+  MPM_PLASTIC_FLUID = 3,
+  MPM_PLASTIC_SIGMA = 4
+};
 
 typedef struct {
   int32_t elastic;       /* MPM_ELASTIC_* */
@@ -141,7 +161,7 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps,
 int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes);
 
 /* Reverse of the n_steps substeps taped by the last mpm_step_n call with
- * the same tape (both elastic models, identity plasticity only; det F > 0).  Inputs: the
+ * the same tape (any elastic model, identity plasticity only; det F > 0).  Inputs: the
  * adjoints of the final x, v, C, F (device [3][N], [3][N], [9][N], [9][N];
  * any may be NULL = zero).  Outputs (overwritten): g_log_E[N], g_nu[N] and,
  * when non-NULL, the adjoints of the initial state g_x0, g_v0, g_C0, g_F0.

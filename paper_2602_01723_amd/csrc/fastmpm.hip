@@ -375,8 +375,8 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   fmpm::Material mats[fmpm::kMaxMaterials]{};
   for (int k = 0; k < n_materials; ++k) {
     const mpm_material& m = materials[k];
-    if (m.elastic != MPM_ELASTIC_FCR && m.elastic != MPM_ELASTIC_HENCKY) return MPM_EINVAL;
-    if (m.plastic < MPM_PLASTIC_NONE || m.plastic > MPM_PLASTIC_DRUCKER_PRAGER) return MPM_EINVAL;
+    if (m.elastic < MPM_ELASTIC_FCR || m.elastic > MPM_ELASTIC_VOLUME) return MPM_EINVAL;
+    if (m.plastic < MPM_PLASTIC_NONE || m.plastic > MPM_PLASTIC_SIGMA) return MPM_EINVAL;
     if (m.plastic == MPM_PLASTIC_VON_MISES && !(m.yield_stress > 0.0f)) return MPM_EINVAL;
     if (m.plastic == MPM_PLASTIC_DRUCKER_PRAGER && !(m.friction_deg > 0.0f && m.friction_deg < 90.0f))
       return MPM_EINVAL;

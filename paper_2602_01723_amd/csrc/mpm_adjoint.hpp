@@ -1,5 +1,6 @@
 // Reverse-mode (adjoint) kernels of the MLS-MPM substep for elastic
-// particles with identity plasticity (fixed-corotated and Hencky models)
+// particles with identity plasticity (fixed-corotated, Hencky, Neo-Hookean,
+// StVK, fluid and volume models)
 // (included once, by fastmpm.hip after mpm_kernels.hpp).
 //
 // Forward substep k on state s_k = (x, v, C, F), per particle p and node i:
@@ -165,6 +166,104 @@ __device__ __forceinline__ void tau_fcr_adjoint(const double* F, const double* R
       const double Rc = R[3 * i] * cx[j] + R[3 * i + 1] * cx[3 + j] + R[3 * i + 2] * cx[6 + j];
       Fb[3 * i + j] += 2.0 * mu * (tbF + tbtP - Rc) + kv * cf[3 * i + j];
     }
+}
+
+// Adjoint of the closed-form models (Fb += dL/dF, mub, lamb), with
+// cof = J F^-T = dJ/dF and tb the cotangent of tau:
+//   Neo-Hookean  Fb += mu (tb + tb^T) F + lam tr(tb) F^-T [J > 1e-4]
+//   StVK         Fb += (tb + tb^T) F S + F sym(Eb), Sb = F^T tb F,
+//                Eb = 2 mu Sb + lam tr(Sb) I, mub = 2 <Sb, E>, lamb = tr(Sb) tr(E)
+//   fluid        Fb += lam tr(tb) (2J - 1) cof
+//   volume       Fb += kappa tr(tb) (1 + [J > 1e-4] / J^2) cof, kappab = tr(tb) (J - 1/J+)
+__device__ __forceinline__ void tau_closed_form_adjoint(int model, const double* F, double mu, double lam,
+                                                        const double* tb, double* Fb, double& mub, double& lamb) {
+  const double J = det3(F);
+  const double trtb = tb[0] + tb[4] + tb[8];
+  double cof[9];
+  cof[0] = F[4] * F[8] - F[5] * F[7];
+  cof[1] = F[5] * F[6] - F[3] * F[8];
+  cof[2] = F[3] * F[7] - F[4] * F[6];
+  cof[3] = F[2] * F[7] - F[1] * F[8];
+  cof[4] = F[0] * F[8] - F[2] * F[6];
+  cof[5] = F[1] * F[6] - F[0] * F[7];
+  cof[6] = F[1] * F[5] - F[2] * F[4];
+  cof[7] = F[2] * F[3] - F[0] * F[5];
+  cof[8] = F[0] * F[4] - F[1] * F[3];
+  if (model == kElasticNeoHookean) {
+    const double kj = (J > kJMin) ? lam * trtb / J : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double b = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+        s += tb[3 * i + j] * (b - (i == j ? 1.0 : 0.0));
+        // (tb + tb^T) F
+        Fb[3 * i + j] += mu * ((tb[3 * i] + tb[i]) * F[j] + (tb[3 * i + 1] + tb[3 + i]) * F[3 + j] +
+                               (tb[3 * i + 2] + tb[6 + i]) * F[6 + j]) +
+                         kj * cof[3 * i + j];
+      }
+    mub += s;
+    lamb += trtb * log(fmax(J, kJMin));
+    return;
+  }
+  if (model == kElasticStVK) {
+    double E[9], S[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        E[3 * i + j] = 0.5 * (F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j] - (i == j ? 1.0 : 0.0));
+    const double trE = E[0] + E[4] + E[8];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S[k] = 2.0 * mu * E[k] + (k % 4 == 0 ? lam * trE : 0.0);
+    double T[9], FS[9], TF[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) T[k] = tb[k] + tb[3 * (k % 3) + k / 3];  // tb + tb^T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        FS[3 * i + j] = F[3 * i] * S[j] + F[3 * i + 1] * S[3 + j] + F[3 * i + 2] * S[6 + j];
+        TF[3 * i + j] = tb[3 * i] * F[j] + tb[3 * i + 1] * F[3 + j] + tb[3 * i + 2] * F[6 + j];  // tb F
+      }
+    // Sb = F^T tb F
+    double Sb[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Sb[3 * i + j] = F[i] * TF[j] + F[3 + i] * TF[3 + j] + F[6 + i] * TF[6 + j];
+    const double trSb = Sb[0] + Sb[4] + Sb[8];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s += Sb[k] * E[k];
+    mub += 2.0 * s;
+    lamb += trSb * trE;
+    double Es[9];  // sym(Eb), Eb = 2 mu Sb + lam tr(Sb) I
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      Es[k] = mu * (Sb[k] + Sb[3 * (k % 3) + k / 3]) + (k % 4 == 0 ? lam * trSb : 0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Fb[3 * i + j] += T[3 * i] * FS[j] + T[3 * i + 1] * FS[3 + j] + T[3 * i + 2] * FS[6 + j] +
+                         F[3 * i] * Es[j] + F[3 * i + 1] * Es[3 + j] + F[3 * i + 2] * Es[6 + j];
+    return;
+  }
+  double dp;  // d(pressure)/dJ times tr(tb)
+  if (model == kElasticFluid) {
+    dp = lam * trtb * (2.0 * J - 1.0);
+    lamb += trtb * J * (J - 1.0);
+  } else {
+    const double kappa = 2.0 / 3.0 * mu + lam;
+    dp = kappa * trtb * (1.0 + ((J > kJMin) ? 1.0 / (J * J) : 0.0));
+    const double kb = trtb * (J - 1.0 / fmax(J, kJMin));
+    mub += 2.0 / 3.0 * kb;
+    lamb += kb;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Fb[k] += dp * cof[k];
 }
 
 // Adjoint of the Hencky stress tau = mu L + (lam/2) tr(L) I, L = log(F F^T)
@@ -489,11 +588,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
   {
     int mid = a.mat[i];
     mid = (mid >= 0 && mid < a.n_materials) ? mid : 0;
-    const bool fcr = a.mats[mid].elastic == 0;
+    const int el = a.mats[mid].elastic;
+    const bool fcr = el == kElasticFCR;
     double R[9], tau[9], U[3][3], V[3][3], sg[3];
     if (fcr) {
       polar_rotation(Fd, R);
       tau_fixed_corotated_R(Fd, R, mu, lam, tau);
+    } else if (el >= kElasticNeoHookean) {
+      tau_closed_form(el, Fd, mu, lam, tau);
     } else {
       svd3(Fd, U, sg, V);
       double e[3];
@@ -551,6 +653,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
     double mub = 0.0, lamb = 0.0;
     if (fcr)
       tau_fcr_adjoint(Fd, R, mu, lam, tb, Fb, mub, lamb);
+    else if (el >= kElasticNeoHookean)
+      tau_closed_form_adjoint(el, Fd, mu, lam, tb, Fb, mub, lamb);
     else
       tau_hencky_adjoint(Fd, U, sg, mu, lam, tb, Fb, mub, lamb);
     const double E = exp((double)a.lnE[i]);

@@ -7,10 +7,11 @@
 // values with the sign of det F carried by the last one (the convention of
 // Irving et al. 2004 for inverted elements).  V in SO(3) as well.
 //
-// Stresses are Kirchhoff tau = P F^T (App. A.2 fixed corotated and StVK /
-// Hencky forms, App. B.1 Corotated and SigmaElasticity).  Return maps follow
-// App. A.2 / B.2 (identity, von Mises, Drucker-Prager with the Klar et al.
-// 2016 plastic multiplier).
+// Stresses are Kirchhoff tau = P F^T (App. A.2 fixed corotated, StVK /
+// Hencky and Neo-Hookean forms; App. B.1 Corotated, SigmaElasticity, StVK
+// (Green-Lagrange), fluid and volume models).  Return maps follow App. A.2 /
+// B.2 (identity, von Mises, Drucker-Prager with the Klar et al. 2016 plastic
+// multiplier, fluid, sigma).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,6 +21,14 @@
 namespace fmpm {
 
 constexpr double kSigmaMin = 1e-4;  // log-strain floor for singular values
+constexpr double kJMin = 1e-4;      // floor of J inside log J and 1/J
+constexpr double kSigmaJLo = 0.05, kSigmaJHi = 1.2;  // sigma plasticity clamp of J
+
+// model codes (the MPM_ELASTIC_* / MPM_PLASTIC_* values of the C ABI)
+constexpr int kElasticFCR = 0, kElasticHencky = 1, kElasticNeoHookean = 2, kElasticStVK = 3, kElasticFluid = 4,
+              kElasticVolume = 5;
+constexpr int kPlasticNone = 0, kPlasticVonMises = 1, kPlasticDruckerPrager = 2, kPlasticFluid = 3,
+              kPlasticSigma = 4;
 
 struct Material {
   int32_t elastic;
@@ -247,6 +256,54 @@ __device__ __forceinline__ void tau_hencky_eps(const double U[3][3], const doubl
   diag_sandwich(U, d, U, tau);
 }
 
+// Elastic models in closed form of F (no SVD):
+//   Neo-Hookean  tau = mu (F F^T - I) + lam log(J+) I
+//   StVK         tau = F (2 mu E + lam tr(E) I) F^T, E = (F^T F - I) / 2
+//   fluid        tau = lam J (J - 1) I
+//   volume       tau = kappa (J - 1 / J+) I, kappa = 2/3 mu + lam
+// with J+ = max(J, 1e-4).
+__device__ __forceinline__ void tau_closed_form(int model, const double* F, double mu, double lam, double* tau) {
+  const double J = det3(F);
+  if (model == kElasticNeoHookean) {
+    const double p = lam * log(fmax(J, kJMin));
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double b = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+        tau[3 * i + j] = mu * (b - (i == j ? 1.0 : 0.0)) + (i == j ? p : 0.0);
+      }
+    return;
+  }
+  if (model == kElasticStVK) {
+    double S[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        S[3 * i + j] = 0.5 * (F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j] - (i == j ? 1.0 : 0.0));
+    const double tr = S[0] + S[4] + S[8];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S[k] = 2.0 * mu * S[k] + (k % 4 == 0 ? lam * tr : 0.0);
+    double FS[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        FS[3 * i + j] = F[3 * i] * S[j] + F[3 * i + 1] * S[3 + j] + F[3 * i + 2] * S[6 + j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        tau[3 * i + j] = FS[3 * i] * F[3 * j] + FS[3 * i + 1] * F[3 * j + 1] + FS[3 * i + 2] * F[3 * j + 2];
+    return;
+  }
+  const double p = (model == kElasticFluid) ? lam * J * (J - 1.0)
+                                            : (2.0 / 3.0 * mu + lam) * (J - 1.0 / fmax(J, kJMin));
+#pragma unroll
+  for (int k = 0; k < 9; ++k) tau[k] = (k % 4 == 0) ? p : 0.0;
+}
+
 // -------------------------------------------------------------------------
 // Return maps.  Input: F_trial (FP64) and its SVD.  Output: F' and the
 // principal log strains of F' (U, V unchanged), which the Hencky stress of
@@ -294,37 +351,65 @@ __device__ __forceinline__ void return_map(const Material& mat, double mu, doubl
 // Deformation update and stress of one particle.  Ftr is the trial
 // deformation gradient (FP64).  Computes the plastic return map (when the
 // material has one) into Fout and the Kirchhoff stress tau of Fout for the
-// particle's elastic model.  One SVD of Ftr at most: a fixed-corotated
-// particle without plasticity takes its rotation from Newton's polar
-// iteration, falling back to the SVD for inverted or degenerate F.
+// particle's elastic model.  One SVD at most: the closed-form models need
+// one only under von Mises / Drucker-Prager; fluid and sigma plasticity use
+// det F alone; a fixed-corotated particle takes its rotation from Newton's
+// polar iteration, falling back to the SVD for inverted or degenerate F.
 // apply_plasticity = false evaluates the stress of Ftr as given.
 __device__ __forceinline__ void update_and_stress(const Material& mat, double mu, double lam, const double* Ftr,
                                                   bool apply_plasticity, bool want_stress, double* Fout,
                                                   double* tau) {
-  const bool plastic = apply_plasticity && mat.plastic != 0;
+  const bool svd_plastic =
+      apply_plasticity && (mat.plastic == kPlasticVonMises || mat.plastic == kPlasticDruckerPrager);
+  const bool j_plastic = apply_plasticity && (mat.plastic == kPlasticFluid || mat.plastic == kPlasticSigma);
+  // Fs: the trial F, or its volumetric projection cbrt(J) I (fluid / sigma
+  // plasticity), whose stress the elastic model then gives
+  double Fs[9];
+  if (j_plastic) {
+    double J = det3(Ftr);
+    if (mat.plastic == kPlasticSigma) J = fmin(fmax(J, kSigmaJLo), kSigmaJHi);
+    const double c = cbrt(J);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fs[k] = (k % 4 == 0) ? c : 0.0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fs[k] = Ftr[k];
+  }
+  if (mat.elastic >= kElasticNeoHookean) {
+    if (svd_plastic) {
+      double U[3][3], V[3][3], sig[3], eps[3];
+      svd3(Fs, U, sig, V);
+      return_map(mat, mu, lam, Fs, U, sig, V, Fout, eps);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fout[k] = Fs[k];
+    }
+    if (want_stress) tau_closed_form(mat.elastic, Fout, mu, lam, tau);
+    return;
+  }
   double R[9];
   bool have_R = false;
-  if (!plastic && mat.elastic == 0) {
+  if (!svd_plastic && mat.elastic == kElasticFCR) {
     if (!want_stress) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) Fout[k] = Ftr[k];
+      for (int k = 0; k < 9; ++k) Fout[k] = Fs[k];
       return;
     }
-    have_R = polar_rotation_newton(Ftr, R);
+    have_R = polar_rotation_newton(Fs, R);
   }
   double U[3][3], V[3][3], eps[3];
   if (!have_R) {
     double sig[3];
-    svd3(Ftr, U, sig, V);
-    if (plastic) {
-      return_map(mat, mu, lam, Ftr, U, sig, V, Fout, eps);
+    svd3(Fs, U, sig, V);
+    if (svd_plastic) {
+      return_map(mat, mu, lam, Fs, U, sig, V, Fout, eps);
     } else {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) Fout[k] = Ftr[k];
+      for (int k = 0; k < 9; ++k) Fout[k] = Fs[k];
 #pragma unroll
       for (int k = 0; k < 3; ++k) eps[k] = log(fmax(sig[k], kSigmaMin));
     }
-    if (mat.elastic == 0) {
+    if (mat.elastic == kElasticFCR) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -332,10 +417,10 @@ __device__ __forceinline__ void update_and_stress(const Material& mat, double mu
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Fout[k] = Ftr[k];
+    for (int k = 0; k < 9; ++k) Fout[k] = Fs[k];
   }
   if (!want_stress) return;
-  if (mat.elastic == 0)
+  if (mat.elastic == kElasticFCR)
     tau_fixed_corotated_R(Fout, R, mu, lam, tau);
   else
     tau_hencky_eps(U, eps, mu, lam, tau);

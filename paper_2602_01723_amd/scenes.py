@@ -37,9 +37,15 @@ import numpy as np
 # Material codes shared with include/fastmpm.h (MPM_ELASTIC_*, MPM_PLASTIC_*).
 ELASTIC_FCR = 0
 ELASTIC_HENCKY = 1
+ELASTIC_NEO_HOOKEAN = 2
+ELASTIC_STVK = 3
+ELASTIC_FLUID = 4
+ELASTIC_VOLUME = 5
 PLASTIC_NONE = 0
 PLASTIC_VON_MISES = 1
 PLASTIC_DRUCKER_PRAGER = 2
+PLASTIC_FLUID = 3
+PLASTIC_SIGMA = 4
 
 RHO = 1000.0
 GRAVITY = (0.0, -9.8, 0.0)

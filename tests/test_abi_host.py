@@ -66,10 +66,11 @@ def test_invalid_config_rejected_on_host(lib, kw):
 
 
 def test_invalid_materials_and_offsets(lib):
-    assert _init(lib, _cfg(), mats=[B.mpm_material(2, 0, 0.0, 0.0)])[0] == B.MPM_EINVAL
+    assert _init(lib, _cfg(), mats=[B.mpm_material(6, 0, 0.0, 0.0)])[0] == B.MPM_EINVAL   # elastic code
+    assert _init(lib, _cfg(), mats=[B.mpm_material(-1, 0, 0.0, 0.0)])[0] == B.MPM_EINVAL
     assert _init(lib, _cfg(), mats=[B.mpm_material(1, 1, 0.0, 0.0)])[0] == B.MPM_EINVAL   # yield 0
     assert _init(lib, _cfg(), mats=[B.mpm_material(1, 2, 0.0, 95.0)])[0] == B.MPM_EINVAL  # friction
-    assert _init(lib, _cfg(), mats=[B.mpm_material(1, 3, 0.0, 0.0)])[0] == B.MPM_EINVAL
+    assert _init(lib, _cfg(), mats=[B.mpm_material(1, 5, 0.0, 0.0)])[0] == B.MPM_EINVAL   # plastic code
     assert _init(lib, _cfg(), n=-1)[0] == B.MPM_EINVAL
     assert _init(lib, _cfg(n_batch=2), n=10, offsets=None)[0] == B.MPM_EINVAL
     assert _init(lib, _cfg(n_batch=2), n=10, offsets=[0, 6, 5])[0] == B.MPM_EINVAL

@@ -16,6 +16,8 @@ pytestmark = pytest.mark.gpu
 FCR = [dict(elastic=0, plastic=0, yield_stress=0.0, friction_deg=0.0)]
 HENCKY = [dict(elastic=1, plastic=0, yield_stress=0.0, friction_deg=0.0)]
 MIXED = FCR + HENCKY
+CLOSED_FORM = [dict(elastic=e, plastic=0, yield_stress=0.0, friction_deg=0.0) for e in (2, 3, 4, 5)]
+ALL_ELASTIC = FCR + HENCKY + CLOSED_FORM
 
 
 def elastic_case(seed, N=1500, n=32, dt=2e-4, spread=0.3, n_mat=1):
@@ -63,7 +65,9 @@ def random_cotangents(rng, N):
 
 
 @pytest.mark.parametrize("steps,K,mats", [(1, 1, FCR), (10, 4, FCR), (12, 12, FCR), (1, 1, HENCKY),
-                                          (10, 4, HENCKY), (10, 3, MIXED)])
+                                          (10, 4, HENCKY), (10, 3, MIXED)] +
+                         [(1, 1, [m]) for m in CLOSED_FORM] + [(10, 4, [m]) for m in CLOSED_FORM] +
+                         [(10, 3, ALL_ELASTIC)])
 def test_adjoint_matches_oracle(steps, K, mats):
     d = elastic_case(1, n_mat=len(mats))
     N = len(d["mass"])

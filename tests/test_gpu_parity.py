@@ -19,6 +19,17 @@ MATS_MIXED = [dict(elastic=0, plastic=0, yield_stress=0.0, friction_deg=0.0),
               dict(elastic=0, plastic=1, yield_stress=2e3, friction_deg=0.0)]
 
 
+# every elastic model alone, and each plastic model under a different elastic one
+MATS_ALL = [dict(elastic=e, plastic=0, yield_stress=0.0, friction_deg=0.0) for e in range(6)] + [
+    dict(elastic=2, plastic=1, yield_stress=2e3, friction_deg=0.0),
+    dict(elastic=3, plastic=2, yield_stress=0.0, friction_deg=30.0),
+    dict(elastic=0, plastic=3, yield_stress=0.0, friction_deg=0.0),
+    dict(elastic=1, plastic=4, yield_stress=0.0, friction_deg=0.0),
+    dict(elastic=5, plastic=3, yield_stress=0.0, friction_deg=0.0),
+    dict(elastic=2, plastic=4, yield_stress=0.0, friction_deg=0.0),
+    dict(elastic=4, plastic=4, yield_stress=0.0, friction_deg=0.0)]
+
+
 def _grid_np(ctx):
     m, mv, v = B.grid_state(ctx)
     torch.cuda.synchronize()
@@ -68,6 +79,31 @@ def test_substep_random_mixed_materials(N):
     d = random_scene(100 + N, N)
     errs, diag, _, _ = run_case(d)
     print(N, errs, diag, flush=True)
+    assert diag["nonfinite"] == 0 and diag["out_of_grid"] == 0
+    assert_parity(errs)
+
+
+@pytest.mark.parametrize("N", [257, 5000])
+def test_substep_all_constitutive_models(N):
+    d = random_scene(300 + N, N, mats=MATS_ALL)
+    errs, diag, _, _ = run_case(d)
+    print(N, errs, diag, flush=True)
+    assert diag["nonfinite"] == 0 and diag["out_of_grid"] == 0
+    assert_parity(errs)
+
+
+def test_substep_large_volume_change_models():
+    """F = s (I + 0.05 N) with s^3 in [0.01, 2]: the sigma clamp of J acts
+    on both sides, the J floors of the Neo-Hookean and volume models do not."""
+    N = 3000
+    d = random_scene(77, N, mats=MATS_ALL, cgrad=5.0)
+    rng = np.random.default_rng(78)
+    s = np.cbrt(rng.uniform(0.01, 2.0, N))
+    d["F"] = (s[:, None, None] * (np.eye(3) + rng.normal(0, 0.05, (N, 3, 3)))).astype(np.float32)
+    J = np.linalg.det(d["F"].astype(np.float64))
+    assert (J < 0.05).any() and (J > 1.2).any() and (J > 0).all()
+    errs, diag, _, _ = run_case(d)
+    print(errs, diag, flush=True)
     assert diag["nonfinite"] == 0 and diag["out_of_grid"] == 0
     assert_parity(errs)
 
