@@ -542,3 +542,67 @@ def test_adjoint_matches_central_differences(elastic):
     fd = (loss(p.log_E, p.nu, state0[0] + h * dx) - loss(p.log_E, p.nu, state0[0] - h * dx)) / (2 * h)
     an = float((res["g_x0"] * dx).sum())
     assert abs(fd - an) <= 1e-4 * abs(an) + 1e-12, (fd, an)
+
+
+# --------------------------------------------------------------------------
+# BGDO (Alg. 1, Sec. 4.2, App. B.3-B.4)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("elastic", [0, 1, 2, 3, 4, 5])
+def test_bgdo_stress_gradient_is_stress_norm(elastic):
+    """Every model's tau is linear in (mu, lam), both proportional to E, so
+    d|tau|/d log E = |tau|: the autograd derivative must reproduce it."""
+    rng = np.random.default_rng(20 + elastic)
+    N = 64
+    F = np.eye(3) + rng.normal(0, 0.15, (N, 3, 3))
+    F[np.linalg.det(F) < 0.2] = np.eye(3) * 1.05
+    mats = [dict(elastic=elastic, plastic=0, yield_stress=0.0, friction_deg=0.0)]
+    p = _params(N, 16, 1e-4, mats=mats, rng=rng)
+    p.log_E = torch.tensor(np.log(rng.uniform(1e3, 1e6, N)))
+    x = torch.tensor(rng.uniform(0.4, 0.6, (N, 3)))
+    state = (x, torch.zeros(N, 3, dtype=F64), torch.zeros(N, 3, 3, dtype=F64), torch.tensor(F))
+    g, delta, term = O.bgdo_key_frame(state, p)
+    mu, lam = O.lame(p.log_E, p.nu)
+    s = torch.linalg.matrix_norm(O.kirchhoff_stress(torch.tensor(F), mu, lam, p.mat_id, mats))
+    assert torch.allclose(g, s, rtol=1e-10, atol=1e-9)
+    eta = torch.clamp(0.1 * torch.log(1.0 + torch.exp(p.log_E)), max=1.0)
+    assert torch.allclose(term, eta * torch.log(1.0 + s) - (1 - eta) * (delta - 0.1), rtol=1e-12, atol=1e-12)
+
+
+def test_bgdo_rest_state_closed_form():
+    """At rest (F = I, v = C = 0, no gravity) tau = 0 and F' = I, so each key
+    frame contributes 0.1 (1 - eta); E = 1e3 gives eta = 0.1 ln(1001)."""
+    rng = np.random.default_rng(30)
+    N = 200
+    p = _params(N, 16, 1e-4, E=1e3, rng=rng)
+    state0 = (torch.tensor(rng.uniform(0.4, 0.6, (N, 3))), torch.zeros(N, 3, dtype=F64),
+              torch.zeros(N, 3, 3, dtype=F64), torch.eye(3, dtype=F64).expand(N, 3, 3).clone())
+    out = O.bgdo(state0, p, frames=3, substeps_per_frame=2, key_frames=[0, 1, 2])
+    eta = 0.1 * math.log(1001.0)
+    assert torch.allclose(out, torch.full((N,), math.log(1e3) - 0.1 * (1 - eta), dtype=F64), atol=1e-12)
+
+
+def test_bgdo_deformation_of_an_affine_field():
+    """v = a + B x, C = B, F = I: tau = 0 in the first substep and APIC moves
+    the affine field exactly, so F' = I + dt B and delta = dt |B|_F."""
+    rng = np.random.default_rng(31)
+    N, n, dt = 300, 16, 1e-4
+    x = torch.tensor(rng.uniform(0.3, 0.7, (N, 3)))
+    a = torch.tensor(rng.normal(0, 1, 3))
+    B = torch.tensor(rng.normal(0, 2, (3, 3)))
+    state = (x, a + x @ B.T, B.expand(N, 3, 3).clone(), torch.eye(3, dtype=F64).expand(N, 3, 3).clone())
+    p = _params(N, n, dt, rng=rng)
+    g, delta, _ = O.bgdo_key_frame(state, p)
+    assert torch.allclose(g, torch.zeros(N, dtype=F64), atol=1e-9)
+    assert torch.allclose(delta, torch.full((N,), dt * float(torch.linalg.norm(B)), dtype=F64), rtol=1e-9)
+
+
+def test_bgdo_key_frames_are_stored_before_their_substeps():
+    """Key frame k holds the state after k frames (k S substeps), and the
+    update is the mean of the key-frame terms."""
+    rng = np.random.default_rng(32)
+    N, S = 150, 3
+    state0, p = _small_elastic_scene(rng, N=N)
+    out = O.bgdo(state0, p, frames=4, substeps_per_frame=S, key_frames=[0, 2, 3])
+    terms = [O.bgdo_key_frame(O.step_n(state0, p, k * S), p)[2] for k in (0, 2, 3)]
+    assert torch.allclose(out, p.log_E - sum(terms) / 3, rtol=0, atol=1e-12)
