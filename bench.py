@@ -67,7 +67,7 @@ def measured_traffic(n_particles):
 
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
-               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched")
+               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched --no-bgdo")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
@@ -103,6 +103,31 @@ def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) 
         json.dump(t, fh, indent=1)
         fh.write("\n")
     return t
+
+
+def bgdo_timing(sc, frames=25, substeps_per_frame=20):
+    """One BGDO iteration (Alg. 1) on the workload: a gradient-free run of
+    frames x substeps_per_frame substeps storing key frames {0, t, n}, one
+    substep from each and the log E update.  Wall time, device-synchronised."""
+    import numpy as np
+    import torch
+
+    from paper_2602_01723_amd import bgdo as BG
+    from paper_2602_01723_amd import binding as B
+    ctx = B.init_from_scene(sc)
+    p = B.Particles.from_scene(sc)
+    B.mpm_step_n(ctx, p.clone(), 2)  # warm-up (allocations, first sort)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    BG.bgdo(ctx, p, frames, substeps_per_frame)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    upd = p.log_E.cpu().numpy().astype(np.float64) - sc.log_E
+    return {"workload": f"same scene, {frames} frames x {substeps_per_frame} substeps, key frames "
+                        f"{BG.default_key_frames(frames)}, one iteration",
+            "seconds": dt, "substeps": frames * substeps_per_frame,
+            "mean_log_E_update": float(upd.mean()),
+            "paper_context": "39 s BGDO forward per scene on an RTX A6000 (different scenes, not comparable)"}
 
 
 def copy_probe():
@@ -195,6 +220,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs plain fwd+bwd comparison")
     ap.add_argument("--n-total", type=int, default=2_000_000)
+    ap.add_argument("--no-bgdo", action="store_true", help="skip the BGDO iteration timing")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
     args = ap.parse_args()
@@ -265,6 +291,12 @@ def main():
 
     del ctx, p
     torch.cuda.empty_cache()
+    bgdo = None
+    if not args.no_bgdo:
+        log("one BGDO iteration ...")
+        bgdo = bgdo_timing(sc)
+        log(f"  {bgdo['seconds']:.3f} s for {bgdo['substeps']} substeps + 3 key frames")
+        torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
         log("batched vs plain forward + adjoint ...")
@@ -301,6 +333,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_fwd_bwd": batched,
+        "bgdo": bgdo,
     }
     print(json.dumps(out), flush=True)
 

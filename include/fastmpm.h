@@ -228,6 +228,23 @@ int mpm_graph_destroy(mpm_graph g);
 int mpm_position_loss_grad(mpm_ctx ctx, const float* x, const float* x_target, const float* weight, float* g_x,
                            void* stream);
 
+/* BGDO (Alg. 1, Sec. 4.2, App. B.3-B.4): signals of one key frame.  `key`
+ * is the key-frame state in the caller's order (reads F, log_E, nu,
+ * mat_id); F_next [9][N] is F one substep later (mpm_substep from that
+ * state, return map included).  For every particle, with E = exp(log_E):
+ *   s      = |tau(F)|_F, the Kirchhoff stress of its elastic model; its
+ *            derivative by log E equals s (tau is linear in mu, lam ~ E)
+ *   delta  = |F_next - I|_F
+ *   eta    = min(1, 0.1 log(1 + E))
+ *   g_total[p] += eta log(1 + s) - (1 - eta) (delta - delta_target)
+ * s_out, delta_out (optional, may be NULL) receive s and delta.  All
+ * device arrays of N floats; g_total accumulates across key frames. */
+int mpm_bgdo_accumulate(mpm_ctx ctx, const mpm_particles* key, const float* F_next, float delta_target,
+                        float* g_total, float* s_out, float* delta_out, void* stream);
+
+/* BGDO update: log_E[p] -= g_total[p] / n_keys (n_keys >= 1). */
+int mpm_bgdo_apply(mpm_ctx ctx, float* log_E, const float* g_total, int32_t n_keys, void* stream);
+
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, by class: 0 fused G2P+P2G substep kernel, 1 P2G-only kernel,
  * 2 G2P-only kernel, 3 sort and permute, 4 grid clear, 5 gather from /

@@ -24,8 +24,8 @@ MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNS
 EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_tape_size",
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
             "mpm_set_tuning", "mpm_get_tuning", "mpm_autotune", "mpm_graph_begin", "mpm_graph_end",
-            "mpm_graph_launch", "mpm_graph_destroy", "mpm_position_loss_grad", "mpm_profile", "mpm_profile_read",
-            "mpm_destroy")
+            "mpm_graph_launch", "mpm_graph_destroy", "mpm_position_loss_grad", "mpm_bgdo_accumulate",
+            "mpm_bgdo_apply", "mpm_profile", "mpm_profile_read", "mpm_destroy")
 PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io", "unused",
                    "other_fill")
 
@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_graph_end": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp)]),
         "mpm_position_loss_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "mpm_graph_launch": (ctypes.c_int, [vp, vp]),
+        "mpm_bgdo_accumulate": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp, ctypes.c_float, vp, vp, vp, vp]),
+        "mpm_bgdo_apply": (ctypes.c_int, [vp, vp, vp, i32, vp]),
         "mpm_graph_destroy": (ctypes.c_int, [vp]),
         "mpm_profile": (ctypes.c_int, [vp, i32]),
         "mpm_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -342,6 +344,19 @@ def mpm_graph_end(ctx: Context, stream, keep=()) -> Graph:
 def mpm_position_loss_grad(ctx: Context, x, x_target, weight, g_x, stream=None):
     rc = load().mpm_position_loss_grad(ctx.handle, _ptr(x), _ptr(x_target), _ptr(weight), _ptr(g_x), _stream(stream))
     _check(ctx, rc, "mpm_position_loss_grad")
+
+
+def mpm_bgdo_accumulate(ctx: Context, key: "Particles", F_next, delta_target, g_total, s_out=None, delta_out=None,
+                        stream=None):
+    st = key.as_struct()
+    rc = load().mpm_bgdo_accumulate(ctx.handle, ctypes.byref(st), _ptr(F_next), float(delta_target),
+                                    _ptr(g_total), _ptr(s_out), _ptr(delta_out), _stream(stream))
+    _check(ctx, rc, "mpm_bgdo_accumulate")
+
+
+def mpm_bgdo_apply(ctx: Context, log_E, g_total, n_keys, stream=None):
+    rc = load().mpm_bgdo_apply(ctx.handle, _ptr(log_E), _ptr(g_total), int(n_keys), _stream(stream))
+    _check(ctx, rc, "mpm_bgdo_apply")
 
 
 def mpm_profile(ctx: Context, enable: bool = True):

@@ -887,6 +887,31 @@ int mpm_position_loss_grad(mpm_ctx ctx, const float* x, const float* x_target, c
   return MPM_OK;
 }
 
+int mpm_bgdo_accumulate(mpm_ctx ctx, const mpm_particles* key, const float* F_next, float delta_target,
+                        float* g_total, float* s_out, float* delta_out, void* stream) {
+  if (!ctx || !key) return MPM_EINVAL;
+  if (!std::isfinite(delta_target)) return fail(ctx, MPM_EINVAL, "delta_target");
+  if (ctx->N == 0) return MPM_OK;
+  if (!key->F || !key->log_E || !key->nu || !key->mat_id || !F_next || !g_total)
+    return fail(ctx, MPM_EINVAL, "NULL array");
+  fmpm::k_bgdo_accumulate<<<blocks_for(ctx->N, 256), 256, 0, (hipStream_t)stream>>>(
+      key->F, F_next, key->log_E, key->nu, key->mat_id, ctx->d_mats, ctx->n_mat, delta_target, g_total, s_out,
+      delta_out, ctx->N);
+  LAUNCH_CHECK(ctx, "k_bgdo_accumulate");
+  return MPM_OK;
+}
+
+int mpm_bgdo_apply(mpm_ctx ctx, float* log_E, const float* g_total, int32_t n_keys, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (n_keys < 1) return fail(ctx, MPM_EINVAL, "n_keys < 1");
+  if (ctx->N == 0) return MPM_OK;
+  if (!log_E || !g_total) return fail(ctx, MPM_EINVAL, "NULL array");
+  fmpm::k_bgdo_apply<<<blocks_for(ctx->N, 256), 256, 0, (hipStream_t)stream>>>(log_E, g_total, 1.0f / (float)n_keys,
+                                                                               ctx->N);
+  LAUNCH_CHECK(ctx, "k_bgdo_apply");
+  return MPM_OK;
+}
+
 int mpm_graph_launch(mpm_graph g, void* stream) {
   if (!g) return MPM_EINVAL;
   return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? MPM_OK : MPM_EDEVICE;

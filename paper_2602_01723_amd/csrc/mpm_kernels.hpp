@@ -822,4 +822,44 @@ __global__ void k_covariance(const float* F, const float* cov0, float* cov, int6
   }
 }
 
+// BGDO key-frame signals (Alg. 1, stage 2), one particle per thread in the
+// caller's order: s = |tau(F)|_F of the particle's elastic model, whose
+// log E derivative is s itself (tau is linear in (mu, lam), both
+// proportional to E); delta = |F_next - I|_F; with eta = min(1, 0.1 log(1 + E))
+// g_total += eta log(1 + s) - (1 - eta) (delta - delta_target).
+__global__ void k_bgdo_accumulate(const float* F, const float* F_next, const float* log_E, const float* nu,
+                                  const int* mat_id, const Material* mats, int n_materials, float delta_target,
+                                  float* g_total, float* s_out, float* d_out, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double Fd[9], Fo[9], tau[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Fd[k] = (double)F[k * N + i];
+  const double E = exp((double)log_E[i]);
+  const double nv = (double)nu[i];
+  const double mu = E / (2.0 * (1.0 + nv));
+  const double lam = E * nv / ((1.0 + nv) * (1.0 - 2.0 * nv));
+  int mid = mat_id[i];
+  mid = (mid >= 0 && mid < n_materials) ? mid : 0;
+  update_and_stress(mats[mid], mu, lam, Fd, false, true, Fo, tau);
+  double s2 = 0.0, d2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    s2 += tau[k] * tau[k];
+    const double d = (double)F_next[k * N + i] - (k % 4 == 0 ? 1.0 : 0.0);
+    d2 += d * d;
+  }
+  const double sn = sqrt(s2), delta = sqrt(d2);
+  const double eta = fmin(1.0, 0.1 * log1p(E));
+  g_total[i] += (float)(eta * log1p(sn) - (1.0 - eta) * (delta - (double)delta_target));
+  if (s_out) s_out[i] = (float)sn;
+  if (d_out) d_out[i] = (float)delta;
+}
+
+// log E -= g_total / n_keys (Alg. 1, the log-space update)
+__global__ void k_bgdo_apply(float* log_E, const float* g_total, float inv_keys, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) log_E[i] -= g_total[i] * inv_keys;
+}
+
 }  // namespace fmpm
