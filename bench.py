@@ -67,7 +67,7 @@ def measured_traffic(n_particles):
 
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
-               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched --no-bgdo")
+               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched --no-bgdo --no-models")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
@@ -128,6 +128,38 @@ def bgdo_timing(sc, frames=25, substeps_per_frame=20):
             "seconds": dt, "substeps": frames * substeps_per_frame,
             "mean_log_E_update": float(upd.mean()),
             "paper_context": "39 s BGDO forward per scene on an RTX A6000 (different scenes, not comparable)"}
+
+
+MODEL_VARIANTS = (("fixed_corotated", 0, 0), ("hencky", 1, 0), ("neo_hookean", 2, 0), ("stvk", 3, 0),
+                  ("fluid_elastic", 4, 0), ("volume", 5, 0), ("hencky+von_mises", 1, 1),
+                  ("hencky+drucker_prager", 1, 2), ("fixed_corotated+fluid", 0, 3), ("hencky+sigma", 1, 4))
+
+
+def per_model_timing(sc, steps=3, substeps=10):
+    """Fused-kernel time (HIP events) of the same workload with every
+    particle given one material, for each elastic model and return map."""
+    import torch
+
+    from paper_2602_01723_amd import binding as B
+    out = {}
+    for name, el, pl in MODEL_VARIANTS:
+        mat = dict(elastic=el, plastic=pl, yield_stress=1e3, friction_deg=30.0)
+        ctx = B.mpm_init(sc.grid_res, sc.dt, [mat] * len(sc.materials), sc.n, None, sc.gravity, sc.bound)
+        p = B.Particles.from_scene(sc)
+        B.mpm_step_n(ctx, p, substeps)
+        torch.cuda.synchronize()
+        B.mpm_profile(ctx, True)
+        B.mpm_profile_read(ctx)
+        for _ in range(steps):
+            B.mpm_step_n(ctx, p, substeps)
+        torch.cuda.synchronize()
+        ms, n = B.mpm_profile_read(ctx)["fused_substep"]
+        d = B.mpm_get_diagnostics(ctx)
+        out[name] = {"fused_us": round(ms / max(n, 1) * 1e3, 1),
+                     "particle_substeps_per_s_fused": sc.n / (ms / max(n, 1) / 1e3),
+                     "nonfinite": d["nonfinite"], "out_of_grid": d["out_of_grid"]}
+        del ctx, p
+    return out
 
 
 def copy_probe():
@@ -221,6 +253,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs plain fwd+bwd comparison")
     ap.add_argument("--n-total", type=int, default=2_000_000)
     ap.add_argument("--no-bgdo", action="store_true", help="skip the BGDO iteration timing")
+    ap.add_argument("--no-models", action="store_true", help="skip the per-model fused-kernel timing")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
     args = ap.parse_args()
@@ -297,6 +330,12 @@ def main():
         bgdo = bgdo_timing(sc)
         log(f"  {bgdo['seconds']:.3f} s for {bgdo['substeps']} substeps + 3 key frames")
         torch.cuda.empty_cache()
+    models = None
+    if not args.no_models:
+        log("fused kernel per constitutive model ...")
+        models = per_model_timing(sc)
+        log("  " + ", ".join(f"{k} {v['fused_us']} us" for k, v in models.items()))
+        torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
         log("batched vs plain forward + adjoint ...")
@@ -334,6 +373,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_fwd_bwd": batched,
         "bgdo": bgdo,
+        "per_model_fused": models,
     }
     print(json.dumps(out), flush=True)
 
