@@ -25,6 +25,10 @@ What it computes, step by step, in float64 with plain PyTorch CPU ops:
       (autograd), the deformation |F' - I|_F one substep later,
       and the log-space update of log E
 
+  O10 MCIS interior filling: nearest-surface distance,        Sec. 4.1 (MCIS steps 1-5)
+      Gaussian weight with floor, normalised probability,
+      sampling without replacement by exponential keys
+
 The adjoint is torch autograd through the same steps (``adjoint``), with the
 polar factor of the fixed-corotated model computed by the Newton iteration
 X <- (X + X^-T) / 2 instead of an SVD, whose derivative is undefined at
@@ -596,3 +600,61 @@ def bgdo(state0, p: Params, frames: int, substeps_per_frame: int, key_frames: Se
             g_total = g_total + bgdo_key_frame(snap, q, delta_target)[2]
         log_E = log_E - g_total / len(stored)
     return log_E
+
+
+# ---------------------------------------------------------------------------
+# O10: interior filling by instance-aware Monte Carlo importance sampling
+# (Sec. 4.1, MCIS steps 1-5), given each instance's surface points (the
+# Gaussian centres) and its candidate points already inside it
+# ---------------------------------------------------------------------------
+#
+# Readings: multinomial sampling of n_k points is without replacement (R19),
+# by exponential keys (Efraimidis & Spirakis 2006): the n_k largest
+# log(u_j) / p_j for uniform u_j in (0, 1), which the caller supplies.  Ties of
+# equal keys go to the lower candidate index.
+
+MCIS_SIGMA = 0.02
+MCIS_EPS = 1e-6
+
+
+def mcis_distance(cand, surf, chunk=4096):
+    """Step 1: d_j = min over surface points c of |q_j - c|_2, brute force."""
+    cand, surf = as64(cand), as64(surf)
+    out = torch.empty(cand.shape[0], dtype=F64)
+    if surf.shape[0] == 0:  # no surface: every candidate is infinitely far
+        return out.fill_(math.inf)
+    for s in range(0, cand.shape[0], chunk):
+        q = cand[s:s + chunk]
+        d2 = ((q[:, None, :] - surf[None, :, :]) ** 2).sum(-1)
+        out[s:s + chunk] = torch.sqrt(d2.min(dim=1).values)
+    return out
+
+
+def mcis_weight(d, sigma=MCIS_SIGMA, eps=MCIS_EPS):
+    """Step 2: w_j = max(exp(-d_j^2 / (2 sigma^2)), eps)."""
+    return torch.clamp(torch.exp(-as64(d) ** 2 / (2.0 * sigma * sigma)), min=eps)
+
+
+def mcis_select_instance(cand, surf, u, n_sel, sigma=MCIS_SIGMA, eps=MCIS_EPS):
+    """Steps 1-4 for one instance: indices (ascending) of the n_sel sampled
+    candidates, and the distances d."""
+    d = mcis_distance(cand, surf)
+    w = mcis_weight(d, sigma, eps)
+    p = w / w.sum()                                   # step 3
+    keys = torch.log(as64(u)) / p                     # step 4, exponential keys
+    order = torch.sort(-keys, stable=True).indices    # largest first, ties by index
+    return torch.sort(order[:int(n_sel)]).values, d
+
+
+def mcis(cand, cand_off, surf, surf_off, u, n_sel, sigma=MCIS_SIGMA, eps=MCIS_EPS):
+    """All instances; step 5 is the union of the selections.  Returns the
+    selected global candidate indices (instance by instance, ascending) and
+    d for every candidate."""
+    sel, dist = [], []
+    for k in range(len(n_sel)):
+        c0, c1 = int(cand_off[k]), int(cand_off[k + 1])
+        s0, s1 = int(surf_off[k]), int(surf_off[k + 1])
+        idx, d = mcis_select_instance(as64(cand)[c0:c1], as64(surf)[s0:s1], as64(u)[c0:c1], n_sel[k], sigma, eps)
+        sel.append(idx + c0)
+        dist.append(d)
+    return torch.cat(sel) if sel else torch.zeros(0, dtype=torch.int64), torch.cat(dist) if dist else None

@@ -606,3 +606,76 @@ def test_bgdo_key_frames_are_stored_before_their_substeps():
     out = O.bgdo(state0, p, frames=4, substeps_per_frame=S, key_frames=[0, 2, 3])
     terms = [O.bgdo_key_frame(O.step_n(state0, p, k * S), p)[2] for k in (0, 2, 3)]
     assert torch.allclose(out, p.log_E - sum(terms) / 3, rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# MCIS interior filling (Sec. 4.1)
+# --------------------------------------------------------------------------
+
+def test_mcis_distance_matches_kdtree():
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(40)
+    surf = rng.uniform(0.2, 0.8, (3000, 3))
+    cand = rng.uniform(0.1, 0.9, (5000, 3))
+    d = O.mcis_distance(torch.tensor(cand), torch.tensor(surf)).numpy()
+    ref, _ = cKDTree(surf).query(cand, k=1)
+    np.testing.assert_allclose(d, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_mcis_weight_closed_forms():
+    s = O.MCIS_SIGMA
+    d = torch.tensor([0.0, s, 2 * s, 1.0], dtype=F64)
+    w = O.mcis_weight(d)
+    expect = torch.tensor([1.0, math.exp(-0.5), math.exp(-2.0), 1e-6], dtype=F64)
+    assert torch.allclose(w, expect, rtol=1e-15, atol=0)
+
+
+def _mcis_toy(rng, dists):
+    """Candidates on the x axis at the given distances from one surface point."""
+    surf = torch.tensor([[0.5, 0.5, 0.5]], dtype=F64)
+    cand = torch.tensor([[0.5 + d, 0.5, 0.5] for d in dists], dtype=F64)
+    w = O.mcis_weight(torch.tensor(dists, dtype=F64))
+    return surf, cand, (w / w.sum()).numpy()
+
+
+def test_mcis_single_draw_follows_p():
+    """n = 1: the exponential-key race picks candidate j with probability p_j."""
+    rng = np.random.default_rng(41)
+    surf, cand, p = _mcis_toy(rng, [0.0, 0.01, 0.02, 0.03, 0.2])
+    T = 20000
+    counts = np.zeros(len(p))
+    for _ in range(T):
+        idx, _ = O.mcis_select_instance(cand, surf, torch.tensor(rng.uniform(0, 1, len(p))), 1)
+        counts[int(idx[0])] += 1
+    sd = np.sqrt(T * p * (1 - p))
+    assert np.all(np.abs(counts - T * p) <= 4.5 * sd + 1), (counts, T * p)
+
+
+def test_mcis_two_draws_without_replacement_inclusion():
+    """n = 2 of 3: successive sampling without replacement includes j with
+    probability p_j + sum_{i != j} p_i p_j / (1 - p_i)."""
+    rng = np.random.default_rng(42)
+    surf, cand, p = _mcis_toy(rng, [0.0, 0.015, 0.03])
+    incl = np.array([p[j] + sum(p[i] * p[j] / (1 - p[i]) for i in range(3) if i != j) for j in range(3)])
+    T = 20000
+    counts = np.zeros(3)
+    for _ in range(T):
+        idx, _ = O.mcis_select_instance(cand, surf, torch.tensor(rng.uniform(0, 1, 3)), 2)
+        assert len(set(idx.tolist())) == 2
+        counts[idx.numpy()] += 1
+    sd = np.sqrt(T * incl * (1 - incl))
+    assert np.all(np.abs(counts - T * incl) <= 4.5 * sd + 1), (counts, T * incl)
+
+
+def test_mcis_instances_union_and_limits():
+    rng = np.random.default_rng(43)
+    surf = torch.tensor(rng.uniform(0.3, 0.7, (400, 3)))
+    cand = torch.tensor(rng.uniform(0.3, 0.7, (900, 3)))
+    u = torch.tensor(rng.uniform(0, 1, 900))
+    surf_off, cand_off = [0, 150, 150, 400], [0, 300, 300, 900]
+    sel, d = O.mcis(cand, cand_off, surf, surf_off, u, [300, 0, 17])
+    assert sel[:300].tolist() == list(range(300))          # n_k = all candidates
+    assert len(sel) == 317 and len(set(sel.tolist())) == 317
+    assert all(300 <= j < 900 for j in sel[300:].tolist())
+    # the instance's own surface sets the distance
+    assert torch.allclose(d[300:], O.mcis_distance(cand[300:], surf[150:]))
