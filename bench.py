@@ -67,7 +67,7 @@ def measured_traffic(n_particles):
 
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
-               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched --no-bgdo --no-models")
+               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
@@ -162,6 +162,48 @@ def per_model_timing(sc, steps=3, substeps=10):
     return out
 
 
+def mcis_timing(reps=3):
+    """MCIS interior fill (Sec. 4.1) at the scale of the 2M workload: 12
+    ellipsoid instances, 1M surface points, 8M inside candidates, 1M drawn.
+    Wall time of mpm_mcis_select (it synchronises), best of `reps` after a
+    warm-up; the oracle on a bounded sample of one instance beside it."""
+    import numpy as np
+    import torch
+
+    from oracle import mpm_oracle as O
+    from paper_2602_01723_amd import binding as B
+    from paper_2602_01723_amd import scenes
+    rng = np.random.default_rng(11)
+    ns = np.exp(rng.uniform(math.log(2e4), math.log(2e5), 12))
+    ns = np.floor(ns * (1_000_000 / ns.sum())).astype(np.int64)
+    ns[0] += 1_000_000 - ns.sum()
+    d = scenes.mcis_inputs(seed=12, n_shell=tuple(int(v) for v in ns), cand_per_shell=8.0, fill_frac=0.125,
+                           r_range=(0.05, 0.12))
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a.T)).cuda()
+    surf, cand, u = dev(d["surface"]), dev(d["candidates"]), torch.as_tensor(d["u"]).cuda()
+    args = (surf, d["surface_offsets"], cand, d["candidate_offsets"], u, d["n_select"])
+    B.mpm_mcis_select(*args)
+    best = math.inf
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.mpm_mcis_select(*args)
+        best = min(best, time.perf_counter() - t0)
+    M = int(d["candidate_offsets"][-1])
+    # oracle: the first 4000 surface points and 20000 candidates of instance 0
+    so, co = d["surface_offsets"], d["candidate_offsets"]
+    s_n, c_n = min(4000, int(so[1])), min(20000, int(co[1]))
+    t0 = time.perf_counter()
+    O.mcis_select_instance(d["candidates"][:c_n], d["surface"][:s_n], d["u"][:c_n], c_n // 8)
+    t_cpu = time.perf_counter() - t0
+    return {"workload": "12 ellipsoid instances, 1,000,000 surface points, 8,000,000 inside candidates, "
+                        "1,000,000 drawn (sigma 0.02, eps 1e-6)",
+            "seconds": best, "candidates_per_s": M / best,
+            "oracle": {"candidates_per_s": c_n / t_cpu, "cores": torch.get_num_threads(),
+                       "sample": f"{c_n} candidates against {s_n} surface points (brute force, {t_cpu:.1f} s)"},
+            "paper_context": "IPF with MCIS 22 s per scene on an RTX A6000 (with DBSCAN and hulls; not comparable)"}
+
+
 def copy_probe():
     """A plain 256 MiB device copy, the calibration point of the HBM counters."""
     import torch
@@ -254,6 +296,8 @@ def main():
     ap.add_argument("--n-total", type=int, default=2_000_000)
     ap.add_argument("--no-bgdo", action="store_true", help="skip the BGDO iteration timing")
     ap.add_argument("--no-models", action="store_true", help="skip the per-model fused-kernel timing")
+    ap.add_argument("--no-mcis", action="store_true", help="skip the MCIS interior-fill timing")
+    ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
     args = ap.parse_args()
@@ -274,6 +318,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.mcis_only:
+        print(json.dumps({"mcis": mcis_timing()}), flush=True)
+        return
     copy_probe()
     log("generating workload ...")
     t = time.perf_counter()
@@ -336,6 +383,12 @@ def main():
         models = per_model_timing(sc)
         log("  " + ", ".join(f"{k} {v['fused_us']} us" for k, v in models.items()))
         torch.cuda.empty_cache()
+    mcis = None
+    if not args.no_mcis:
+        log("MCIS interior fill ...")
+        mcis = mcis_timing()
+        log(f"  {mcis['seconds'] * 1e3:.1f} ms for 8M candidates")
+        torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
         log("batched vs plain forward + adjoint ...")
@@ -374,6 +427,7 @@ def main():
         "batched_fwd_bwd": batched,
         "bgdo": bgdo,
         "per_model_fused": models,
+        "mcis": mcis,
     }
     print(json.dumps(out), flush=True)
 

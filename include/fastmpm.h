@@ -245,6 +245,37 @@ int mpm_bgdo_accumulate(mpm_ctx ctx, const mpm_particles* key, const float* F_ne
 /* BGDO update: log_E[p] -= g_total[p] / n_keys (n_keys >= 1). */
 int mpm_bgdo_apply(mpm_ctx ctx, float* log_E, const float* g_total, int32_t n_keys, void* stream);
 
+/* Interior filling by instance-aware Monte Carlo importance sampling (Sec. 4.1,
+ * MCIS steps 1-5).  Context-free.  n_instances = K instances; instance k owns
+ *   surface points     surface[3][S]    columns [surface_offsets[k], surface_offsets[k+1])
+ *   candidate points   candidates[3][M] columns [candidate_offsets[k], candidate_offsets[k+1])
+ *                      (points the caller's occupancy test kept inside the instance)
+ *   uniforms           u[M] (float64, in (0, 1]), one per candidate
+ *   count              n_select[k], 0 <= n_select[k] <= the instance's candidates
+ * (surface, candidates, u, out_index, d_out: device; the three offset /
+ * count arrays: host, int64, offsets starting at 0).  Every point must lie
+ * in [0, 1]^3 (scenes are normalised to the unit cube, App. C).
+ * For every candidate j of instance k, with r_s = sigma sqrt(-2 ln eps):
+ *   d_j = distance to the nearest surface point of instance k (+inf when
+ *         none lies within r_s: the weight is then at its floor either way)
+ *   w_j = max(exp(-d_j^2 / (2 sigma^2)), eps)      (the paper: sigma 0.02, eps 1e-6)
+ * and the n_select[k] candidates with the largest keys log(u_j) / w_j (the
+ * exponential keys of sampling without replacement by p = w / sum w, whose
+ * common factor does not change the order; equal keys by lower index) are
+ * written, ascending, to out_index[o_k .. o_k + n_select[k]) with
+ * o_k = n_select[0] + ... + n_select[k-1].  d_out (optional, may be NULL)
+ * receives d_j.  workspace: device memory of the size
+ * mpm_mcis_workspace_size gives, overwritten.  Runs on `stream` and
+ * synchronises it before returning.  MPM_EINVAL for bad sizes, offsets or
+ * counts, a missing workspace, or (found on the device) points outside the
+ * unit cube or u outside (0, 1]; MPM_EDEVICE for a HIP failure. */
+int mpm_mcis_workspace_size(int32_t n_instances, int64_t n_surface, int64_t n_candidates, double sigma, double eps,
+                            size_t* bytes);
+int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* surface_offsets,
+                    const float* candidates, const int64_t* candidate_offsets, const double* u,
+                    const int64_t* n_select, double sigma, double eps, void* workspace, size_t workspace_bytes,
+                    int64_t* out_index, double* d_out, void* stream);
+
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, by class: 0 fused G2P+P2G substep kernel, 1 P2G-only kernel,
  * 2 G2P-only kernel, 3 sort and permute, 4 grid clear, 5 gather from /

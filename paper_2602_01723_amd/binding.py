@@ -25,7 +25,8 @@ EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "m
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
             "mpm_set_tuning", "mpm_get_tuning", "mpm_autotune", "mpm_graph_begin", "mpm_graph_end",
             "mpm_graph_launch", "mpm_graph_destroy", "mpm_position_loss_grad", "mpm_bgdo_accumulate",
-            "mpm_bgdo_apply", "mpm_profile", "mpm_profile_read", "mpm_destroy")
+            "mpm_bgdo_apply", "mpm_mcis_workspace_size", "mpm_mcis_select", "mpm_profile", "mpm_profile_read",
+            "mpm_destroy")
 PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io", "unused",
                    "other_fill")
 
@@ -98,6 +99,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_graph_launch": (ctypes.c_int, [vp, vp]),
         "mpm_bgdo_accumulate": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp, ctypes.c_float, vp, vp, vp, vp]),
         "mpm_bgdo_apply": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+        "mpm_mcis_workspace_size": (ctypes.c_int, [i32, i64, i64, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.POINTER(sz)]),
+        "mpm_mcis_select": (ctypes.c_int, [i32, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64), vp,
+                                           ctypes.POINTER(i64), ctypes.c_double, ctypes.c_double, vp, sz, vp, vp,
+                                           vp]),
         "mpm_graph_destroy": (ctypes.c_int, [vp]),
         "mpm_profile": (ctypes.c_int, [vp, i32]),
         "mpm_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -357,6 +363,35 @@ def mpm_bgdo_accumulate(ctx: Context, key: "Particles", F_next, delta_target, g_
 def mpm_bgdo_apply(ctx: Context, log_E, g_total, n_keys, stream=None):
     rc = load().mpm_bgdo_apply(ctx.handle, _ptr(log_E), _ptr(g_total), int(n_keys), _stream(stream))
     _check(ctx, rc, "mpm_bgdo_apply")
+
+
+def mpm_mcis_select(surface, surface_offsets, candidates, candidate_offsets, u, n_select, sigma=0.02, eps=1e-6,
+                    want_distance=False, stream=None):
+    """MCIS interior filling (see include/fastmpm.h).  surface [3, S] and
+    candidates [3, M] float32 device tensors, u [M] float64 device tensor,
+    offsets and counts as integer sequences.  Returns (selected candidate
+    indices, int64 device tensor instance by instance, and d [M] float64 or
+    None)."""
+    import torch
+    lib = load()
+    K = len(n_select)
+    so = (ctypes.c_int64 * (K + 1))(*[int(v) for v in surface_offsets])
+    co = (ctypes.c_int64 * (K + 1))(*[int(v) for v in candidate_offsets])
+    ns = (ctypes.c_int64 * K)(*[int(v) for v in n_select])
+    nbytes = ctypes.c_size_t()
+    rc = lib.mpm_mcis_workspace_size(K, int(so[K]), int(co[K]), float(sigma), float(eps), ctypes.byref(nbytes))
+    if rc:
+        _check(None, rc, "mpm_mcis_workspace_size")
+    dev = candidates.device if hasattr(candidates, "device") else "cuda"
+    ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(max(sum(int(v) for v in n_select), 1), dtype=torch.int64, device=dev)
+    d = torch.empty(int(co[K]), dtype=torch.float64, device=dev) if want_distance else None
+    rc = lib.mpm_mcis_select(K, _ptr(surface) if int(so[K]) else None, so, _ptr(candidates), co, _ptr(u), ns,
+                             float(sigma), float(eps), _ptr(ws), int(nbytes.value), _ptr(out), _ptr(d),
+                             _stream(stream))
+    if rc:
+        _check(None, rc, "mpm_mcis_select")
+    return out[:sum(int(v) for v in n_select)], d
 
 
 def mpm_profile(ctx: Context, enable: bool = True):

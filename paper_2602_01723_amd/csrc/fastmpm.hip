@@ -18,6 +18,7 @@
 #include "fastmpm.h"
 #include "mpm_adjoint.hpp"
 #include "mpm_kernels.hpp"
+#include "mcis_kernels.hpp"
 
 using fmpm::kBlock;
 
@@ -965,3 +966,211 @@ int mpm_destroy(mpm_ctx ctx) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// MCIS interior filling (context-free; the caller supplies the workspace)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct McisLayout {
+  fmpm::McisGrid g;
+  int64_t fine_cells = 0, coarse_cells = 0;  // over all instances
+  size_t so = 0, co = 0, out_off = 0, prefix = 0, rank = 0, start = 0, bsum_start = 0, coarse = 0, skey = 0,
+         sslot = 0, sorted = 0, cstart = 0, ckey = 0, cslot = 0, corder = 0, okey = 0, eq = 0, sel = 0, bsum_m = 0,
+         hist = 0, bad = 0, total = 0;
+};
+
+constexpr int64_t kMcisMaxCells = (int64_t)1 << 27;  // per cell array (0.5 GB of uint32)
+
+int mcis_layout(int32_t K, int64_t S, int64_t M, double sigma, double eps, McisLayout& L) {
+  if (K < 1 || S < 0 || M < 0 || M >= ((int64_t)1 << 32) || S >= ((int64_t)1 << 32)) return MPM_EINVAL;
+  if (!(sigma > 0.0) || !(eps > 0.0 && eps < 1.0) || !std::isfinite(sigma)) return MPM_EINVAL;
+  const double rs = sigma * std::sqrt(-2.0 * std::log(eps)) * (1.0 + 1e-9);
+  L.g.hc = rs * (1.0 + 1e-9);
+  L.g.r2 = rs * rs;
+  L.g.gc = (int)std::max(1.0, std::ceil(1.0 / L.g.hc));
+  L.coarse_cells = (int64_t)K * L.g.gc * L.g.gc * L.g.gc;
+  // the finest grid (most rings per search radius) that stays within the cell budget
+  for (int rings = fmpm::kMcisRings; rings >= 1; --rings) {
+    L.g.rings = rings;
+    L.g.hf = rs * (1.0 + 1e-9) / rings;
+    L.g.gf = (int)std::max(1.0, std::ceil(1.0 / L.g.hf));
+    L.fine_cells = (int64_t)K * L.g.gf * L.g.gf * L.g.gf;
+    if (L.fine_cells < kMcisMaxCells) break;
+  }
+  if (L.fine_cells >= kMcisMaxCells || L.coarse_cells >= kMcisMaxCells) return MPM_EINVAL;  // sigma too small
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const int64_t nb_start = (L.fine_cells + 2 + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  const int64_t nb_m = (M + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  L.so = take(8 * (size_t)(K + 1));
+  L.co = take(8 * (size_t)(K + 1));
+  L.out_off = take(8 * (size_t)K);
+  L.prefix = take(8 * (size_t)K);
+  L.rank = take(8 * (size_t)K);
+  L.start = take(4 * (size_t)(L.fine_cells + 1));
+  L.bsum_start = take(4 * (size_t)std::max<int64_t>(nb_start, 1));
+  L.coarse = take(4 * (size_t)L.coarse_cells);
+  L.skey = take(4 * (size_t)std::max<int64_t>(S, 1));
+  L.sslot = take(4 * (size_t)std::max<int64_t>(S, 1));
+  L.sorted = take(16 * (size_t)std::max<int64_t>(S, 1));
+  L.cstart = take(4 * (size_t)(L.fine_cells + 2));  // one more bin for out-of-domain candidates
+  L.ckey = take(4 * (size_t)std::max<int64_t>(M, 1));
+  L.cslot = take(4 * (size_t)std::max<int64_t>(M, 1));
+  L.corder = take(4 * (size_t)std::max<int64_t>(M, 1));
+  L.okey = take(8 * (size_t)std::max<int64_t>(M, 1));
+  L.eq = take(4 * (size_t)std::max<int64_t>(M, 1));
+  L.sel = take(4 * (size_t)std::max<int64_t>(M, 1));
+  L.bsum_m = take(4 * (size_t)std::max<int64_t>(nb_m, 1));
+  L.hist = take(4 * 256 * (size_t)K);
+  L.bad = take(8);
+  L.total = off;
+  return MPM_OK;
+}
+
+#define MCIS_TRY(call)                                  \
+  do {                                                  \
+    if ((call) != hipSuccess) {                         \
+      (void)hipGetLastError();                          \
+      return MPM_EDEVICE;                               \
+    }                                                   \
+  } while (0)
+
+int mcis_fill(void* p, int64_t count, hipStream_t s) {
+  if (count <= 0) return MPM_OK;
+  const int64_t n4 = std::max<int64_t>(count >> 2, 4);
+  fmpm::k_fill_u32<<<blocks_for(n4, 256), 256, 0, s>>>((uint32_t*)p, 0u, count, nullptr);
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EDEVICE;
+}
+
+int mcis_scan(uint32_t* data, uint32_t* bsum, int64_t n, hipStream_t s) {
+  const int64_t nb = (n + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  fmpm::k_scan_reduce<<<(unsigned)nb, fmpm::kScanThreads, 0, s>>>(data, bsum, n);
+  fmpm::k_scan_top<<<1, fmpm::kScanThreads, 0, s>>>(bsum, nb);
+  fmpm::k_scan_apply<<<(unsigned)nb, fmpm::kScanThreads, 0, s>>>(data, bsum, n);
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EDEVICE;
+}
+
+}  // namespace
+
+int mpm_mcis_workspace_size(int32_t n_instances, int64_t n_surface, int64_t n_candidates, double sigma, double eps,
+                            size_t* bytes) {
+  if (!bytes) return MPM_EINVAL;
+  McisLayout L;
+  const int rc = mcis_layout(n_instances, n_surface, n_candidates, sigma, eps, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return MPM_OK;
+}
+
+int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* surface_offsets,
+                    const float* candidates, const int64_t* candidate_offsets, const double* u,
+                    const int64_t* n_select, double sigma, double eps, void* workspace, size_t workspace_bytes,
+                    int64_t* out_index, double* d_out, void* stream) {
+  const int K = n_instances;
+  if (K < 1 || !surface_offsets || !candidate_offsets || !n_select) return MPM_EINVAL;
+  const int64_t S = surface_offsets[K], M = candidate_offsets[K];
+  if (surface_offsets[0] != 0 || candidate_offsets[0] != 0) return MPM_EINVAL;
+  std::vector<int64_t> out_off(K), prefix(K), rank(K);
+  int64_t total_sel = 0;
+  for (int k = 0; k < K; ++k) {
+    const int64_t ns = surface_offsets[k + 1] - surface_offsets[k], nc = candidate_offsets[k + 1] - candidate_offsets[k];
+    if (ns < 0 || nc < 0 || n_select[k] < 0 || n_select[k] > nc) return MPM_EINVAL;
+    out_off[k] = total_sel;
+    total_sel += n_select[k];
+    if (n_select[k] == 0) {  // nothing: a threshold above every key
+      prefix[k] = (int64_t)~0ull;
+      rank[k] = 0;
+    } else if (n_select[k] == nc) {  // everything: every valid key is above 0
+      prefix[k] = 0;
+      rank[k] = 0;
+    } else {
+      prefix[k] = 0;
+      rank[k] = n_select[k];
+    }
+  }
+  McisLayout L;
+  int rc = mcis_layout(K, S, M, sigma, eps, L);
+  if (rc) return rc;
+  if (M == 0) return MPM_OK;
+  if (!candidates || !u || !out_index || (S > 0 && !surface)) return MPM_EINVAL;
+  if (!workspace || workspace_bytes < L.total) return MPM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = static_cast<char*>(workspace);
+  auto at = [&](size_t o) { return static_cast<void*>(w + o); };
+  int64_t* d_so = (int64_t*)at(L.so);
+  int64_t* d_co = (int64_t*)at(L.co);
+  int64_t* d_out_off = (int64_t*)at(L.out_off);
+  uint64_t* d_prefix = (uint64_t*)at(L.prefix);
+  int64_t* d_rank = (int64_t*)at(L.rank);
+  uint32_t* d_start = (uint32_t*)at(L.start);
+  uint32_t* d_coarse = (uint32_t*)at(L.coarse);
+  uint32_t* d_skey = (uint32_t*)at(L.skey);
+  uint32_t* d_sslot = (uint32_t*)at(L.sslot);
+  float4* d_sorted = (float4*)at(L.sorted);
+  uint64_t* d_okey = (uint64_t*)at(L.okey);
+  uint32_t* d_eq = (uint32_t*)at(L.eq);
+  uint32_t* d_sel = (uint32_t*)at(L.sel);
+  uint32_t* d_hist = (uint32_t*)at(L.hist);
+  unsigned long long* d_bad = (unsigned long long*)at(L.bad);
+  uint32_t* d_cstart = (uint32_t*)at(L.cstart);
+  uint32_t* d_corder = (uint32_t*)at(L.corder);
+
+  MCIS_TRY(hipMemcpyAsync(d_so, surface_offsets, 8 * (size_t)(K + 1), hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_co, candidate_offsets, 8 * (size_t)(K + 1), hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_out_off, out_off.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_prefix, prefix.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_rank, rank.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
+  if ((rc = mcis_fill(d_start, L.fine_cells + 1, s)) || (rc = mcis_fill(d_cstart, L.fine_cells + 2, s)) ||
+      (rc = mcis_fill(d_coarse, L.coarse_cells, s)) ||
+      (rc = mcis_fill(d_hist, 256 * (int64_t)K, s)) || (rc = mcis_fill(d_bad, 2, s)))
+    return rc;
+  // surface points into fine-cell order
+  if (S > 0) {
+    fmpm::k_mcis_bin_surface<<<blocks_for(S, 256), 256, 0, s>>>(surface, S, d_so, K, L.g, d_start, d_coarse, d_skey,
+                                                                d_sslot, d_bad);
+    MCIS_TRY(hipGetLastError());
+  }
+  if ((rc = mcis_scan(d_start, (uint32_t*)at(L.bsum_start), L.fine_cells + 1, s))) return rc;
+  if (S > 0) {
+    fmpm::k_mcis_place_surface<<<blocks_for(S, 256), 256, 0, s>>>(surface, S, d_skey, d_sslot, d_start, d_sorted);
+    MCIS_TRY(hipGetLastError());
+  }
+  // candidates into fine-cell order
+  fmpm::k_mcis_bin_candidates<<<blocks_for(M, 256), 256, 0, s>>>(candidates, M, d_co, K, L.g, d_cstart,
+                                                                 (uint32_t*)at(L.ckey), (uint32_t*)at(L.cslot));
+  MCIS_TRY(hipGetLastError());
+  if ((rc = mcis_scan(d_cstart, (uint32_t*)at(L.bsum_start), L.fine_cells + 2, s))) return rc;
+  fmpm::k_mcis_place_candidates<<<blocks_for(M, 256), 256, 0, s>>>(M, (uint32_t*)at(L.ckey), (uint32_t*)at(L.cslot),
+                                                                   d_cstart, d_corder);
+  MCIS_TRY(hipGetLastError());
+  // steps 1, 2 and the keys
+  fmpm::k_mcis_keys<<<blocks_for(M, 256), 256, 0, s>>>(candidates, M, d_co, K, u, L.g, sigma, eps, d_coarse, d_start,
+                                                       d_sorted, d_corder, d_okey, d_out, d_bad);
+  MCIS_TRY(hipGetLastError());
+  // radix select of each instance's n-th largest key, 8 digits of 8 bits
+  const unsigned hist_blocks = (unsigned)std::min<int64_t>((M + fmpm::kMcisChunk - 1) / fmpm::kMcisChunk, 2048);
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    fmpm::k_mcis_hist<<<hist_blocks, 256, 0, s>>>(d_okey, M, d_co, K, d_prefix, d_rank, shift, d_hist);
+    fmpm::k_mcis_pick<<<blocks_for(K, 64), 64, 0, s>>>(K, shift, d_hist, d_prefix, d_rank);
+    MCIS_TRY(hipGetLastError());
+  }
+  // ties by index, then ordered compaction
+  fmpm::k_mcis_eq<<<blocks_for(M, 256), 256, 0, s>>>(d_okey, M, d_co, K, d_prefix, d_eq);
+  MCIS_TRY(hipGetLastError());
+  if ((rc = mcis_scan(d_eq, (uint32_t*)at(L.bsum_m), M, s))) return rc;
+  fmpm::k_mcis_sel<<<blocks_for(M, 256), 256, 0, s>>>(d_okey, M, d_co, K, d_prefix, d_rank, d_eq, d_sel);
+  MCIS_TRY(hipGetLastError());
+  if ((rc = mcis_scan(d_sel, (uint32_t*)at(L.bsum_m), M, s))) return rc;
+  fmpm::k_mcis_write<<<blocks_for(M, 256), 256, 0, s>>>(d_okey, M, d_co, K, d_prefix, d_rank, d_eq, d_sel, d_out_off,
+                                                        out_index);
+  MCIS_TRY(hipGetLastError());
+  unsigned long long bad = 0;
+  MCIS_TRY(hipMemcpyAsync(&bad, d_bad, 8, hipMemcpyDeviceToHost, s));
+  MCIS_TRY(hipStreamSynchronize(s));
+  return bad ? MPM_EINVAL : MPM_OK;
+}

@@ -410,3 +410,43 @@ def random_state(rng, n, grid_res, spread=0.3, vel=0.5, cgrad=2.0, fdev=0.05, ce
     C = rng.normal(0, cgrad, (n, 3, 3)).astype(np.float32)
     F = (np.eye(3) + rng.normal(0, fdev, (n, 3, 3))).astype(np.float32)
     return x, v, C, F
+
+
+def mcis_inputs(seed=7, n_shell=(2000, 3000, 1500), cand_per_shell=2.0, fill_frac=0.5, r_range=(0.06, 0.16),
+                empty_instances=()):
+    """Inputs of the MCIS interior fill (Sec. 4.1) for ellipsoid instances:
+    surface points on each shell (the Gaussian centres), candidates drawn
+    uniformly in the instance's box and kept if inside the ellipsoid (the
+    analytic occupancy test standing in for hull + ray casting), one uniform
+    u in (0, 1] per candidate, and n_k = fill_frac x candidates.  Instances
+    listed in ``empty_instances`` get no surface points.  Returns a dict of
+    NumPy arrays: surface [S, 3], surface_offsets [K+1], candidates [M, 3],
+    candidate_offsets [K+1], u [M], n_select [K]."""
+    rng = np.random.default_rng(seed)
+    surf, cand, so, co, nsel = [], [], [0], [0], []
+    for k, ns in enumerate(n_shell):
+        axes = rng.uniform(r_range[0], r_range[1], 3)
+        rot = haar_rotation(rng)
+        half = np.sqrt(((rot * axes[None, :]) ** 2).sum(1))
+        centre = rng.uniform(half + 0.01, 1.0 - half - 0.01)
+        d = rng.standard_normal((ns, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        shell = centre + (d * axes) @ rot.T
+        want = int(cand_per_shell * ns)
+        pts = []
+        while sum(len(p) for p in pts) < want:
+            q = centre + rng.uniform(-1.0, 1.0, (2 * want, 3)) * half
+            loc = (q - centre) @ rot / axes
+            pts.append(q[(loc ** 2).sum(1) < 1.0])
+        c = np.concatenate(pts)[:want]
+        if k not in empty_instances:
+            surf.append(shell)
+        cand.append(c)
+        so.append(so[-1] + (0 if k in empty_instances else ns))
+        co.append(co[-1] + len(c))
+        nsel.append(int(fill_frac * len(c)))
+    M = co[-1]
+    return dict(surface=np.concatenate(surf).astype(np.float32) if surf else np.zeros((0, 3), np.float32),
+                surface_offsets=np.array(so, np.int64), candidates=np.concatenate(cand).astype(np.float32),
+                candidate_offsets=np.array(co, np.int64), u=1.0 - rng.uniform(0.0, 1.0, M),
+                n_select=np.array(nsel, np.int64))
