@@ -298,6 +298,8 @@ def main():
     ap.add_argument("--no-models", action="store_true", help="skip the per-model fused-kernel timing")
     ap.add_argument("--no-mcis", action="store_true", help="skip the MCIS interior-fill timing")
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched vs plain forward + adjoint and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
     args = ap.parse_args()
@@ -320,6 +322,9 @@ def main():
     torch.cuda.set_device(0)
     if args.mcis_only:
         print(json.dumps({"mcis": mcis_timing()}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_fwd_bwd": batched_vs_plain()}), flush=True)
         return
     copy_probe()
     log("generating workload ...")

@@ -265,6 +265,7 @@ struct TapeLayout {
   int64_t n_ckpt, K;
   float *ckpt, *seg, *adj, *adjc, *gl, *gn, *lnE, *nu;
   float4* vhb;
+  float4* grids;  // K grids (mv, m): the P2G result of each recomputed state of a segment
   size_t bytes;
 };
 
@@ -288,6 +289,7 @@ TapeLayout tape_layout(mpm_ctx c, int32_t n_steps, int32_t K, void* base) {
   t.lnE = take(N);
   t.nu = take(N);
   t.vhb = reinterpret_cast<float4*>(take(4 * c->nodes));
+  t.grids = reinterpret_cast<float4*>(take((int64_t)K * 4 * c->nodes));
   t.bytes = (size_t)(p - static_cast<char*>(base));
   return t;
 }
@@ -605,8 +607,10 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
                                               p->mat_id, ctx->perm, N);
     fmpm::k_gather_lnE_nu<<<gp, 256, 0, s>>>(tl.lnE, tl.nu, p->log_E, p->nu, ctx->perm, N);
     LAUNCH_CHECK(ctx, "backward gather");
-    // (2) recompute the segment: slot j holds the state of substep k0 + j;
-    // the fused kernel reads slot j and writes slot j + 1
+    // (2) recompute the segment: slot j holds the state of substep k0 + j
+    // and grid slot j its P2G (the grid the forward pass read at that
+    // substep); the fused kernel reads slot j and grid j, writes slot j + 1
+    // and grid j + 1
     auto args_for = [&](int j_in, int j_out) {
       fmpm::SubstepArgs a = make_args(ctx);
       float* si = slot(j_in);
@@ -621,25 +625,24 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       a.Fo = so + 15 * N;
       return a;
     };
-    rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, -1, ctx->work_counter);
+    auto gslot = [&](int j) { return tl.grids + (int64_t)j * ctx->nodes; };
+    rc = fill_u32(ctx, gslot(0), 4 * ctx->nodes, s, -1, ctx->work_counter);
     if (rc) return rc;
     {
       fmpm::SubstepArgs a = args_for(0, 0);
-      a.grid_out = ctx->grid[0];
+      a.grid_out = gslot(0);
       fmpm::k_substep<fmpm::kP2G><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(ctx, "recompute P2G");
     }
-    int cur = 0;
     for (int j = 0; j + 1 < L; ++j) {
-      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, -1, ctx->work_counter);
+      rc = fill_u32(ctx, gslot(j + 1), 4 * ctx->nodes, s, -1, ctx->work_counter);
       if (rc) return rc;
       fmpm::SubstepArgs a = args_for(j, j + 1);
-      a.grid_in = ctx->grid[cur];
-      a.grid_out = ctx->grid[1 - cur];
+      a.grid_in = gslot(j);
+      a.grid_out = gslot(j + 1);
       a.write_vc = 1;
       fmpm::k_substep<fmpm::kFused><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(ctx, "recompute substep");
-      cur = 1 - cur;
     }
     // (3) adjoint of the segment's final state, in sorted order
     fmpm::k_gather_or_zero<<<gp, 256, 0, s>>>(tl.adj, tl.adjc, ctx->perm, 24, N);
@@ -650,12 +653,6 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     // (4) reverse the substeps of the segment
     for (int j = L - 1; j >= 0; --j) {
       const float* st = slot(j);
-      fmpm::SubstepArgs a = args_for(j, j);
-      a.grid_out = ctx->grid[0];
-      rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, -1, ctx->work_counter);
-      if (rc) return rc;
-      fmpm::k_substep<fmpm::kP2G><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
-      LAUNCH_CHECK(ctx, "backward P2G");
       rc = fill_u32(ctx, tl.vhb, 4 * ctx->nodes, s, -1, ctx->work_counter);
       if (rc) return rc;
       fmpm::AdjArgs b{};
@@ -669,7 +666,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       b.N = N;
       b.chunk_start = ctx->chunk_start;
       b.chunk_batch = ctx->chunk_batch;
-      b.grid = ctx->grid[0];
+      b.grid = gslot(j);
       b.vhb = tl.vhb;
       b.ax = tl.adj;
       b.av = tl.adj + 3 * N;

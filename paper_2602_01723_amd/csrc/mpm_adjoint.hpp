@@ -399,12 +399,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
     block_minmax(lo, hi, red, box);
     const bool empty = box[0] > box[3];
     const int gx = box[3] - box[0] + 3, gy = box[4] - box[1] + 3, gz = box[5] - box[2] + 3;
-    const int GT = empty ? 0 : gx * gy * gz;
+    // x stride padded like the forward P2G tile (the scatter's LDS banks)
+    const int sz = gy * gz + kPadX;
+    const int GT = empty ? 0 : (gx - 1) * sz + (gy - 1) * gz + gz;
     const bool lds = !empty && GT <= it.tile_cap;
     if (lds) {
       for (int t = threadIdx.x; t < GT; t += kBlock) {
-        const int tk = t % gz, tq = t / gz;
-        const int tj = tq % gy, ti = tq / gy;
+        const int ti = t / sz, tr = t - ti * sz;
+        const int tj = min(tr / gz, gy - 1), tk = tr - (tr / gz) * gz;  // padding entries load a valid node
         const int ix = box[0] + ti, iy = box[1] + tj, iz = box[2] + tk;
         float vv[3];
         grid_velocity(a.grid[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, ga, vv);
@@ -417,7 +419,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
       }
     }
     __syncthreads();
-    const int sz = gy * gz;
     for (int sub = start; sub < end; sub += kBlock) {
       const int i = sub + (int)threadIdx.x;
       if (i >= end) break;
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
         bspline_w(f[k], w[k]);
         bspline_dw(f[k], dw[k]);
       }
-      const int a0 = ((b[0] - box[0]) * gy + (b[1] - box[1])) * gz + (b[2] - box[2]);
+      const int a0 = (b[0] - box[0]) * sz + (b[1] - box[1]) * gz + (b[2] - box[2]);
       // C' of the forward pass from the stencil's node velocities
       auto node_v = [&](int ox, int oy, int oz, float* out) {
         if (lds) {
@@ -539,8 +540,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
       for (int t = threadIdx.x; t < GT; t += kBlock) {
         const double v0 = ptile[t], v1 = ptile[kTileCapMax + t], v2 = ptile[2 * kTileCapMax + t];
         if (v0 == 0.0 && v1 == 0.0 && v2 == 0.0) continue;
-        const int tk = t % gz, tq = t / gz;
-        const int tj = tq % gy, ti = tq / gy;
+        const int ti = t / sz, tr = t - ti * sz;
+        const int tj = tr / gz, tk = tr - tj * gz;
+        if (tj >= gy) continue;  // padding
         float* gp = (float*)&a.vhb[gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk)];
         atomicAdd(gp + 0, (float)v0);
         atomicAdd(gp + 1, (float)v1);
