@@ -489,45 +489,67 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
         }
 #pragma unroll
       for (int k = 0; k < 3; ++k) vbt[k] = vb[k] + a.dt * xb[k];
-      // staggered node order (lanes of one cell hit different nodes)
+      // staggered node order (lanes of one cell hit different nodes): lane
+      // group g visits offset (k + g_axis) mod 3 at step k on each axis.  x
+      // and y loops stay rolled (register use); the z values sit in
+      // compile-time indexed tables
       const int g = (threadIdx.x & 63) % 27;
+      const int gs[3] = {g / 9, (g / 3) % 3, g % 3};
+      int roz[3];
+      float wrz[3], dwrz[3], dprz[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        roz[k] = rot3(gs[2], k);
+        wrz[k] = sel3(w[2], roz[k]);
+        dwrz[k] = inv_dx * sel3(dw[2], roz[k]);
+        dprz[k] = ((float)roz[k] - f[2]) * dx;
+      }
       float xo[3] = {xb[0], xb[1], xb[2]};
 #pragma unroll 1
-      for (int k = 0; k < 27; ++k) {
-        int o = k + g;
-        o = (o >= 27) ? o - 27 : o;
-        const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
-        float vho[3];
-        node_v(ox, oy, oz, vho);
-        const float wx = sel3(w[0], ox), wy = sel3(w[1], oy), wz = sel3(w[2], oz);
-        const float wt = wx * wy * wz;
-        const float gw[3] = {inv_dx * sel3(dw[0], ox) * wy * wz, inv_dx * wx * sel3(dw[1], oy) * wz,
-                             inv_dx * wx * wy * sel3(dw[2], oz)};
-        const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
-        float cd[3];
+      for (int kx = 0; kx < 3; ++kx) {
+        // x-axis values by selection (a rolled loop keeps register use down)
+        const int ox = rot3(gs[0], kx);
+        const float wx = sel3(w[0], ox), dwx = inv_dx * sel3(dw[0], ox), dpx = ((float)ox - f[0]) * dx;
+#pragma unroll 1
+        for (int ky = 0; ky < 3; ++ky) {
+          const int oy = rot3(gs[1], ky);
+          const float wy = sel3(w[1], oy), dwy = inv_dx * sel3(dw[1], oy), dpy = ((float)oy - f[1]) * dx;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) cd[r] = Cbt[3 * r] * dp[0] + Cbt[3 * r + 1] * dp[1] + Cbt[3 * r + 2] * dp[2];
-        float wb = 0.f, gv[3];
+          for (int kz = 0; kz < 3; ++kz) {
+            const int oz = roz[kz];
+            float vho[3];
+            node_v(ox, oy, oz, vho);
+            const float wz = wrz[kz];
+            const float wt = wx * wy * wz;
+            const float gw[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * dwrz[kz]};
+            const float dp[3] = {dpx, dpy, dprz[kz]};
+            float cd[3];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const float gval = vbt[r] + D * cd[r];
-          gv[r] = wt * gval;
-          wb += vho[r] * gval;
-        }
-        if (lds) {
-          const int t = a0 + ox * sz + oy * gz + oz;
+            for (int r = 0; r < 3; ++r)
+              cd[r] = Cbt[3 * r] * dp[0] + Cbt[3 * r + 1] * dp[1] + Cbt[3 * r + 2] * dp[2];
+            float wb = 0.f, gv[3];
 #pragma unroll
-          for (int r = 0; r < 3; ++r) atomicAdd(&ptile[r * kTileCapMax + t], (double)gv[r]);
-        } else {
-          const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-          float* gp = (float*)&a.vhb[gbase + ((int64_t)ix * n + iy) * n + iz];
+            for (int r = 0; r < 3; ++r) {
+              const float gval = vbt[r] + D * cd[r];
+              gv[r] = wt * gval;
+              wb += vho[r] * gval;
+            }
+            if (lds) {
+              const int t = a0 + ox * sz + oy * gz + oz;
 #pragma unroll
-          for (int r = 0; r < 3; ++r) atomicAdd(gp + r, gv[r]);
-        }
+              for (int r = 0; r < 3; ++r) atomicAdd(&ptile[r * kTileCapMax + t], (double)gv[r]);
+            } else {
+              const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
+              float* gp = (float*)&a.vhb[gbase + ((int64_t)ix * n + iy) * n + iz];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float ctv = Cbt[c] * vho[0] + Cbt[3 + c] * vho[1] + Cbt[6 + c] * vho[2];
-          xo[c] += wb * gw[c] - D * wt * ctv;
+              for (int r = 0; r < 3; ++r) atomicAdd(gp + r, gv[r]);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const float ctv = Cbt[c] * vho[0] + Cbt[3 + c] * vho[1] + Cbt[6 + c] * vho[2];
+              xo[c] += wb * gw[c] - D * wt * ctv;
+            }
+          }
         }
       }
 #pragma unroll
