@@ -684,7 +684,9 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::AdjItems items{ctx->dchunk_start, ctx->dchunk_batch, ctx->dn_chunks, ctx->work_counter, ctx->tile_cap};
       fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       LAUNCH_CHECK(ctx, "k_adj_g2p");
-      fmpm::k_adj_p2g<<<ctx->n_chunks, kBlock, 0, s>>>(b);
+      rc = fill_u32(ctx, ctx->work_counter, 1, s);  // the item queue again, for k_adj_p2g
+      if (rc) return rc;
+      fmpm::k_adj_p2g<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       LAUNCH_CHECK(ctx, "k_adj_p2g");
     }
     // (5) back to caller order

@@ -577,13 +577,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
 // --------------------------------------------------------------------------
 // Reverse of the grid update and of P2G, stress and Lame parameters
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
-  const int chunk = blockIdx.x;
-  const int i = a.chunk_start[chunk] + (int)threadIdx.x;
-  if (i >= a.chunk_start[chunk + 1]) return;
+// One particle of the P2G / stress reverse; node(ix, iy, iz, gm, gb) fetches
+// the node's (mv, m) and grid-velocity adjoint.
+template <typename NodeFn>
+__device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn node) {
   const int n = a.n;
   const int64_t N = a.N;
-  const int64_t gbase = (int64_t)a.chunk_batch[chunk] * n * n * n;
   const float inv_dx = (float)n, dx = 1.0f / (float)n, D = 4.0f * inv_dx * inv_dx;
   float xp[3], vp[3], Cp[9], xb[3];
   double Fd[9], Fb[9];
@@ -642,10 +641,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
     for (int o = 0; o < 27; ++o) {
       const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
       const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-      const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
-      const float4 gm = a.grid[node];
+      float4 gm, gb;
+      node(ix, iy, iz, gm, gb);
       if (!grid_active(gm.w, ix, iy, iz, n, a.bound)) continue;
-      const float4 gb = a.vhb[node];
       const float im = 1.0f / gm.w;
       const float mvb[3] = {gb.x * im, gb.y * im, gb.z * im};
       const float mb = -(gb.x * gm.x + gb.y * gm.y + gb.z * gm.z) * im * im;
@@ -696,6 +694,71 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a) {
   for (int k = 0; k < 9; ++k) {
     a.aC[k * N + i] = Cb[k];
     a.aF[k * N + i] = (float)Fb[k];
+  }
+}
+
+// Persistent over the work items of the last sort: each item's box of grid
+// nodes ((mv, m) and the grid-velocity adjoint) is staged in LDS, the
+// particles then gather from it (global memory when the box exceeds the tile).
+__global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a, AdjItems it) {
+  __shared__ float4 gm_t[kTileCapMax];
+  __shared__ float4 gb_t[kTileCapMax];
+  __shared__ int red[8 * (kBlock / 64)];
+  __shared__ int item_s;
+  const int n = a.n;
+  const int64_t N = a.N;
+  const int n_items = *it.n_items;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_s = atomicAdd(it.counter, 1);
+    __syncthreads();
+    const int item = item_s;
+    if (item >= n_items) break;
+    const int start = it.item_start[item], end = it.item_start[item + 1];
+    const int64_t gbase = (int64_t)it.item_batch[item] * n * n * n;
+    int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+      int b[3];
+      float f[3];
+      bool in = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
+      if (in) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = min(lo[k], b[k]);
+          hi[k] = max(hi[k], b[k]);
+        }
+      }
+    }
+    int box[6];
+    block_minmax(lo, hi, red, box);
+    const bool empty = box[0] > box[3];
+    const int gx = box[3] - box[0] + 3, gy = box[4] - box[1] + 3, gz = box[5] - box[2] + 3;
+    const int GT = empty ? 0 : gx * gy * gz;
+    const bool lds = !empty && GT <= it.tile_cap;
+    if (lds) {
+      for (int t = threadIdx.x; t < GT; t += kBlock) {
+        const int tk = t % gz, tq = t / gz;
+        const int tj = tq % gy, ti = tq / gy;
+        const int64_t node = gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk);
+        gm_t[t] = a.grid[node];
+        gb_t[t] = a.vhb[node];
+      }
+    }
+    __syncthreads();
+    auto fetch = [&](int ix, int iy, int iz, float4& gm, float4& gb) {
+      if (lds) {
+        const int t = ((ix - box[0]) * gy + (iy - box[1])) * gz + (iz - box[2]);
+        gm = gm_t[t];
+        gb = gb_t[t];
+      } else {
+        const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
+        gm = a.grid[node];
+        gb = a.vhb[node];
+      }
+    };
+    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) adj_p2g_particle(a, i, fetch);
   }
 }
 
