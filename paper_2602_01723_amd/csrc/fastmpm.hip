@@ -307,14 +307,18 @@ int copy_f32(mpm_ctx c, float* out, const float* in, int64_t count, hipStream_t 
   return MPM_OK;
 }
 
-// internal state (x, v, C, F planes) -> caller-order 24-plane block via pid
+// internal state (x, v, C, F planes) -> caller-order 24-plane block: a
+// gather through the inverse of pid (kept in the sort's key buffer, free
+// between sorts)
 int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
   const unsigned g = blocks_for(c->N, 256);
   const int64_t N = c->N;
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24, c->xs, c->pid, 3, N);
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24 + 3 * N, c->vs, c->pid, 3, N);
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24 + 6 * N, c->Cs, c->pid, 9, N);
-  fmpm::k_scatter_planes<<<g, 256, 0, s>>>(out24 + 15 * N, c->Fs, c->pid, 9, N);
+  int* inv = reinterpret_cast<int*>(c->keys);
+  fmpm::k_invert<<<g, 256, 0, s>>>(c->pid, inv, N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24, c->xs, inv, 3, N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24 + 3 * N, c->vs, inv, 3, N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24 + 6 * N, c->Cs, inv, 9, N);
+  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24 + 15 * N, c->Fs, inv, 9, N);
   LAUNCH_CHECK(c, "scatter_state");
   return MPM_OK;
 }
@@ -689,11 +693,15 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::k_adj_p2g<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       LAUNCH_CHECK(ctx, "k_adj_p2g");
     }
-    // (5) back to caller order
-    fmpm::k_scatter_planes<<<gp, 256, 0, s>>>(tl.adjc, tl.adj, ctx->pid, 24, N);
-    fmpm::k_scatter_add<<<gp, 256, 0, s>>>(g_log_E, tl.gl, ctx->pid, 1, N);
-    fmpm::k_scatter_add<<<gp, 256, 0, s>>>(g_nu, tl.gn, ctx->pid, 1, N);
-    LAUNCH_CHECK(ctx, "adjoint scatter");
+    // (5) back to caller order, by gathers through the inverse of pid
+    {
+      int* inv = reinterpret_cast<int*>(ctx->keys);
+      fmpm::k_invert<<<gp, 256, 0, s>>>(ctx->pid, inv, N);
+      fmpm::k_gather_planes<<<gp, 256, 0, s>>>(tl.adjc, tl.adj, inv, 24, N);
+      fmpm::k_gather_add<<<gp, 256, 0, s>>>(g_log_E, tl.gl, inv, 1, N);
+      fmpm::k_gather_add<<<gp, 256, 0, s>>>(g_nu, tl.gn, inv, 1, N);
+      LAUNCH_CHECK(ctx, "adjoint scatter");
+    }
   }
   float* gout[4] = {g_x0, g_v0, g_C0, g_F0};
   for (int k = 0; k < 4 && !rc; ++k)

@@ -770,12 +770,13 @@ __global__ void k_gather_or_zero(float* out, const float* in, const int* perm, i
   for (int c = 0; c < planes; ++c) out[c * N + j] = in ? in[c * N + s] : 0.0f;
 }
 
-// out[c][pid[j]] += in[c][j]
-__global__ void k_scatter_add(float* out, const float* in, const int* pid, int planes, int64_t N) {
+// out[c][j] += in[c][perm[j]] (back to caller order with perm the inverse of
+// the sorted-to-caller map pid: coalesced writes, random reads)
+__global__ void k_gather_add(float* out, const float* in, const int* perm, int planes, int64_t N) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
-  const int64_t d = pid[j];
-  for (int c = 0; c < planes; ++c) out[c * N + d] += in[c * N + j];
+  const int64_t s = perm[j];
+  for (int c = 0; c < planes; ++c) out[c * N + j] += in[c * N + s];
 }
 
 // log E and nu of each sorted slot

@@ -768,14 +768,6 @@ __global__ void k_iota(int* p, int64_t N) {
   if (j < N) p[j] = (int)j;
 }
 
-// out[c][pid[j]] = in[c][j]
-__global__ void k_scatter_planes(float* out, const float* in, const int* pid, int planes, int64_t N) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const int64_t d = pid[j];
-  for (int c = 0; c < planes; ++c) out[c * N + d] = in[c * N + j];
-}
-
 // grid state export: m [B n^3], mv / v [B n^3][3]
 __global__ void k_grid_export(const float4* grid, int64_t nodes, SubstepArgs a, float* m, float* mv, float* v) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
