@@ -204,6 +204,33 @@ def mcis_timing(reps=3):
             "paper_context": "IPF with MCIS 22 s per scene on an RTX A6000 (with DBSCAN and hulls; not comparable)"}
 
 
+def summarize_batched_trace(trace_csv: str) -> str:
+    """One batched evaluation from a rocprofv3 kernel trace of --batched-only:
+    the dispatches between the last two full-size position-loss kernels (the
+    backward of one graph replay and the forward of the next), per kernel."""
+    import collections
+    import csv
+    with open(trace_csv) as fh:
+        rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+    big = [i for i, r in enumerate(rows)
+           if "position_loss" in r["Kernel_Name"] and int(r["Grid_Size_X"]) >= 2_000_000]
+    if len(big) < 2:
+        raise SystemExit(f"{trace_csv}: fewer than two full-size position-loss dispatches")
+    win = rows[big[-2]:big[-1]]
+    acc = collections.defaultdict(lambda: [0, 0])
+    for r in win:
+        k = r["Kernel_Name"][:55]
+        acc[k][0] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        acc[k][1] += 1
+    tot = sum(v[0] for v in acc.values())
+    wall = int(win[-1]["End_Timestamp"]) - int(win[0]["Start_Timestamp"])
+    out = [f"window wall {wall / 1e6:.1f} ms, kernel sum {tot / 1e6:.1f} ms, dispatches {len(win)}"]
+    for k, v in sorted(acc.items(), key=lambda kv: -kv[1][0])[:14]:
+        out.append(f"{k:55s} {v[1]:6d} {v[0] / 1e6:9.2f} ms {v[0] / max(v[1], 1) / 1e3:9.1f} us "
+                   f"{100 * v[0] / tot:5.1f}%")
+    return "\n".join(out)
+
+
 def copy_probe():
     """A plain 256 MiB device copy, the calibration point of the HBM counters."""
     import torch
@@ -300,9 +327,14 @@ def main():
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched vs plain forward + adjoint and exit")
+    ap.add_argument("--summarize-batched-trace", metavar="TRACE_CSV",
+                    help="per-kernel time of one batched evaluation in a rocprofv3 trace, and exit (no GPU use)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
     args = ap.parse_args()
+    if args.summarize_batched_trace:
+        print(summarize_batched_trace(args.summarize_batched_trace))
+        return
     if args.write_traffic:
         print(json.dumps(write_traffic(*args.write_traffic, n_particles=args.n_total)))
         return
