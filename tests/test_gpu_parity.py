@@ -108,6 +108,30 @@ def test_substep_large_volume_change_models():
     assert_parity(errs)
 
 
+def test_substep_inverted_deformation_gradients():
+    """Inverted particles (det F < 0) of every elastic model: the polar
+    iteration declines them and the SVD (sign on the last singular value)
+    takes over; the J floors of the Neo-Hookean and volume models apply.
+    Singular values are kept apart so that U and V are unique."""
+    N = 2000
+    mats = [dict(elastic=e, plastic=0, yield_stress=0.0, friction_deg=0.0) for e in range(6)]
+    d = random_scene(91, N, mats=mats, cgrad=5.0)
+    rng = np.random.default_rng(92)
+    F = np.empty((N, 3, 3))
+    for p in range(N):
+        Q1, Q2 = scenes.haar_rotation(rng), scenes.haar_rotation(rng)
+        sig = np.array([rng.uniform(1.1, 1.3), rng.uniform(0.85, 1.0), rng.uniform(0.5, 0.7)])
+        if p % 2 == 0:
+            sig[2] = -sig[2]  # inverted
+        F[p] = Q1 @ np.diag(sig) @ Q2.T
+    d["F"] = F.astype(np.float32)
+    assert (np.linalg.det(F) < 0).sum() == N // 2
+    errs, diag, _, _ = run_case(d)
+    print(errs, diag, flush=True)
+    assert diag["out_of_grid"] == 0
+    assert_parity(errs)
+
+
 def test_substep_after_warmup_cube_lattice():
     sc = scenes.make_scene("cube_lattice")
     d = dict(x=sc.x, v=sc.v, C=sc.C, F=sc.F, mass=sc.mass, vol0=sc.vol0, log_E=sc.log_E, nu=sc.nu,
