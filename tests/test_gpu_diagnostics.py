@@ -89,3 +89,39 @@ def test_tuning_validation():
     p = B.Particles.from_scene(sc)
     B.mpm_step_n(ctx, p, 5)  # runs with the new settings
     assert B.mpm_get_diagnostics(ctx)["status"] == B.MPM_OK
+
+
+def test_profile_counts_launches_by_class():
+    sc = _cube()
+    ctx = B.init_from_scene(sc)
+    p = B.Particles.from_scene(sc)
+    B.mpm_step_n(ctx, p, 2)
+    torch.cuda.synchronize()
+    B.mpm_profile(ctx, True)
+    B.mpm_profile_read(ctx)  # reset
+    B.mpm_step_n(ctx, p, 10)
+    torch.cuda.synchronize()
+    prof = B.mpm_profile_read(ctx)
+    B.mpm_profile(ctx, False)
+    # one P2G-only launch, fused launches for the rest, one G2P-only launch
+    assert prof["p2g_only"][1] == 1 and prof["g2p_only"][1] == 1
+    assert prof["fused_substep"][1] == 9
+    assert all(ms > 0.0 for ms, n in prof.values() if n)
+    assert prof["caller_io"][1] >= 2  # gather from and scatter back to the caller's order
+    B.mpm_step_n(ctx, p, 3)
+    torch.cuda.synchronize()
+    assert all(n == 0 for _, n in B.mpm_profile_read(ctx).values())  # disabled: nothing recorded
+
+
+def test_position_loss_cotangent_closed_form():
+    rng = np.random.default_rng(31)
+    N = 5000
+    sc = _cube()
+    x = torch.tensor(rng.uniform(0, 1, (3, N)).astype(np.float32)).cuda()
+    xt = torch.tensor(rng.uniform(0, 1, (3, N)).astype(np.float32)).cuda()
+    w = torch.tensor(rng.uniform(0.5, 2.0, N).astype(np.float32)).cuda()
+    g = torch.empty(3, N, device="cuda")
+    ctx = B.mpm_init(16, 1e-4, sc.materials, N)
+    B.mpm_position_loss_grad(ctx, x, xt, w, g)
+    torch.cuda.synchronize()
+    assert torch.allclose(g, 2.0 * w * (x - xt), rtol=1e-6, atol=1e-7)
