@@ -50,6 +50,11 @@ struct mpm_context {
   int64_t max_chunks = 0;
   int grid_blocks = 0;
   uint32_t *keys = nullptr, *slots = nullptr, *count = nullptr, *bsum = nullptr;
+  // bucketed permutation (k_perm_*): destinations, positions, pass-1 buffer, counts
+  int *pdest = nullptr, *ppos = nullptr, *pdop = nullptr;
+  float* ptmp = nullptr;
+  uint32_t *pcount = nullptr, *pbsum = nullptr;
+  const int* pdest_cur = nullptr;  // destinations of the prepared permutation
   unsigned long long* diag = nullptr;
   fmpm::Material* d_mats = nullptr;
   std::vector<void*> allocations;
@@ -201,24 +206,130 @@ int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
   return MPM_OK;
 }
 
+// Geometry of the bucketed permutation of N elements: buckets of 2^shift
+// destinations (at most 4096), counting tiles of ts sources (at most 2048).
+// Pass 2 holds one bucket per workgroup in LDS, so the bucketed form serves
+// N <= 2^26 (64 KB); larger N use one scatter pass.  Up to 2048 buckets
+// (N <= 2^23) pass 1 is staged through LDS one 8192-source tile at a time.
+struct PermGeom {
+  int shift = 12, nb = 0;
+  int64_t ts = 0, ntiles = 0, entries = 0;
+  bool bucketed = false, staged = false;
+};
+
+PermGeom perm_geom(int64_t N) {
+  PermGeom g;
+  int lg = 0;
+  while (((int64_t)1 << lg) < N) ++lg;
+  g.shift = std::max(12, lg - 12);
+  g.nb = (int)((N + ((int64_t)1 << g.shift) - 1) >> g.shift);
+  g.bucketed = N > 0 && g.shift <= 14;
+  g.staged = g.bucketed && g.nb <= 2048;
+  g.ts = g.staged ? 8192 : std::max<int64_t>(4096, ((N + 2047) / 2048 + 255) / 256 * 256);
+  g.ntiles = (N + g.ts - 1) / g.ts;
+  g.entries = (int64_t)g.nb * g.ntiles;
+  return g;
+}
+
+// Positions of the permutation out[dest[s]] = in[s] (dest a permutation of
+// [0, N), device array that must stay unchanged until the last perm_apply).
+int perm_prepare(mpm_ctx c, const int* dest, hipStream_t s) {
+  c->pdest_cur = dest;
+  const PermGeom g = perm_geom(c->N);
+  if (!g.bucketed) return MPM_OK;
+  const size_t lds = (size_t)g.nb * sizeof(uint32_t);
+  fmpm::k_perm_count<<<(unsigned)g.ntiles, 256, lds, s>>>(dest, c->N, g.shift, g.ts, g.nb, g.ntiles, c->pcount);
+  LAUNCH_CHECK(c, "k_perm_count");
+  const int64_t nbs = (g.entries + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  fmpm::k_scan_reduce<<<(unsigned)nbs, fmpm::kScanThreads, 0, s>>>(c->pcount, c->pbsum, g.entries);
+  fmpm::k_scan_top<<<1, fmpm::kScanThreads, 0, s>>>(c->pbsum, nbs);
+  fmpm::k_scan_apply<<<(unsigned)nbs, fmpm::kScanThreads, 0, s>>>(c->pcount, c->pbsum, g.entries);
+  LAUNCH_CHECK(c, "permutation scan");
+  fmpm::k_perm_rank<<<(unsigned)g.ntiles, 256, lds, s>>>(dest, c->N, g.shift, g.ts, g.nb, g.ntiles, c->pcount,
+                                                         c->ppos, c->pdop);
+  LAUNCH_CHECK(c, "k_perm_rank");
+  return MPM_OK;
+}
+
+// Apply the prepared permutation to up to 9 planes of N floats.
+int perm_apply(mpm_ctx c, const fmpm::PlaneSet& ps, hipStream_t s) {
+  if (c->N == 0 || ps.planes == 0) return MPM_OK;
+  const PermGeom g = perm_geom(c->N);
+  const unsigned gb = blocks_for(c->N, 256);
+  const int groups = (ps.planes + fmpm::kPermPlanes - 1) / fmpm::kPermPlanes;  // pass-1 plane groups
+  if (!g.bucketed) {
+    fmpm::k_scatter_planes<<<gb, 256, 0, s>>>(ps, c->pdest_cur, c->N);
+    LAUNCH_CHECK(c, "k_scatter_planes");
+    return MPM_OK;
+  }
+  if (g.staged) {
+    const size_t lds = (size_t)g.ts * 6 + (size_t)g.nb * 8;
+    const dim3 grid1((unsigned)(8 * ((g.ntiles + 7) / 8)), (unsigned)groups);
+    fmpm::k_perm_pass1_staged<<<grid1, 512, lds, s>>>(
+        c->ptmp, ps, c->ppos, c->pcount, c->N, g.shift, (int)g.ts, g.nb, (int)g.ntiles);
+  } else {
+    const int64_t chunks = (c->N + fmpm::kPermChunk - 1) / fmpm::kPermChunk;
+    fmpm::k_perm_pass1<<<(unsigned)(8 * ((chunks + 7) / 8)), 256, 0, s>>>(c->ptmp, ps, c->ppos, c->N);
+  }
+  LAUNCH_CHECK(c, "k_perm_pass1");
+  fmpm::k_perm_pass2<<<(unsigned)g.nb, 1024, ((size_t)1 << g.shift) * sizeof(float), s>>>(ps, c->ptmp, c->pdop,
+                                                                                          c->N, g.shift);
+  LAUNCH_CHECK(c, "k_perm_pass2");
+  return MPM_OK;
+}
+
+// Planes [k0, k0 + planes) of two [*][N] blocks.
+fmpm::PlaneSet plane_block(const float* in, float* out, int planes, int64_t N) {
+  fmpm::PlaneSet ps{};
+  ps.planes = planes;
+  for (int k = 0; k < planes; ++k) {
+    ps.in[k] = in + k * N;
+    ps.out[k] = out + k * N;
+  }
+  return ps;
+}
+
+// The prepared permutation applied to a [planes][N] block, 9 planes at a time.
+int perm_block(mpm_ctx c, const float* in, float* out, int planes, hipStream_t s) {
+  int rc = MPM_OK;
+  for (int k0 = 0; k0 < planes && !rc; k0 += fmpm::PlaneSet::kMax)
+    rc = perm_apply(c, plane_block(in + k0 * c->N, out + k0 * c->N, std::min(fmpm::PlaneSet::kMax, planes - k0), c->N),
+                    s);
+  return rc;
+}
+
+// The five parameter arrays of p through the prepared permutation, into
+// (mass, vol0, log E, nu, mat id bits) planes at out[0..4].
+int perm_params(mpm_ctx c, const mpm_particles* p, float* const out[5], hipStream_t s) {
+  fmpm::PlaneSet ps{};
+  ps.planes = 5;
+  const float* in[5] = {p->mass, p->vol0, p->log_E, p->nu, reinterpret_cast<const float*>(p->mat_id)};
+  for (int k = 0; k < 5; ++k) {
+    ps.in[k] = in[k];
+    ps.out[k] = out[k];
+  }
+  return perm_apply(c, ps, s);
+}
+
 int gather_from_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   ProfScope ps(c, s, 5);
   const unsigned g = blocks_for(c->N, 256);
-  // positions in the previous call's sorted order (nearly sorted now), then
-  // the sort of those; perm = pid o perm2 maps sorted slots to caller indices
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->xs2, p->x, c->pid, 3, c->N);
-  LAUNCH_CHECK(c, "pre-permute");
-  int rc = sort_keys(c, c->xs2, s);
+  const int64_t N = c->N;
+  // sort the caller's particles by cell: perm = caller index of each slot
+  int rc = sort_keys(c, p->x, s);
   if (rc) return rc;
-  int* perm = reinterpret_cast<int*>(c->slots);  // free after k_place
-  fmpm::k_compose<<<g, 256, 0, s>>>(c->pid, c->perm, perm, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->xs, p->x, perm, 3, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->vs, p->v, perm, 3, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Cs, p->C, perm, 9, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(c->Fs, p->F, perm, 9, c->N);
-  fmpm::k_gather_params<<<g, 256, 0, s>>>(c->prm, c->mat, c->pid, p->mass, p->vol0, p->log_E, p->nu, p->mat_id,
-                                          perm, c->N);
-  LAUNCH_CHECK(c, "gather");
+  fmpm::k_invert<<<g, 256, 0, s>>>(c->perm, c->pdest, N);  // caller index -> slot
+  LAUNCH_CHECK(c, "k_invert");
+  rc = perm_prepare(c, c->pdest, s);
+  rc = rc ? rc : perm_block(c, p->x, c->xs, 3, s);
+  rc = rc ? rc : perm_block(c, p->v, c->vs, 3, s);
+  rc = rc ? rc : perm_block(c, p->C, c->Cs, 9, s);
+  rc = rc ? rc : perm_block(c, p->F, c->Fs, 9, s);
+  float* const pl[5] = {c->Fs2, c->Fs2 + N, c->Fs2 + 2 * N, c->Fs2 + 3 * N, c->Fs2 + 4 * N};
+  rc = rc ? rc : perm_params(c, p, pl, s);
+  if (rc) return rc;
+  fmpm::k_params_planes<<<g, 256, 0, s>>>(c->prm, c->mat, c->pid, pl[0], pl[1], pl[2], pl[3], pl[4], c->perm, N);
+  LAUNCH_CHECK(c, "k_params_planes");
   return MPM_OK;
 }
 
@@ -241,16 +352,13 @@ int resort_internal(mpm_ctx c, hipStream_t s) {
 
 int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   ProfScope ps(c, s, 5);
-  const unsigned g = blocks_for(c->N, 256);
-  // gather through the inverse permutation: coalesced writes, random reads
-  int* inv = reinterpret_cast<int*>(c->keys);
-  fmpm::k_invert<<<g, 256, 0, s>>>(c->pid, inv, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->x, c->xs, inv, 3, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->v, c->vs, inv, 3, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->C, c->Cs, inv, 9, c->N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(p->F, c->Fs, inv, 9, c->N);
-  LAUNCH_CHECK(c, "scatter");
-  return MPM_OK;
+  // sorted slot j -> caller index pid[j]
+  int rc = perm_prepare(c, c->pid, s);
+  rc = rc ? rc : perm_block(c, c->xs, p->x, 3, s);
+  rc = rc ? rc : perm_block(c, c->vs, p->v, 3, s);
+  rc = rc ? rc : perm_block(c, c->Cs, p->C, 9, s);
+  rc = rc ? rc : perm_block(c, c->Fs, p->F, 9, s);
+  return rc;
 }
 
 // Tape layout (floats; N particles, B n^3 grid nodes):
@@ -307,20 +415,15 @@ int copy_f32(mpm_ctx c, float* out, const float* in, int64_t count, hipStream_t 
   return MPM_OK;
 }
 
-// internal state (x, v, C, F planes) -> caller-order 24-plane block: a
-// gather through the inverse of pid (kept in the sort's key buffer, free
-// between sorts)
+// internal state (x, v, C, F planes) -> caller-order 24-plane block
 int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
-  const unsigned g = blocks_for(c->N, 256);
   const int64_t N = c->N;
-  int* inv = reinterpret_cast<int*>(c->keys);
-  fmpm::k_invert<<<g, 256, 0, s>>>(c->pid, inv, N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24, c->xs, inv, 3, N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24 + 3 * N, c->vs, inv, 3, N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24 + 6 * N, c->Cs, inv, 9, N);
-  fmpm::k_gather_planes<<<g, 256, 0, s>>>(out24 + 15 * N, c->Fs, inv, 9, N);
-  LAUNCH_CHECK(c, "scatter_state");
-  return MPM_OK;
+  int rc = perm_prepare(c, c->pid, s);
+  rc = rc ? rc : perm_block(c, c->xs, out24, 3, s);
+  rc = rc ? rc : perm_block(c, c->vs, out24 + 3 * N, 3, s);
+  rc = rc ? rc : perm_block(c, c->Cs, out24 + 6 * N, 9, s);
+  rc = rc ? rc : perm_block(c, c->Fs, out24 + 15 * N, 9, s);
+  return rc;
 }
 
 template <int MODE>
@@ -454,6 +557,17 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   rc = rc ? rc : alloc(c, &c->nchk, c->nblocks);
   rc = rc ? rc : alloc(c, &c->work_counter, 1);
   rc = rc ? rc : alloc(c, &c->d_mats, fmpm::kMaxMaterials);
+  {
+    const PermGeom pg = perm_geom(N);
+    rc = rc ? rc : alloc(c, &c->pdest, N);
+    if (pg.bucketed) {
+      rc = rc ? rc : alloc(c, &c->ppos, N);
+      rc = rc ? rc : alloc(c, &c->pdop, N);
+      rc = rc ? rc : alloc(c, &c->ptmp, (int64_t)fmpm::PlaneSet::kMax * N);
+      rc = rc ? rc : alloc(c, &c->pcount, pg.entries);
+      rc = rc ? rc : alloc(c, &c->pbsum, (pg.entries + fmpm::kScanTile - 1) / fmpm::kScanTile);
+    }
+  }
   if (rc) {
     mpm_destroy(c);
     return rc;
@@ -606,10 +720,15 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     rc = sort_keys(ctx, ck, s);
     if (rc) return rc;
     auto slot = [&](int j) { return tl.seg + (int64_t)j * 24 * N; };
-    fmpm::k_gather_planes<<<gp, 256, 0, s>>>(slot(0), ck, ctx->perm, 24, N);
-    fmpm::k_gather_params<<<gp, 256, 0, s>>>(ctx->prm, ctx->mat, ctx->pid, p->mass, p->vol0, p->log_E, p->nu,
-                                              p->mat_id, ctx->perm, N);
-    fmpm::k_gather_lnE_nu<<<gp, 256, 0, s>>>(tl.lnE, tl.nu, p->log_E, p->nu, ctx->perm, N);
+    fmpm::k_invert<<<gp, 256, 0, s>>>(ctx->perm, ctx->pdest, N);  // caller index -> slot
+    LAUNCH_CHECK(ctx, "k_invert");
+    rc = perm_prepare(ctx, ctx->pdest, s);
+    rc = rc ? rc : perm_block(ctx, ck, slot(0), 24, s);
+    float* const pl[5] = {ctx->Fs2, ctx->Fs2 + N, tl.lnE, tl.nu, ctx->Fs2 + 2 * N};
+    rc = rc ? rc : perm_params(ctx, p, pl, s);
+    if (rc) return rc;
+    fmpm::k_params_planes<<<gp, 256, 0, s>>>(ctx->prm, ctx->mat, ctx->pid, pl[0], pl[1], pl[2], pl[3], pl[4],
+                                              ctx->perm, N);
     LAUNCH_CHECK(ctx, "backward gather");
     // (2) recompute the segment: slot j holds the state of substep k0 + j
     // and grid slot j its P2G (the grid the forward pass read at that
@@ -649,9 +768,9 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       LAUNCH_CHECK(ctx, "recompute substep");
     }
     // (3) adjoint of the segment's final state, in sorted order
-    fmpm::k_gather_or_zero<<<gp, 256, 0, s>>>(tl.adj, tl.adjc, ctx->perm, 24, N);
-    LAUNCH_CHECK(ctx, "adjoint gather");
-    rc = fill_u32(ctx, tl.gl, N, s);
+    rc = perm_prepare(ctx, ctx->pdest, s);  // caller index -> slot, as in (1)
+    rc = rc ? rc : perm_block(ctx, tl.adjc, tl.adj, 24, s);
+    rc = rc ? rc : fill_u32(ctx, tl.gl, N, s);
     rc = rc ? rc : fill_u32(ctx, tl.gn, N, s);
     if (rc) return rc;
     // (4) reverse the substeps of the segment
@@ -693,14 +812,23 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::k_adj_p2g<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       LAUNCH_CHECK(ctx, "k_adj_p2g");
     }
-    // (5) back to caller order, by gathers through the inverse of pid
+    // (5) back to caller order (slot j -> caller index pid[j]); the
+    // parameter gradients go through the sort's free key and slot buffers
     {
-      int* inv = reinterpret_cast<int*>(ctx->keys);
-      fmpm::k_invert<<<gp, 256, 0, s>>>(ctx->pid, inv, N);
-      fmpm::k_gather_planes<<<gp, 256, 0, s>>>(tl.adjc, tl.adj, inv, 24, N);
-      fmpm::k_gather_add<<<gp, 256, 0, s>>>(g_log_E, tl.gl, inv, 1, N);
-      fmpm::k_gather_add<<<gp, 256, 0, s>>>(g_nu, tl.gn, inv, 1, N);
-      LAUNCH_CHECK(ctx, "adjoint scatter");
+      float* gl_c = reinterpret_cast<float*>(ctx->keys);
+      float* gn_c = reinterpret_cast<float*>(ctx->slots);
+      rc = perm_prepare(ctx, ctx->pid, s);
+      rc = rc ? rc : perm_block(ctx, tl.adj, tl.adjc, 24, s);
+      fmpm::PlaneSet pg{};
+      pg.planes = 2;
+      pg.in[0] = tl.gl;
+      pg.in[1] = tl.gn;
+      pg.out[0] = gl_c;
+      pg.out[1] = gn_c;
+      rc = rc ? rc : perm_apply(ctx, pg, s);
+      if (rc) return rc;
+      fmpm::k_add2<<<gp, 256, 0, s>>>(g_log_E, gl_c, g_nu, gn_c, N);
+      LAUNCH_CHECK(ctx, "adjoint to caller order");
     }
   }
   float* gout[4] = {g_x0, g_v0, g_C0, g_F0};

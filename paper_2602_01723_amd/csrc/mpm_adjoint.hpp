@@ -762,31 +762,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a, AdjItems it) {
   }
 }
 
-// Gather `planes` planes by perm (out[c][j] = in[c][perm[j]]); NULL in -> zeros.
-__global__ void k_gather_or_zero(float* out, const float* in, const int* perm, int planes, int64_t N) {
+// a[j] += b[j], c[j] += d[j]
+__global__ void k_add2(float* a, const float* b, float* c, const float* d, int64_t N) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
-  const int64_t s = perm[j];
-  for (int c = 0; c < planes; ++c) out[c * N + j] = in ? in[c * N + s] : 0.0f;
-}
-
-// out[c][j] += in[c][perm[j]] (back to caller order with perm the inverse of
-// the sorted-to-caller map pid: coalesced writes, random reads)
-__global__ void k_gather_add(float* out, const float* in, const int* perm, int planes, int64_t N) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const int64_t s = perm[j];
-  for (int c = 0; c < planes; ++c) out[c * N + j] += in[c * N + s];
-}
-
-// log E and nu of each sorted slot
-__global__ void k_gather_lnE_nu(float* lnE, float* nu, const float* log_E_in, const float* nu_in, const int* perm,
-                                int64_t N) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const int s = perm[j];
-  lnE[j] = log_E_in[s];
-  nu[j] = nu_in[s];
+  a[j] += b[j];
+  c[j] += d[j];
 }
 
 // cotangent of L = sum_p w_p |x_p - x*_p|^2: g_x = 2 w_p (x_p - x*_p)

@@ -13,9 +13,10 @@
 // pipeline fuses G2P of substep s, the return map, the stress and P2G of
 // substep s+1 into one kernel (k_substep<kFused>): v and C never leave
 // registers.  The grid update is folded into the G2P tile load.  P2G
-// accumulates in an LDS tile covering the chunk's stencil box with
-// staggered per-lane node order (lanes of one cell hit different nodes),
-// then flushes the tile with one global FP32 atomic per node and channel.
+// accumulates in an LDS tile (64-bit fixed point, integer atomics) covering
+// the chunk's stencil box with staggered per-lane node order (lanes of one
+// cell hit different nodes), then flushes the tile with one global FP32
+// atomic per node and channel.
 // Chunks whose box exceeds the LDS tile fall back to global memory.
 #pragma once
 
@@ -28,7 +29,7 @@ namespace fmpm {
 
 constexpr int kPadX = 3;            // P2G tile x-stride padding (nodes), spreads LDS banks
 constexpr int kBlock = 256;         // threads per workgroup = particles per chunk
-constexpr int kTileCapMax = 1331;   // LDS tile nodes (11^3): P2G 4 doubles + G2P 3 floats per node
+constexpr int kTileCapMax = 1331;   // LDS tile nodes (11^3): P2G 4 x 64 bits + G2P 3 floats per node
 constexpr int kMaxMaterials = 16;
 
 enum { kP2G = 0, kFused = 1, kG2P = 2 };
@@ -71,6 +72,35 @@ __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
   return v;
+}
+
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// 64-bit fixed point of the P2G tile.  fx_bits(v, s) = bits of
+// fma(v, s, 1.5*2^52): for |v s| < 2^51 that double lies in [2^52, 2^53),
+// where one unit is one ulp, so its bits are 0x4338000000000000 + round(v s)
+// as a 64-bit integer.  The constant has its low 51 bits zero, so a sum of
+// such words, taken modulo 2^51 and sign-extended from bit 50, is the exact
+// sum of the rounded values whenever that sum's magnitude is below 2^50.
+constexpr float kFxMargin = 16.0f;  // headroom of later particles over the first sub-chunk's largest
+
+__device__ __forceinline__ unsigned long long fx_bits(float v, double s) {
+  return (unsigned long long)__double_as_longlong(fma((double)v, s, 6755399441055744.0));
+}
+
+__device__ __forceinline__ long long fx_value(unsigned long long u) { return (long long)(u << 13) >> 13; }
+
+// Power-of-two scale s with x s < 2^49 (x >= 0; 1 for x = 0).
+__device__ __forceinline__ double fx_scale(double x) {
+  if (!(x > 0.0)) return 1.0;
+  int e;
+  (void)frexp(x, &e);  // x < 2^e
+  e = min(max(49 - e, -900), 900);
+  return ldexp(1.0, e);
 }
 
 // Box of base cells over the workgroup's valid particles, plus the maxima
@@ -168,11 +198,12 @@ __device__ __forceinline__ void count_event(unsigned long long* diag, int slot, 
 //   2. G2P tile (box + 2 nodes) loaded from the grid being read, with the
 //      grid update applied on the way in; P2G tile (box grown by one cell,
 //      since a particle moves less than a cell per substep) zeroed;
-//   3. sub-chunks of kBlock particles, one per thread, with no barrier:
-//      G2P gather from the tile, F update, return map (FP64 SVD), stress of
-//      the new F and the P2G scatter into the tile with LDS f64 atomics in
-//      a staggered node order; a particle outside the P2G box scatters to
-//      global memory;
+//   3. sub-chunks of kBlock particles, one per thread: G2P gather from the
+//      tile, F update, return map (FP64 SVD), stress of the new F and the
+//      P2G scatter into the tile with 64-bit fixed-point LDS atomics in a
+//      staggered node order (one barrier, after the first sub-chunk's
+//      stress, fixes the item's fixed-point scales); a particle outside the
+//      P2G box, or beyond the fixed-point range, scatters to global memory;
 //   4. flush: one global FP32 atomic per touched node and channel.
 // Items whose box exceeds the LDS tiles use global memory throughout.
 // --------------------------------------------------------------------------
@@ -209,9 +240,10 @@ __device__ __forceinline__ void block_minmax(const int* lo, const int* hi, int* 
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
-  __shared__ double ptile[4 * kTileCapMax];  // P2G accumulators: mv.x, mv.y, mv.z, m
-  __shared__ float gtile[3 * kTileCapMax];   // G2P node velocities
+  __shared__ unsigned long long ptile[4 * kTileCapMax];  // P2G fixed-point accumulators: mv.x, mv.y, mv.z, m
+  __shared__ float gtile[3 * kTileCapMax];               // G2P node velocities
   __shared__ int red[8 * (kBlock / 64)];
+  __shared__ float fred[2 * (kBlock / 64)];
   __shared__ int item_s;
 
   const int n = a.n;
@@ -285,160 +317,172 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
     }
     if (lds_p) {
       for (int t = threadIdx.x; t < PT; t += kBlock) {
-        ptile[t] = 0.0;
-        ptile[kTileCapMax + t] = 0.0;
-        ptile[2 * kTileCapMax + t] = 0.0;
-        ptile[3 * kTileCapMax + t] = 0.0;
+        ptile[t] = 0ull;
+        ptile[kTileCapMax + t] = 0ull;
+        ptile[2 * kTileCapMax + t] = 0ull;
+        ptile[3 * kTileCapMax + t] = 0ull;
       }
     }
     __syncthreads();
 
-    // 3. particles
+    // 3. particles.  The P2G tile holds 64-bit fixed point: a contribution
+    // val enters as the bits of fma(val, s, 1.5*2^52), whose low 51 bits are
+    // round(val*s) in two's complement (the constant's low 51 bits are 0),
+    // so integer LDS adds (ds_add_u64, about twice the rate of ds_add_f64)
+    // sum the rounded values exactly modulo 2^51.  The scales s (momentum,
+    // mass; powers of two) are set per item from the first sub-chunk's
+    // largest contribution so that every node sum stays below 2^49; a later
+    // particle whose contribution exceeds kFxMargin times that maximum
+    // scatters to global memory instead.
+    double s_mom = 1.0, s_mass = 1.0;
+    float lim_mom = 0.0f, lim_mass = 0.0f;
     for (int sub = start; sub < end; sub += kBlock) {
       const int i = sub + (int)threadIdx.x;
-      if (i >= end) break;
-      float xp[3], vp[3] = {0.f, 0.f, 0.f};
-      float Cp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      double Fd[9];
+      const bool scale_pass = (MODE != kG2P) && lds_p && sub == start;
+      if (i >= end && !scale_pass) break;  // the scale pass needs every thread at its barrier
+      // P2G contribution of this thread's particle: w (q + Ad o) for node offset o
+      bool scat = false;
+      float q[3], Ad[9], f1[3], mass = 0.0f;
+      int b1[3];
+      if (i < end) {
+        float xp[3], vp[3] = {0.f, 0.f, 0.f};
+        float Cp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        double Fd[9];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) xp[k] = a.x[k * N + i];
+        for (int k = 0; k < 3; ++k) xp[k] = a.x[k * N + i];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) Fd[k] = (double)a.F[k * N + i];
-      const float4 prm = a.prm[i];
-      int mid = a.mat[i];
-      if (MODE == kP2G) {
+        for (int k = 0; k < 9; ++k) Fd[k] = (double)a.F[k * N + i];
+        const float4 prm = a.prm[i];
+        int mid = a.mat[i];
+        if (MODE == kP2G) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) vp[k] = a.v[k * N + i];
+          for (int k = 0; k < 3; ++k) vp[k] = a.v[k * N + i];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Cp[k] = a.C[k * N + i];
-      }
-      mid = (mid >= 0 && mid < a.n_materials) ? mid : 0;
-      const Material mat = a.mats[mid];
-      const double mu = (double)prm.z, lam = (double)prm.w;
-      double tau[9];
-      bool ok = true;
+          for (int k = 0; k < 9; ++k) Cp[k] = a.C[k * N + i];
+        }
+        mid = (mid >= 0 && mid < a.n_materials) ? mid : 0;
+        const Material mat = a.mats[mid];
+        const double mu = (double)prm.z, lam = (double)prm.w;
+        double tau[9];
+        bool ok = true;
 
-      // ---------------------------------------------------------- G2P
-      if (MODE != kP2G) {
-        int b0[3];
-        float f0[3];
-        bool in_grid = true;
+        // -------------------------------------------------------- G2P
+        if (MODE != kP2G) {
+          int b0[3];
+          float f0[3];
+          bool in_grid = true;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
-        ok = in_grid;
-        if (!in_grid) {
-          atomicAdd(&a.diag[1], 1ull);
-          if (a.xo != a.x) {  // skipped: carry the state over unchanged
+          for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
+          ok = in_grid;
+          if (!in_grid) {
+            atomicAdd(&a.diag[1], 1ull);
+            if (a.xo != a.x) {  // skipped: carry the state over unchanged
+#pragma unroll
+              for (int k = 0; k < 3; ++k) a.xo[k * N + i] = xp[k];
+#pragma unroll
+              for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = (float)Fd[k];
+              if (a.write_vc) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) a.vo[k * N + i] = a.v[k * N + i];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) a.Co[k * N + i] = a.C[k * N + i];
+              }
+            }
+          }
+          if (ok) {
+            float wx[3], wy[3], wz[3];
+            bspline_w(f0[0], wx);
+            bspline_w(f0[1], wy);
+            bspline_w(f0[2], wz);
+            float vs[3] = {0.f, 0.f, 0.f};
+            float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // sum w v_a o_b
+            const int sz = gy * gz;
+            const int a0 = ((b0[0] - box[0]) * gy + (b0[1] - box[1])) * gz + (b0[2] - box[2]);
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox)
+#pragma unroll
+              for (int oy = 0; oy < 3; ++oy) {
+                const float wxy = wx[ox] * wy[oy];
+                const int row = a0 + ox * sz + oy * gz;
+#pragma unroll
+                for (int oz = 0; oz < 3; ++oz) {
+                  const float w = wxy * wz[oz];
+                  float vi[3];
+                  if (lds_g) {
+                    vi[0] = gtile[row + oz];
+                    vi[1] = gtile[kTileCapMax + row + oz];
+                    vi[2] = gtile[2 * kTileCapMax + row + oz];
+                  } else {
+                    const int ix = b0[0] + ox, iy = b0[1] + oy, iz = b0[2] + oz;
+                    grid_velocity(a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, a, vi);
+                  }
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) {
+                    const float wv = w * vi[c];
+                    vs[c] += wv;
+                    if (ox) M[c][0] += (float)ox * wv;
+                    if (oy) M[c][1] += (float)oy * wv;
+                    if (oz) M[c][2] += (float)oz * wv;
+                  }
+                }
+              }
+            // C' = 4/dx^2 sum w v (x_i - x_p)^T = 4/dx (M - v f^T)
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) Cp[3 * r + c] = 4.0f * inv_dx * (M[r][c] - vs[r] * f0[c]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              vp[k] = vs[k];
+              xp[k] = xp[k] + a.dt * vs[k];
+            }
+            // F_trial = (I + dt C') F, in double
+            double Ftr[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                double acc = Fd[3 * r + c];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) acc += (double)a.dt * (double)Cp[3 * r + k] * Fd[3 * k + c];
+                Ftr[3 * r + c] = acc;
+              }
+            update_and_stress(mat, mu, lam, Ftr, true, MODE == kFused, Fd, tau);
+            float Ff[9];
+            bool fin = true;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+              Ff[k] = (float)Fd[k];
+              fin &= isfinite(Ff[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fin &= isfinite(xp[k]);
+            if (!fin) {
+              atomicAdd(&a.diag[0], 1ull);
+              ok = false;
+            }
 #pragma unroll
             for (int k = 0; k < 3; ++k) a.xo[k * N + i] = xp[k];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = (float)Fd[k];
-            if (a.write_vc) {
+            for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = Ff[k];
+            if (MODE == kG2P || a.write_vc) {
 #pragma unroll
-              for (int k = 0; k < 3; ++k) a.vo[k * N + i] = a.v[k * N + i];
+              for (int k = 0; k < 3; ++k) a.vo[k * N + i] = vp[k];
 #pragma unroll
-              for (int k = 0; k < 9; ++k) a.Co[k * N + i] = a.C[k * N + i];
+              for (int k = 0; k < 9; ++k) a.Co[k * N + i] = Cp[k];
             }
           }
         }
-        if (ok) {
-          float wx[3], wy[3], wz[3];
-          bspline_w(f0[0], wx);
-          bspline_w(f0[1], wy);
-          bspline_w(f0[2], wz);
-          float vs[3] = {0.f, 0.f, 0.f};
-          float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // sum w v_a o_b
-          const int sz = gy * gz;
-          const int a0 = ((b0[0] - box[0]) * gy + (b0[1] - box[1])) * gz + (b0[2] - box[2]);
-#pragma unroll
-          for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
-            for (int oy = 0; oy < 3; ++oy) {
-              const float wxy = wx[ox] * wy[oy];
-              const int row = a0 + ox * sz + oy * gz;
-#pragma unroll
-              for (int oz = 0; oz < 3; ++oz) {
-                const float w = wxy * wz[oz];
-                float vi[3];
-                if (lds_g) {
-                  vi[0] = gtile[row + oz];
-                  vi[1] = gtile[kTileCapMax + row + oz];
-                  vi[2] = gtile[2 * kTileCapMax + row + oz];
-                } else {
-                  const int ix = b0[0] + ox, iy = b0[1] + oy, iz = b0[2] + oz;
-                  grid_velocity(a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, a, vi);
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                  const float wv = w * vi[c];
-                  vs[c] += wv;
-                  if (ox) M[c][0] += (float)ox * wv;
-                  if (oy) M[c][1] += (float)oy * wv;
-                  if (oz) M[c][2] += (float)oz * wv;
-                }
-              }
-            }
-          // C' = 4/dx^2 sum w v (x_i - x_p)^T = 4/dx (M - v f^T)
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Cp[3 * r + c] = 4.0f * inv_dx * (M[r][c] - vs[r] * f0[c]);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            vp[k] = vs[k];
-            xp[k] = xp[k] + a.dt * vs[k];
-          }
-          // F_trial = (I + dt C') F, in double
-          double Ftr[9];
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              double acc = Fd[3 * r + c];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) acc += (double)a.dt * (double)Cp[3 * r + k] * Fd[3 * k + c];
-              Ftr[3 * r + c] = acc;
-            }
-          update_and_stress(mat, mu, lam, Ftr, true, MODE == kFused, Fd, tau);
-          float Ff[9];
-          bool fin = true;
-#pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            Ff[k] = (float)Fd[k];
-            fin &= isfinite(Ff[k]);
-          }
-#pragma unroll
-          for (int k = 0; k < 3; ++k) fin &= isfinite(xp[k]);
-          if (!fin) {
-            atomicAdd(&a.diag[0], 1ull);
-            ok = false;
-          }
-#pragma unroll
-          for (int k = 0; k < 3; ++k) a.xo[k * N + i] = xp[k];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = Ff[k];
-          if (MODE == kG2P || a.write_vc) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) a.vo[k * N + i] = vp[k];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) a.Co[k * N + i] = Cp[k];
-          }
-        }
-      }
 
-      // ---------------------------------------------------------- P2G
-      if (MODE != kG2P) {
-        int b1[3];
-        float f1[3];
-        bool in_grid = true;
+        // -------------------------------------------------------- P2G contribution
+        if (MODE != kG2P) {
+          bool in_grid = true;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
-        if (MODE == kP2G && !in_grid) atomicAdd(&a.diag[1], 1ull);
-        if (ok && in_grid) {
-          // A = m C - 4/dx^2 dt V0 tau, folded with dx for the node offsets
-          const float mass = prm.x;
-          float q[3], Ad[9];
-          {
+          for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
+          if (MODE == kP2G && !in_grid) atomicAdd(&a.diag[1], 1ull);
+          if (ok && in_grid) {
+            // A = m C - 4/dx^2 dt V0 tau, folded with dx for the node offsets
+            mass = prm.x;
             if (MODE == kP2G) {
               double Fs[9];
 #pragma unroll
@@ -448,74 +492,106 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
             const float ks = 4.0f * inv_dx * inv_dx * a.dt * prm.y;
 #pragma unroll
             for (int k = 0; k < 9; ++k) Ad[k] = (mass * Cp[k] - ks * (float)tau[k]) * dx;
-          }
-          // contribution to node o: w (m v + A (o - f) dx) = w (q + Ad o)
-          bool fin = isfinite(mass);
+            // contribution to node o: w (m v + A (o - f) dx) = w (q + Ad o)
+            bool fin = isfinite(mass);
 #pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            q[r] = mass * vp[r] - (Ad[3 * r] * f1[0] + Ad[3 * r + 1] * f1[1] + Ad[3 * r + 2] * f1[2]);
-            fin &= isfinite(q[r]);
-          }
-#pragma unroll
-          for (int k = 0; k < 9; ++k) fin &= isfinite(Ad[k]);
-          if (!fin) {  // never let a bad particle reach the grid
-            atomicAdd(&a.diag[0], 1ull);
-            continue;
-          }
-          const bool in_tile = lds_p && b1[0] >= plo[0] && b1[0] <= phi[0] && b1[1] >= plo[1] &&
-                               b1[1] <= phi[1] && b1[2] >= plo[2] && b1[2] <= phi[2];
-          if (lds_p && !in_tile) atomicAdd(&a.diag[3], 1ull);
-          float w[3][3];
-          bspline_w(f1[0], w[0]);
-          bspline_w(f1[1], w[1]);
-          bspline_w(f1[2], w[2]);
-          // staggered node order: lane group g visits offset (k + g_axis) mod 3 at step k
-          const int g = (threadIdx.x & 63) % 27;
-          const int gs[3] = {g / 9, (g / 3) % 3, g % 3};
-          int r[3][3];
-          float wr[3][3];
-#pragma unroll
-          for (int ax = 0; ax < 3; ++ax)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              r[ax][k] = rot3(gs[ax], k);
-              wr[ax][k] = sel3(w[ax], r[ax][k]);
+            for (int r = 0; r < 3; ++r) {
+              q[r] = mass * vp[r] - (Ad[3 * r] * f1[0] + Ad[3 * r + 1] * f1[1] + Ad[3 * r + 2] * f1[2]);
+              fin &= isfinite(q[r]);
             }
-          const int sz = SX;
-          const int a1 = (b1[0] - plo[0]) * SX + (b1[1] - plo[1]) * pz + (b1[2] - plo[2]);
 #pragma unroll
-          for (int kx = 0; kx < 3; ++kx) {
-            const float ox = (float)r[0][kx];
-            float vx[3];
+            for (int k = 0; k < 9; ++k) fin &= isfinite(Ad[k]);
+            if (fin) {
+              scat = true;
+            } else {  // never let a bad particle reach the grid
+              atomicAdd(&a.diag[0], 1ull);
+            }
+          }
+        }
+      }
+      if (MODE == kG2P) continue;
+
+      // bound of |w (q + Ad o)| over the 27 nodes (w <= 0.75^3) and of w m
+      float bnd_mom = 0.0f, bnd_mass = 0.0f;
+      if (scat) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) vx[c] = q[c] + Ad[3 * c] * ox;
+        for (int r = 0; r < 3; ++r)
+          bnd_mom = fmaxf(bnd_mom, fabsf(q[r]) + 2.0f * (fabsf(Ad[3 * r]) + fabsf(Ad[3 * r + 1]) + fabsf(Ad[3 * r + 2])));
+        bnd_mom *= 0.421875f;
+        bnd_mass = 0.421875f * fabsf(mass);
+      }
+      if (scale_pass) {
+        float m2[2] = {wave_maxf(bnd_mom), wave_maxf(bnd_mass)};
+        if ((threadIdx.x & 63) == 0) {
+          fred[2 * (threadIdx.x >> 6)] = m2[0];
+          fred[2 * (threadIdx.x >> 6) + 1] = m2[1];
+        }
+        __syncthreads();
+        for (int w = 0; w < kBlock / 64; ++w) {
+          m2[0] = fmaxf(m2[0], fred[2 * w]);
+          m2[1] = fmaxf(m2[1], fred[2 * w + 1]);
+        }
+        const double cnt = (double)(end - start) * (double)kFxMargin;
+        lim_mom = kFxMargin * m2[0];
+        lim_mass = kFxMargin * m2[1];
+        s_mom = fx_scale(cnt * (double)m2[0]);
+        s_mass = fx_scale(cnt * (double)m2[1]);
+      }
+      if (!scat) continue;
+
+      const bool in_tile = lds_p && b1[0] >= plo[0] && b1[0] <= phi[0] && b1[1] >= plo[1] && b1[1] <= phi[1] &&
+                           b1[2] >= plo[2] && b1[2] <= phi[2] && bnd_mom <= lim_mom && bnd_mass <= lim_mass;
+      if (lds_p && !in_tile) atomicAdd(&a.diag[3], 1ull);
+      float w[3][3];
+      bspline_w(f1[0], w[0]);
+      bspline_w(f1[1], w[1]);
+      bspline_w(f1[2], w[2]);
+      // staggered node order: lane group g visits offset (k + g_axis) mod 3 at step k
+      const int g = (threadIdx.x & 63) % 27;
+      const int gs[3] = {g / 9, (g / 3) % 3, g % 3};
+      int r[3][3];
+      float wr[3][3];
 #pragma unroll
-            for (int ky = 0; ky < 3; ++ky) {
-              const float oy = (float)r[1][ky];
-              const float wxy = wr[0][kx] * wr[1][ky];
-              float vy[3];
+      for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-              for (int c = 0; c < 3; ++c) vy[c] = vx[c] + Ad[3 * c + 1] * oy;
-              const int row = a1 + r[0][kx] * sz + r[1][ky] * pz;
+        for (int k = 0; k < 3; ++k) {
+          r[ax][k] = rot3(gs[ax], k);
+          wr[ax][k] = sel3(w[ax], r[ax][k]);
+        }
+      const int sz = SX;
+      const int a1 = (b1[0] - plo[0]) * SX + (b1[1] - plo[1]) * pz + (b1[2] - plo[2]);
 #pragma unroll
-              for (int kz = 0; kz < 3; ++kz) {
-                const float oz = (float)r[2][kz];
-                const float wgt = wxy * wr[2][kz];
-                float val[4];
+      for (int kx = 0; kx < 3; ++kx) {
+        const float ox = (float)r[0][kx];
+        float vx[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) val[c] = wgt * (vy[c] + Ad[3 * c + 2] * oz);
-                val[3] = wgt * mass;
-                if (in_tile) {
-                  const int t = row + r[2][kz];
+        for (int c = 0; c < 3; ++c) vx[c] = q[c] + Ad[3 * c] * ox;
 #pragma unroll
-                  for (int c = 0; c < 4; ++c) atomicAdd(&ptile[c * kTileCapMax + t], (double)val[c]);
-                } else {
-                  const int ix = b1[0] + r[0][kx], iy = b1[1] + r[1][ky], iz = b1[2] + r[2][kz];
-                  float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
+        for (int ky = 0; ky < 3; ++ky) {
+          const float oy = (float)r[1][ky];
+          const float wxy = wr[0][kx] * wr[1][ky];
+          float vy[3];
 #pragma unroll
-                  for (int c = 0; c < 4; ++c) atomicAdd(gp + c, val[c]);
-                }
-              }
+          for (int c = 0; c < 3; ++c) vy[c] = vx[c] + Ad[3 * c + 1] * oy;
+          const int row = a1 + r[0][kx] * sz + r[1][ky] * pz;
+#pragma unroll
+          for (int kz = 0; kz < 3; ++kz) {
+            const float oz = (float)r[2][kz];
+            const float wgt = wxy * wr[2][kz];
+            float val[4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) val[c] = wgt * (vy[c] + Ad[3 * c + 2] * oz);
+            val[3] = wgt * mass;
+            if (in_tile) {
+              const int t = row + r[2][kz];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) atomicAdd(&ptile[c * kTileCapMax + t], fx_bits(val[c], s_mom));
+              atomicAdd(&ptile[3 * kTileCapMax + t], fx_bits(val[3], s_mass));
+            } else {
+              const int ix = b1[0] + r[0][kx], iy = b1[1] + r[1][ky], iz = b1[2] + r[2][kz];
+              float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) atomicAdd(gp + c, val[c]);
             }
           }
         }
@@ -525,17 +601,18 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
     // 4. flush
     if (lds_p) {
       __syncthreads();
+      const double is_mom = 1.0 / s_mom, is_mass = 1.0 / s_mass;
       for (int t = threadIdx.x; t < PT; t += kBlock) {
-        const double m = ptile[3 * kTileCapMax + t];
-        if (m == 0.0) continue;
+        const long long im = fx_value(ptile[3 * kTileCapMax + t]);
+        if (im == 0) continue;
         const int ti = t / SX, tr = t - ti * SX;
         const int tj = tr / pz, tk = tr - tj * pz;
         if (tj >= py) continue;  // padding
         float* gp = (float*)&a.grid_out[gbase + ((int64_t)(plo[0] + ti) * n + (plo[1] + tj)) * n + (plo[2] + tk)];
-        atomicAdd(gp + 0, (float)ptile[t]);
-        atomicAdd(gp + 1, (float)ptile[kTileCapMax + t]);
-        atomicAdd(gp + 2, (float)ptile[2 * kTileCapMax + t]);
-        atomicAdd(gp + 3, (float)m);
+        atomicAdd(gp + 0, (float)((double)fx_value(ptile[t]) * is_mom));
+        atomicAdd(gp + 1, (float)((double)fx_value(ptile[kTileCapMax + t]) * is_mom));
+        atomicAdd(gp + 2, (float)((double)fx_value(ptile[2 * kTileCapMax + t]) * is_mom));
+        atomicAdd(gp + 3, (float)((double)im * is_mass));
       }
     }
   }
@@ -726,6 +803,213 @@ __global__ void k_gather_planes(float* out, const float* in, const int* perm, in
   for (int c = 0; c < planes; ++c) out[c * N + j] = in[c * N + s];
 }
 
+// --------------------------------------------------------------------------
+// Bucketed permutation of float planes: out[c][dest[s]] = in[c][s] for a
+// permutation dest of [0, N).  Moving sorted particles to the caller's order
+// (and back) is a random permutation; done as one gather it reads a 128-byte
+// line per 4-byte element.  Here it takes two passes whose HBM traffic is in
+// whole lines: sources are cut into tiles of ts, destinations into buckets
+// of 2^shift.  Pass 1 writes each element to tmp at its bucket-major
+// position (runs of about ts / buckets consecutive elements per tile and
+// bucket); pass 2 gives each bucket (exactly 2^shift elements, the last one
+// fewer) to one workgroup, which places its elements in LDS by destination
+// and writes the bucket out contiguously.  Positions within a run follow LDS
+// atomic order; the output does not depend on it.
+// --------------------------------------------------------------------------
+struct PlaneSet {
+  static constexpr int kMax = 9;
+  const float* in[kMax];
+  float* out[kMax];
+  int planes;
+};
+
+// counts[b * ntiles + tile] = elements of source tile `tile` bound for bucket b
+__global__ __launch_bounds__(256) void k_perm_count(const int* dest, int64_t N, int shift, int64_t ts, int nb,
+                                                    int64_t ntiles, uint32_t* counts) {
+  extern __shared__ uint32_t hist[];  // nb
+  for (int b = threadIdx.x; b < nb; b += 256) hist[b] = 0u;
+  __syncthreads();
+  const int64_t s0 = (int64_t)blockIdx.x * ts, s1 = min(N, s0 + ts);
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += 256) {
+    const uint32_t b = (uint32_t)dest[s] >> shift;
+    if (b < (uint32_t)nb) atomicAdd(&hist[b], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += 256) counts[(int64_t)b * ntiles + blockIdx.x] = hist[b];
+}
+
+// pos_src[s] = bucket-major position of source s (offsets = exclusive scan of
+// counts); dst_of_pos[p] = destination of the element at position p
+__global__ __launch_bounds__(256) void k_perm_rank(const int* dest, int64_t N, int shift, int64_t ts, int nb,
+                                                   int64_t ntiles, const uint32_t* offsets, int* pos_src,
+                                                   int* dst_of_pos) {
+  extern __shared__ uint32_t cur[];  // nb
+  for (int b = threadIdx.x; b < nb; b += 256) cur[b] = offsets[(int64_t)b * ntiles + blockIdx.x];
+  __syncthreads();
+  const int64_t s0 = (int64_t)blockIdx.x * ts, s1 = min(N, s0 + ts);
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += 256) {
+    const int d = dest[s];
+    const uint32_t b = (uint32_t)d >> shift;
+    if (b >= (uint32_t)nb) continue;
+    const uint32_t p = atomicAdd(&cur[b], 1u);
+    if (p < (uint32_t)N) {
+      pos_src[s] = (int)p;
+      dst_of_pos[p] = d;
+    }
+  }
+}
+
+// pass 1: tmp[c][pos_src[s]] = in[c][s].  Workgroup w takes source chunk
+// (w mod 8) q + w / 8 (q = gridDim / 8): workgroups are dealt to the 8 XCDs
+// in turn, so XCD x handles one contiguous eighth of the sources, whose
+// positions in every bucket are contiguous too, and its L2 assembles whole
+// lines before they are written back.
+constexpr int kPermChunk = 1024;  // sources per pass-1 workgroup (256 threads x 4)
+constexpr int kPermPlanes = 3;    // planes per workgroup of the LDS-staged pass 1
+
+__global__ __launch_bounds__(256) void k_perm_pass1(float* tmp, PlaneSet ps, const int* pos_src, int64_t N) {
+  const int64_t q = gridDim.x >> 3;
+  const int64_t chunk = (int64_t)(blockIdx.x & 7) * q + (blockIdx.x >> 3);
+  const int64_t s0 = chunk * kPermChunk;
+  int64_t p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t s = s0 + k * 256 + threadIdx.x;
+    p[k] = s < N ? (int64_t)pos_src[s] : -1;
+  }
+  for (int c = 0; c < ps.planes; ++c) {
+    const float* in = ps.in[c];
+    float* t = tmp + c * N;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (p[k] >= 0) t[p[k]] = in[s0 + k * 256 + threadIdx.x];
+  }
+}
+
+// Pass 1 staged through LDS, one counting tile per workgroup (tiles dealt to
+// XCDs as in k_perm_pass1).  The tile's elements are placed in LDS in
+// position order (bucket by bucket: bucket b = position >> shift, its run
+// starts at offsets[b][tile]), so consecutive lanes store consecutive
+// positions and each run goes out in whole lines.  LDS: ts floats, ts
+// 16-bit bucket ids, 2 nb run starts.
+__global__ __launch_bounds__(512) void k_perm_pass1_staged(float* tmp, PlaneSet ps, const int* pos_src,
+                                                           const uint32_t* offsets, int64_t N, int shift, int ts,
+                                                           int nb, int ntiles) {
+  extern __shared__ uint32_t smem[];
+  float* buf = reinterpret_cast<float*>(smem);                   // ts
+  uint16_t* bk = reinterpret_cast<uint16_t*>(smem + ts);        // ts
+  uint32_t* base = smem + ts + ts / 2;                          // nb: run start (position)
+  uint32_t* lst = base + nb;                                    // nb: run start (local index)
+  __shared__ uint32_t sh[160];
+  const int q = (int)(gridDim.x >> 3);
+  const int t = (int)(blockIdx.x & 7) * q + (int)(blockIdx.x >> 3);
+  if (t >= ntiles) return;  // uniform over the workgroup
+  const int64_t s0 = (int64_t)t * ts;
+  const int nt = (int)min((int64_t)ts, N - s0);
+  // runs of this tile: start and length per bucket, exclusive scan of lengths
+  constexpr int kPer = 8;  // buckets per thread (nb <= 512 x 8)
+  uint32_t len[kPer], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int b = threadIdx.x * kPer + k;
+    len[k] = 0;
+    if (b < nb) {
+      const uint32_t o = offsets[(int64_t)b * ntiles + t];
+      const uint32_t e = (t + 1 < ntiles) ? offsets[(int64_t)b * ntiles + t + 1]
+                                          : (uint32_t)min((int64_t)(b + 1) << shift, N);
+      base[b] = o;
+      len[k] = e - o;
+    }
+    sum += len[k];
+  }
+  uint32_t total;
+  uint32_t e = block_exclusive_scan(sum, sh, total);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int b = threadIdx.x * kPer + k;
+    if (b < nb) lst[b] = e;
+    e += len[k];
+  }
+  __syncthreads();
+  // local index of each source of the tile
+  constexpr int kSrc = 16;  // sources per thread (ts <= 512 x 16)
+  int loc[kSrc];
+#pragma unroll
+  for (int k = 0; k < kSrc; ++k) {
+    const int i = k * 512 + (int)threadIdx.x;
+    loc[k] = -1;
+    if (i < nt) {
+      const uint32_t pp = (uint32_t)pos_src[s0 + i];
+      const uint32_t b = pp >> shift;
+      if (b < (uint32_t)nb) {
+        const uint32_t l = lst[b] + (pp - base[b]);
+        if (l < (uint32_t)nt) {
+          loc[k] = (int)l;
+          bk[l] = (uint16_t)b;
+        }
+      }
+    }
+  }
+  // planes kPermPlanes blockIdx.y ... (+ kPermPlanes - 1): fewer planes per
+  // workgroup put more workgroups in flight, more share the prologue
+  const int c1 = min(ps.planes, (int)(blockIdx.y + 1) * kPermPlanes);
+  for (int c = blockIdx.y * kPermPlanes; c < c1; ++c) {
+    const float* in = ps.in[c] + s0;
+#pragma unroll
+    for (int k = 0; k < kSrc; ++k)
+      if (loc[k] >= 0) buf[loc[k]] = in[k * 512 + threadIdx.x];
+    __syncthreads();
+    float* out = tmp + c * N;
+    for (int l = threadIdx.x; l < nt; l += 512) {
+      const uint32_t b = bk[l];
+      out[base[b] + (uint32_t)l - lst[b]] = buf[l];
+    }
+    __syncthreads();
+  }
+}
+
+// pass 2: workgroup b places bucket b's elements of each plane by
+// destination in LDS and writes out[c][b 2^shift ...] contiguously
+__global__ __launch_bounds__(1024) void k_perm_pass2(PlaneSet ps, const float* tmp, const int* dst_of_pos,
+                                                     int64_t N, int shift) {
+  extern __shared__ float buf[];  // 2^shift
+  const int64_t base = (int64_t)blockIdx.x << shift;
+  const int64_t cnt = min((int64_t)1 << shift, N - base);
+  for (int c = 0; c < ps.planes; ++c) {
+    for (int64_t k = threadIdx.x; k < cnt; k += 1024) {
+      const int64_t o = (int64_t)dst_of_pos[base + k] - base;
+      if (o >= 0 && o < cnt) buf[o] = tmp[c * N + base + k];
+    }
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < cnt; k += 1024) ps.out[c][base + k] = buf[k];
+    __syncthreads();
+  }
+}
+
+// one-pass form for very large N: out[c][dest[s]] = in[c][s]
+__global__ void k_scatter_planes(PlaneSet ps, const int* dest, int64_t N) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const int64_t d = dest[s];
+  for (int c = 0; c < ps.planes; ++c) ps.out[c][d] = ps.in[c][s];
+}
+
+// internal particle parameters from the sorted parameter planes (mat id as
+// int bits); pid = caller index per slot
+__global__ void k_params_planes(float4* prm, int* mat, int* pid, const float* mass, const float* vol0,
+                                const float* log_E, const float* nu, const float* mat_bits, const int* perm,
+                                int64_t N) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double E = exp((double)log_E[j]);
+  const double nv = (double)nu[j];
+  const double mu = E / (2.0 * (1.0 + nv));
+  const double la = E * nv / ((1.0 + nv) * (1.0 - 2.0 * nv));
+  prm[j] = make_float4(mass[j], vol0[j], (float)mu, (float)la);
+  mat[j] = __float_as_int(mat_bits[j]);
+  pid[j] = perm[j];
+}
+
 __global__ void k_gather_misc(float4* prm_out, int* mat_out, int* pid_out, const float4* prm_in, const int* mat_in,
                               const int* pid_in, const int* perm, int64_t N) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -734,21 +1018,6 @@ __global__ void k_gather_misc(float4* prm_out, int* mat_out, int* pid_out, const
   prm_out[j] = prm_in[s];
   mat_out[j] = mat_in[s];
   pid_out[j] = pid_in[s];
-}
-
-// internal arrays from the caller's (perm = caller index of each sorted slot)
-__global__ void k_gather_params(float4* prm, int* mat, int* pid, const float* mass, const float* vol0,
-                                const float* log_E, const float* nu, const int* mat_id, const int* perm, int64_t N) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const int s = perm[j];
-  const double E = exp((double)log_E[s]);
-  const double nv = (double)nu[s];
-  const double mu = E / (2.0 * (1.0 + nv));
-  const double la = E * nv / ((1.0 + nv) * (1.0 - 2.0 * nv));
-  prm[j] = make_float4(mass[s], vol0[s], (float)mu, (float)la);
-  mat[j] = mat_id[s];
-  pid[j] = s;
 }
 
 // inv[pid[j]] = j
