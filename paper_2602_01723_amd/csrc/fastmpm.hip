@@ -40,7 +40,8 @@ struct mpm_context {
   float *xs = nullptr, *vs = nullptr, *Cs = nullptr, *Fs = nullptr, *xs2 = nullptr, *Fs2 = nullptr;
   float4 *prm = nullptr, *prm2 = nullptr;
   int *mat = nullptr, *mat2 = nullptr, *pid = nullptr, *pid2 = nullptr, *perm = nullptr;
-  float4* grid[2] = {nullptr, nullptr};
+  float4* grid[3] = {nullptr, nullptr, nullptr};  // rotation: read, write, cleared for the step after
+  unsigned* done_counter = nullptr;                // finished workgroups of the substep kernel
   int *chunk_start = nullptr, *chunk_batch = nullptr;            // by scene, fixed (cell keys)
   int *dchunk_start = nullptr, *dchunk_batch = nullptr, *dn_chunks = nullptr;  // by cell block, per sort
   uint32_t* nchk = nullptr;
@@ -175,6 +176,7 @@ fmpm::SubstepArgs make_args(mpm_ctx c) {
   a.diag = c->diag;
   a.n_materials = c->n_mat;
   a.mats = c->d_mats;
+  a.done_counter = c->done_counter;
   return a;
 }
 
@@ -427,11 +429,14 @@ int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
 }
 
 template <int MODE>
-int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hipStream_t s) {
+int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hipStream_t s,
+                   float4* gclear = nullptr) {
   fmpm::SubstepArgs a = make_args(c);
   a.grid_in = gin;
   a.grid_out = gout;
   a.write_vc = write_vc;
+  a.grid_clear = gclear;
+  a.clear_nodes = gclear ? c->nodes : 0;
   ProfScope ps(c, s, MODE == fmpm::kFused ? 0 : (MODE == fmpm::kP2G ? 1 : 2));
   fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);  // persistent: items from the queue
   LAUNCH_CHECK(c, "k_substep");
@@ -546,6 +551,8 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   rc = rc ? rc : alloc(c, &c->slots, N);
   rc = rc ? rc : alloc(c, &c->grid[0], c->nodes);
   rc = rc ? rc : alloc(c, &c->grid[1], c->nodes);
+  rc = rc ? rc : alloc(c, &c->grid[2], c->nodes);
+  rc = rc ? rc : alloc(c, &c->done_counter, 1);
   rc = rc ? rc : alloc(c, &c->count, bins);
   rc = rc ? rc : alloc(c, &c->bsum, c->n_bsum);
   rc = rc ? rc : alloc(c, &c->chunk_start, (int64_t)cs.size());
@@ -577,6 +584,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     e = hipMemcpy(c->chunk_batch, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->diag, 0, 8 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->dn_chunks, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->done_counter, 0, sizeof(unsigned));
   if (e == hipSuccess) e = hipMemcpy(c->d_mats, c->mats, sizeof(c->mats), hipMemcpyHostToDevice);
   if (e == hipSuccess && n_particles > 0) {
     fmpm::k_iota<<<blocks_for(n_particles, 256), 256>>>(c->pid, n_particles);
@@ -630,24 +638,25 @@ int run_steps(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, 
   }
   rc = gather_from_caller(ctx, p, s);
   if (rc) return rc;
+  // three grids in rotation: substep kernel k reads grid k % 3, writes
+  // grid (k + 1) % 3 (zeroed by kernel k - 1) and zeroes grid (k + 2) % 3;
+  // each kernel leaves the work-queue head at zero for the next
   rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, 4, ctx->work_counter);
   if (rc) return rc;
-  rc = launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s);
+  rc = launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s, n_steps > 1 ? ctx->grid[1] : nullptr);
   if (rc) return rc;
   int cur = 0;
   for (int st = 0; st < n_steps; ++st) {
     if (st == n_steps - 1) {
-      rc = fill_u32(ctx, ctx->work_counter, 1, s, -1, ctx->work_counter);
-      if (rc) return rc;
       rc = launch_substep<fmpm::kG2P>(ctx, ctx->grid[cur], nullptr, 1, s);
       if (rc) return rc;
     } else {
-      rc = fill_u32(ctx, ctx->grid[1 - cur], 4 * ctx->nodes, s, 4, ctx->work_counter);
-      if (rc) return rc;
+      const int nxt = (cur + 1) % 3, clr = (cur + 2) % 3;
       const bool ckpt = tape && (st + 1) % checkpoint_every == 0;
-      rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[1 - cur], ckpt ? 1 : 0, s);
+      rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[nxt], ckpt ? 1 : 0, s,
+                                        st + 2 < n_steps ? ctx->grid[clr] : nullptr);
       if (rc) return rc;
-      cur = 1 - cur;
+      cur = nxt;
       if (ckpt) {
         rc = scatter_state(ctx, tl.ckpt + ((st + 1) / checkpoint_every) * 24 * N, s);
         if (rc) return rc;

@@ -63,6 +63,13 @@ struct SubstepArgs {
   unsigned long long* diag;
   int n_materials;
   const Material* mats;  // device table [n_materials]
+  // a grid buffer this launch neither reads nor writes, zeroed for the
+  // launch after next (NULL: none), and its node count
+  float4* grid_clear;
+  int64_t clear_nodes;
+  // workgroups finished; the last one resets it and the queue head, so the
+  // next launch needs no counter reset (NULL: the caller resets the queue)
+  unsigned* done_counter;
 };
 
 // --------------------------------------------------------------------------
@@ -251,6 +258,12 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
   const float inv_dx = (float)n, dx = 1.0f / (float)n;
   const int cap = a.tile_cap;
   const int n_items = *a.n_chunks;
+
+  if (a.grid_clear) {  // this workgroup's slice of the buffer to clear
+    const int64_t per = (a.clear_nodes + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * per, c1 = min(a.clear_nodes, c0 + per);
+    for (int64_t t = c0 + threadIdx.x; t < c1; t += kBlock) a.grid_clear[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
 
   for (;;) {
     __syncthreads();  // tiles and item_s are reused
@@ -614,6 +627,14 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
         atomicAdd(gp + 2, (float)((double)fx_value(ptile[2 * kTileCapMax + t]) * is_mom));
         atomicAdd(gp + 3, (float)((double)im * is_mass));
       }
+    }
+  }
+  // the queue is drained: the last workgroup out resets the counters
+  if (a.done_counter && threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(a.done_counter, 1u) == gridDim.x - 1) {
+      atomicExch(a.work_counter, 0);
+      atomicExch(a.done_counter, 0u);
     }
   }
 }
