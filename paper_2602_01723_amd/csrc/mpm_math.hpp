@@ -64,7 +64,8 @@ __device__ __forceinline__ double rsq_nr(double x) {
 
 // One Jacobi rotation in plane (P, Q) of the symmetric S, accumulated into V.
 // t = tan(phi) = 2 a_pq / (d + sign(d) sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp,
-// the smaller of the two roots; (c, s) renormalised so V stays orthogonal.
+// the smaller of the two roots; c = 1 / sqrt(1 + t^2) with one Newton step on
+// the hardware estimate, so c^2 + s^2 = 1 to about 1e-15.
 template <int P, int Q>
 __device__ __forceinline__ void jacobi_rotate(double S[3][3], double V[3][3]) {
   constexpr int R = 3 - P - Q;
@@ -76,11 +77,8 @@ __device__ __forceinline__ void jacobi_rotate(double S[3][3], double V[3][3]) {
   const double h = h2 * rsq_nr<1>(h2);
   const double den = d + ((d < 0.0) ? -h : h);
   const double t = 2.0 * apq * rcp_nr<1>(den);
-  double c = rsq_nr<1>(fma(t, t, 1.0));
-  double s = t * c;
-  const double k = fma(-0.5, fma(c, c, s * s), 1.5);
-  c *= k;
-  s *= k;
+  const double c = rsq_nr<1>(fma(t, t, 1.0));
+  const double s = t * c;
   const double arp = S[R][P], arq = S[R][Q];
   S[P][P] -= t * apq;
   S[Q][Q] += t * apq;
@@ -120,7 +118,7 @@ __device__ __forceinline__ void givens_qr(double B[3][3], double U[3][3]) {
   const double a = B[I][COL], b = B[K][COL];
   const double r2 = fma(a, a, b * b);
   if (r2 == 0.0) return;
-  const double ir = rsq_nr<2>(r2);
+  const double ir = rsq_nr<1>(r2);
   const double c = a * ir, s = b * ir;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -137,6 +135,11 @@ __device__ __forceinline__ void givens_qr(double B[3][3], double U[3][3]) {
 }
 
 // F = U diag(sig) V^T, U, V in SO(3), |sig0| >= |sig1| >= |sig2|, sig0, sig1 >= 0.
+// Jacobi on F^T F stops once its off-diagonal part E is below 1e-8 of the
+// diagonal (sums of squares: 1e-16).  The QR of F V then has off-diagonal
+// entries of about E / sig, which the factorisation drops: U diag(sig) V^T
+// differs from F by about 1e-8 |F|, under the float32 rounding of the
+// stored F (6e-8), while sig (the diagonal of R) is exact to second order.
 __device__ __forceinline__ void svd3(const double* F, double U[3][3], double sig[3], double V[3][3]) {
   double S[3][3];
 #pragma unroll
@@ -154,7 +157,7 @@ __device__ __forceinline__ void svd3(const double* F, double U[3][3], double sig
   for (int sweep = 0; sweep < 12; ++sweep) {
     const double off = S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[1][2] * S[1][2];
     const double dia = S[0][0] * S[0][0] + S[1][1] * S[1][1] + S[2][2] * S[2][2];
-    if (off <= 1e-32 * dia) break;
+    if (off <= 1e-16 * dia) break;
     jacobi_rotate<0, 1>(S, V);
     jacobi_rotate<0, 2>(S, V);
     jacobi_rotate<1, 2>(S, V);
