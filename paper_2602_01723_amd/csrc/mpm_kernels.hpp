@@ -407,19 +407,22 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
             bspline_w(f0[0], wx);
             bspline_w(f0[1], wy);
             bspline_w(f0[2], wz);
+            // vs = sum w v and M[c][b] = sum w v_c o_b, summed axis by axis
+            // (the weight is a product of per-axis factors): z sums per
+            // (ox, oy) row, then y per ox plane, then x
             float vs[3] = {0.f, 0.f, 0.f};
-            float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // sum w v_a o_b
+            float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
             const int sz = gy * gz;
             const int a0 = ((b0[0] - box[0]) * gy + (b0[1] - box[1])) * gz + (b0[2] - box[2]);
 #pragma unroll
-            for (int ox = 0; ox < 3; ++ox)
+            for (int ox = 0; ox < 3; ++ox) {
+              float s0[3] = {0.f, 0.f, 0.f}, sy[3] = {0.f, 0.f, 0.f}, sz1[3] = {0.f, 0.f, 0.f};  // per ox plane
 #pragma unroll
               for (int oy = 0; oy < 3; ++oy) {
-                const float wxy = wx[ox] * wy[oy];
                 const int row = a0 + ox * sz + oy * gz;
+                float r0[3] = {0.f, 0.f, 0.f}, r1[3] = {0.f, 0.f, 0.f};  // sum_z wz v, sum_z oz wz v
 #pragma unroll
                 for (int oz = 0; oz < 3; ++oz) {
-                  const float w = wxy * wz[oz];
                   float vi[3];
                   if (lds_g) {
                     vi[0] = gtile[row + oz];
@@ -431,14 +434,25 @@ __global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
                   }
 #pragma unroll
                   for (int c = 0; c < 3; ++c) {
-                    const float wv = w * vi[c];
-                    vs[c] += wv;
-                    if (ox) M[c][0] += (float)ox * wv;
-                    if (oy) M[c][1] += (float)oy * wv;
-                    if (oz) M[c][2] += (float)oz * wv;
+                    r0[c] = fmaf(wz[oz], vi[c], r0[c]);
+                    if (oz) r1[c] = fmaf((float)oz * wz[oz], vi[c], r1[c]);
                   }
                 }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                  s0[c] = fmaf(wy[oy], r0[c], s0[c]);
+                  if (oy) sy[c] = fmaf((float)oy * wy[oy], r0[c], sy[c]);
+                  sz1[c] = fmaf(wy[oy], r1[c], sz1[c]);
+                }
               }
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                vs[c] = fmaf(wx[ox], s0[c], vs[c]);
+                if (ox) M[c][0] = fmaf((float)ox * wx[ox], s0[c], M[c][0]);
+                M[c][1] = fmaf(wx[ox], sy[c], M[c][1]);
+                M[c][2] = fmaf(wx[ox], sz1[c], M[c][2]);
+              }
+            }
             // C' = 4/dx^2 sum w v (x_i - x_p)^T = 4/dx (M - v f^T)
 #pragma unroll
             for (int r = 0; r < 3; ++r)
