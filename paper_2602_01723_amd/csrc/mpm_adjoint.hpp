@@ -460,19 +460,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
           grid_velocity(a.grid[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, ga, out);
         }
       };
-      float B[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+      // B = sum w v (o - f)^T dx = dx (M - v f^T)
+      float vs[3], M[3][3], B[3][3];
+      g2p_moments(w[0], w[1], w[2], node_v, vs, M);
 #pragma unroll
-      for (int o = 0; o < 27; ++o) {
-        const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
-        float vo[3];
-        node_v(ox, oy, oz, vo);
-        const float wt = w[0][ox] * w[1][oy] * w[2][oz];
-        const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) B[r][c] += wt * vo[r] * dp[c];
-      }
+        for (int c = 0; c < 3; ++c) B[r][c] = dx * (M[r][c] - vs[r] * f[c]);
       float Fb[9], Cbt[9], vbt[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r)

@@ -171,6 +171,51 @@ __device__ __forceinline__ void bspline_w(float f, float* w) {
   w[2] = 0.5f * c * c;
 }
 
+// vs = sum_o w_o v_o and M[c][b] = sum_o w_o v_o[c] o_b over the 27 nodes o
+// of a stencil, w_o = wx[ox] wy[oy] wz[oz].  The weight is a product of
+// per-axis factors, so the sums go axis by axis: z per (ox, oy) row, then y
+// per ox plane, then x.  fetch(ox, oy, oz, v) loads node o's velocity.
+template <class Fetch>
+__device__ __forceinline__ void g2p_moments(const float* wx, const float* wy, const float* wz, Fetch fetch,
+                                            float* vs, float (*M)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    vs[c] = 0.f;
+    M[c][0] = M[c][1] = M[c][2] = 0.f;
+  }
+#pragma unroll
+  for (int ox = 0; ox < 3; ++ox) {
+    float s0[3] = {0.f, 0.f, 0.f}, sy[3] = {0.f, 0.f, 0.f}, sz1[3] = {0.f, 0.f, 0.f};  // per ox plane
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) {
+      float r0[3] = {0.f, 0.f, 0.f}, r1[3] = {0.f, 0.f, 0.f};  // sum_z wz v, sum_z oz wz v
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz) {
+        float vi[3];
+        fetch(ox, oy, oz, vi);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          r0[c] = fmaf(wz[oz], vi[c], r0[c]);
+          if (oz) r1[c] = fmaf((float)oz * wz[oz], vi[c], r1[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s0[c] = fmaf(wy[oy], r0[c], s0[c]);
+        if (oy) sy[c] = fmaf((float)oy * wy[oy], r0[c], sy[c]);
+        sz1[c] = fmaf(wy[oy], r1[c], sz1[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vs[c] = fmaf(wx[ox], s0[c], vs[c]);
+      if (ox) M[c][0] = fmaf((float)ox * wx[ox], s0[c], M[c][0]);
+      M[c][1] = fmaf(wx[ox], sy[c], M[c][1]);
+      M[c][2] = fmaf(wx[ox], sz1[c], M[c][2]);
+    }
+  }
+}
+
 // Grid velocity from accumulated (mv, m): normalise, gravity, sticky walls.
 __device__ __forceinline__ void grid_velocity(const float4 g, int ix, int iy, int iz, const SubstepArgs& a,
                                               float* vo) {
@@ -246,7 +291,7 @@ __device__ __forceinline__ void block_minmax(const int* lo, const int* hi, int* 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_substep(SubstepArgs a) {
+__global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   __shared__ unsigned long long ptile[4 * kTileCapMax];  // P2G fixed-point accumulators: mv.x, mv.y, mv.z, m
   __shared__ float gtile[3 * kTileCapMax];               // G2P node velocities
   __shared__ int red[8 * (kBlock / 64)];
