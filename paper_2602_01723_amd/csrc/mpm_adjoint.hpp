@@ -75,6 +75,14 @@ __device__ __forceinline__ bool grid_active(float m, int ix, int iy, int iz, int
   return (m > 0.0f) && !wall;
 }
 
+// (mv / m, 1 / m) of a node whose velocity the grid update computes (m > 0,
+// off the walls); zero for every other node
+__device__ __forceinline__ float4 node_vim(float4 g, int ix, int iy, int iz, int n, int bd) {
+  if (!grid_active(g.w, ix, iy, iz, n, bd)) return make_float4(0.f, 0.f, 0.f, 0.f);
+  const float im = 1.0f / g.w;
+  return make_float4(g.x * im, g.y * im, g.z * im, im);
+}
+
 // Polar rotation of F (det F > 0 expected), SVD fallback.
 __device__ __forceinline__ void polar_rotation(const double* F, double* R) {
   if (polar_rotation_newton(F, R)) return;
@@ -571,8 +579,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
 // --------------------------------------------------------------------------
 // Reverse of the grid update and of P2G, stress and Lame parameters
 // --------------------------------------------------------------------------
-// One particle of the P2G / stress reverse; node(ix, iy, iz, gm, gb) fetches
-// the node's (mv, m) and grid-velocity adjoint.
+// One particle of the P2G / stress reverse; node(ix, iy, iz, gv, gb) fetches
+// the node's node_vim (mv / m, 1 / m) and grid-velocity adjoint.
 template <typename NodeFn>
 __device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn node) {
   const int n = a.n;
@@ -635,12 +643,12 @@ __device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn
     for (int o = 0; o < 27; ++o) {
       const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
       const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-      float4 gm, gb;
-      node(ix, iy, iz, gm, gb);
-      if (!grid_active(gm.w, ix, iy, iz, n, a.bound)) continue;
-      const float im = 1.0f / gm.w;
+      float4 gv, gb;
+      node(ix, iy, iz, gv, gb);
+      const float im = gv.w;
+      if (!(im > 0.0f)) continue;  // no mass, or a wall node: its velocity does not depend on mv, m
       const float mvb[3] = {gb.x * im, gb.y * im, gb.z * im};
-      const float mb = -(gb.x * gm.x + gb.y * gm.y + gb.z * gm.z) * im * im;
+      const float mb = -(gb.x * gv.x + gb.y * gv.y + gb.z * gv.z) * im;  // -(gb . mv) / m^2
       const float wt = w[0][ox] * w[1][oy] * w[2][oz];
       const float gw[3] = {inv_dx * dw[0][ox] * w[1][oy] * w[2][oz], inv_dx * w[0][ox] * dw[1][oy] * w[2][oz],
                            inv_dx * w[0][ox] * w[1][oy] * dw[2][oz]};
@@ -695,7 +703,7 @@ __device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn
 // nodes ((mv, m) and the grid-velocity adjoint) is staged in LDS, the
 // particles then gather from it (global memory when the box exceeds the tile).
 __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a, AdjItems it) {
-  __shared__ float4 gm_t[kTileCapMax];
+  __shared__ float4 gm_t[kTileCapMax];  // node_vim of the item's node box
   __shared__ float4 gb_t[kTileCapMax];
   __shared__ int red[8 * (kBlock / 64)];
   __shared__ int item_s;
@@ -736,7 +744,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a, AdjItems it) {
         const int tk = t % gz, tq = t / gz;
         const int tj = tq % gy, ti = tq / gy;
         const int64_t node = gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk);
-        gm_t[t] = a.grid[node];
+        gm_t[t] = node_vim(a.grid[node], box[0] + ti, box[1] + tj, box[2] + tk, n, a.bound);
         gb_t[t] = a.vhb[node];
       }
     }
@@ -748,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a, AdjItems it) {
         gb = gb_t[t];
       } else {
         const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
-        gm = a.grid[node];
+        gm = node_vim(a.grid[node], ix, iy, iz, n, a.bound);
         gb = a.vhb[node];
       }
     };
