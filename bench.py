@@ -344,6 +344,9 @@ def main():
     ap.add_argument("--substeps-per-step", type=int, default=20)
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--item", type=int, default=0, help="particles per work item (0 = library default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch tuning instead of running mpm_autotune before warm-up "
+                         "(--item / --sort-every also skip the autotuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs plain fwd+bwd comparison")
     ap.add_argument("--n-total", type=int, default=2_000_000)
@@ -402,6 +405,12 @@ def main():
         B.mpm_set_tuning(ctx, chunk=args.item)
     p = B.Particles.from_scene(sc)
     S = args.substeps_per_step
+    autotuned = not (args.no_autotune or args.item or args.sort_every)
+    if autotuned:  # untimed, before warm-up: trial calls of S substeps on internal copies
+        t = time.perf_counter()
+        tun = B.mpm_autotune(ctx, p, S)
+        log(f"  autotuned in {time.perf_counter() - t:.1f} s: {tun}")
+    tuning = B.mpm_get_tuning(ctx)
     for w in range(args.warmup):
         B.mpm_step_n(ctx, p, S)
         torch.cuda.synchronize()
@@ -488,8 +497,9 @@ def main():
         "config": {
             "workload": "large_scene: 2M particles (12 ellipsoids, shell + MCIS interior), 128^3 grid, dt 5e-5, "
                         "fixed-corotated / von Mises / Drucker-Prager, FP32 state, FP64 SVD",
-            "particles": sc.n, "grid_res": sc.grid_res, "substeps_per_step": S, "sort_every": args.sort_every,
-            "item": args.item,
+            "particles": sc.n, "grid_res": sc.grid_res, "substeps_per_step": S,
+            "tuning": {"autotuned": autotuned, **{k: tuning[k] for k in ("chunk", "sort_every", "workgroups",
+                                                                         "tile_cap")}},
             "kernel_time_by_class_ms": breakdown,
             "diagnostics": {k: diag[k] for k in ("nonfinite", "out_of_grid", "tile_overflow", "tile_escapes")},
         },

@@ -203,10 +203,12 @@ int mpm_set_tuning(mpm_ctx ctx, const mpm_tuning* t);
 int mpm_get_tuning(mpm_ctx ctx, mpm_tuning* t);
 
 /* Autotuner: times trial runs of trial_steps (>= 2) substeps of the given
- * particles for candidate settings (coordinate descent over chunk, then
- * workgroups, then sort_every) with HIP events on `stream`, applies the
- * fastest and returns it in *best.  Synchronous.  The trial runs work on the
- * context's internal copies: the caller's arrays are only read. */
+ * particles for candidate settings (coordinate descent over chunk in
+ * {256..2048}, then workgroups in {256..2048}, then sort_every in {2..64}
+ * below 2 trial_steps) with HIP events on `stream`, applies the fastest and
+ * returns it in *best.  Synchronous.  The trial runs work on the context's
+ * internal copies: the caller's arrays are only read.  Use trial_steps equal
+ * to the substeps of the calls to be tuned: each trial is such a call. */
 int mpm_autotune(mpm_ctx ctx, const mpm_particles* p, int32_t trial_steps, void* stream, mpm_tuning* best);
 
 /* Graph capture.  Between mpm_graph_begin and mpm_graph_end every call on

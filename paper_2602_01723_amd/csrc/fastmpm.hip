@@ -959,7 +959,7 @@ int mpm_autotune(mpm_ctx ctx, const mpm_particles* p, int32_t trial_steps, void*
   }
   for (int so : sorts) {
     if (rc) break;
-    if (so > trial_steps) break;
+    if (so >= 2 * trial_steps) break;  // one interval beyond the trial: no re-sort inside a call
     mpm_tuning t = bt;
     t.sort_every = so;
     double ms;
