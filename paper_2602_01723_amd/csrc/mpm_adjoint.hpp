@@ -632,42 +632,78 @@ __device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn
     float A[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) A[k] = mass * Cp[k] - ks * (float)tau[k];
-    float w[3][3], dw[3][3];
+    // Per node o (weight w_o, weight gradient gw_o, adjoints mvb_o, mb_o of
+    // its mv, m): the forward added w_o (m v + A (o - f) dx) to mv_o and
+    // w_o m to m_o.  With g = m v - A f dx the momentum term is g + A o dx,
+    // and the sums over o that do not involve gw reduce to
+    //   S0 = sum w mvb,  M1[r][c] = sum w mvb_r o_c:
+    //   vb = m S0,  Ab = dx (M1 - S0 f^T),  xb -= A^T S0.
+    // The remaining term xb += sum_o wb_o gw_o, wb_o = m mb_o + mvb_o . (g + A o dx),
+    // is summed node by node.
+    float w[3][3], dwi[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+      float dw[3];
       bspline_w(f[k], w[k]);
-      bspline_dw(f[k], dw[k]);
+      bspline_dw(f[k], dw);
+#pragma unroll
+      for (int o = 0; o < 3; ++o) dwi[k][o] = inv_dx * dw[o];
     }
-    float Ab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float g[3], Ad[9];  // Ad = A dx (A itself is not kept: register use)
 #pragma unroll
-    for (int o = 0; o < 27; ++o) {
-      const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
-      const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-      float4 gv, gb;
-      node(ix, iy, iz, gv, gb);
-      const float im = gv.w;
-      if (!(im > 0.0f)) continue;  // no mass, or a wall node: its velocity does not depend on mv, m
-      const float mvb[3] = {gb.x * im, gb.y * im, gb.z * im};
-      const float mb = -(gb.x * gv.x + gb.y * gv.y + gb.z * gv.z) * im;  // -(gb . mv) / m^2
-      const float wt = w[0][ox] * w[1][oy] * w[2][oz];
-      const float gw[3] = {inv_dx * dw[0][ox] * w[1][oy] * w[2][oz], inv_dx * w[0][ox] * dw[1][oy] * w[2][oz],
-                           inv_dx * w[0][ox] * w[1][oy] * dw[2][oz]};
-      const float dp[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
-      float wb = mb * mass;
+    for (int k = 0; k < 9; ++k) Ad[k] = A[k] * dx;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const float mom = mass * vp[r] + A[3 * r] * dp[0] + A[3 * r + 1] * dp[1] + A[3 * r + 2] * dp[2];
-        wb += mvb[r] * mom;
-        vb[r] += mass * wt * mvb[r];
+    for (int r = 0; r < 3; ++r) g[r] = mass * vp[r] - (Ad[3 * r] * f[0] + Ad[3 * r + 1] * f[1] + Ad[3 * r + 2] * f[2]);
+    float S0[3] = {0.f, 0.f, 0.f};
+    float M1[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Ab[3 * r + c] += wt * mvb[r] * dp[c];
-      }
+    for (int ox = 0; ox < 3; ++ox) {
+      float ax[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float atm = A[c] * mvb[0] + A[3 + c] * mvb[1] + A[6 + c] * mvb[2];
-        xb[c] += wb * gw[c] - wt * atm;
+      for (int r = 0; r < 3; ++r) ax[r] = g[r] + Ad[3 * r] * (float)ox;
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy) {
+        float ay[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ay[r] = ax[r] + Ad[3 * r + 1] * (float)oy;
+        const float wxy = w[0][ox] * w[1][oy];
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
+          float4 gv, gb;
+          node(ix, iy, iz, gv, gb);
+          const float im = gv.w;
+          if (!(im > 0.0f)) continue;  // no mass, or a wall node: its velocity does not depend on mv, m
+          const float mvb[3] = {gb.x * im, gb.y * im, gb.z * im};
+          const float mb = -(gb.x * gv.x + gb.y * gv.y + gb.z * gv.z) * im;  // -(gb . mv) / m^2
+          float wb = mass * mb;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) wb += mvb[r] * (ay[r] + Ad[3 * r + 2] * (float)oz);
+          const float wyz = w[1][oy] * w[2][oz];
+          const float gw[3] = {dwi[0][ox] * wyz, w[0][ox] * dwi[1][oy] * w[2][oz], wxy * dwi[2][oz]};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) xb[c] += wb * gw[c];
+          const float wt = wxy * w[2][oz];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const float wm = wt * mvb[r];
+            S0[r] += wm;
+            if (ox) M1[r][0] += (float)ox * wm;
+            if (oy) M1[r][1] += (float)oy * wm;
+            if (oz) M1[r][2] += (float)oz * wm;
+          }
+        }
       }
     }
+    float Ab[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      vb[r] = mass * S0[r];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Ab[3 * r + c] = dx * (M1[r][c] - f[c] * S0[r]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xb[c] -= inv_dx * (Ad[c] * S0[0] + Ad[3 + c] * S0[1] + Ad[6 + c] * S0[2]);
     // A = m C - ks tau
 #pragma unroll
     for (int k = 0; k < 9; ++k) Cb[k] = mass * Ab[k];
@@ -702,7 +738,7 @@ __device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn
 // Persistent over the work items of the last sort: each item's box of grid
 // nodes ((mv, m) and the grid-velocity adjoint) is staged in LDS, the
 // particles then gather from it (global memory when the box exceeds the tile).
-__global__ __launch_bounds__(kBlock) void k_adj_p2g(AdjArgs a, AdjItems it) {
+__global__ __launch_bounds__(kBlock, 2) void k_adj_p2g(AdjArgs a, AdjItems it) {
   __shared__ float4 gm_t[kTileCapMax];  // node_vim of the item's node box
   __shared__ float4 gb_t[kTileCapMax];
   __shared__ int red[8 * (kBlock / 64)];
