@@ -67,7 +67,8 @@ def measured_traffic(n_particles):
 
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
-               "--steps 2 --warmup 1 --substeps-per-step 5 --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis")
+               "--steps 2 --warmup 1 --substeps-per-step 5 --no-autotune --no-cpu-baseline --no-batched --no-bgdo --no-models "
+               "--no-mcis")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
