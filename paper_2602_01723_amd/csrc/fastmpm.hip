@@ -42,6 +42,7 @@ struct mpm_context {
   int *mat = nullptr, *mat2 = nullptr, *pid = nullptr, *pid2 = nullptr, *perm = nullptr;
   float4* grid[3] = {nullptr, nullptr, nullptr};  // rotation: read, write, cleared for the step after
   unsigned* done_counter = nullptr;                // finished workgroups of the substep kernel
+  int* item_box = nullptr;                         // [2][max_chunks][6]: per-item cell boxes, in turn
   int *chunk_start = nullptr, *chunk_batch = nullptr;            // by scene, fixed (cell keys)
   int *dchunk_start = nullptr, *dchunk_batch = nullptr, *dn_chunks = nullptr;  // by cell block, per sort
   uint32_t* nchk = nullptr;
@@ -430,13 +431,15 @@ int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
 
 template <int MODE>
 int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hipStream_t s,
-                   float4* gclear = nullptr) {
+                   float4* gclear = nullptr, const int* box_in = nullptr, int* box_out = nullptr) {
   fmpm::SubstepArgs a = make_args(c);
   a.grid_in = gin;
   a.grid_out = gout;
   a.write_vc = write_vc;
   a.grid_clear = gclear;
   a.clear_nodes = gclear ? c->nodes : 0;
+  a.box_in = box_in;
+  a.box_out = box_out;
   ProfScope ps(c, s, MODE == fmpm::kFused ? 0 : (MODE == fmpm::kP2G ? 1 : 2));
   fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);  // persistent: items from the queue
   LAUNCH_CHECK(c, "k_substep");
@@ -553,6 +556,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   rc = rc ? rc : alloc(c, &c->grid[1], c->nodes);
   rc = rc ? rc : alloc(c, &c->grid[2], c->nodes);
   rc = rc ? rc : alloc(c, &c->done_counter, 1);
+  rc = rc ? rc : alloc(c, &c->item_box, 2 * 6 * (c->max_chunks + 1));
   rc = rc ? rc : alloc(c, &c->count, bins);
   rc = rc ? rc : alloc(c, &c->bsum, c->n_bsum);
   rc = rc ? rc : alloc(c, &c->chunk_start, (int64_t)cs.size());
@@ -641,21 +645,31 @@ int run_steps(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, 
   // three grids in rotation: substep kernel k reads grid k % 3, writes
   // grid (k + 1) % 3 (zeroed by kernel k - 1) and zeroes grid (k + 2) % 3;
   // each kernel leaves the work-queue head at zero for the next
+  // per-item cell boxes in turn: each kernel hands the next one the box of
+  // its particles' new cells, so only the first kernel after a sort reads x
+  // for it
+  int* boxes[2] = {ctx->item_box, ctx->item_box + 6 * (ctx->max_chunks + 1)};
+  int bcur = 0;
   rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, 4, ctx->work_counter);
   if (rc) return rc;
-  rc = launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s, n_steps > 1 ? ctx->grid[1] : nullptr);
+  rc = launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s, n_steps > 1 ? ctx->grid[1] : nullptr, nullptr,
+                                  boxes[0]);
   if (rc) return rc;
+  bool have_box = true;
   int cur = 0;
   for (int st = 0; st < n_steps; ++st) {
     if (st == n_steps - 1) {
-      rc = launch_substep<fmpm::kG2P>(ctx, ctx->grid[cur], nullptr, 1, s);
+      rc = launch_substep<fmpm::kG2P>(ctx, ctx->grid[cur], nullptr, 1, s, nullptr, have_box ? boxes[bcur] : nullptr);
       if (rc) return rc;
     } else {
       const int nxt = (cur + 1) % 3, clr = (cur + 2) % 3;
       const bool ckpt = tape && (st + 1) % checkpoint_every == 0;
       rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[nxt], ckpt ? 1 : 0, s,
-                                        st + 2 < n_steps ? ctx->grid[clr] : nullptr);
+                                        st + 2 < n_steps ? ctx->grid[clr] : nullptr,
+                                        have_box ? boxes[bcur] : nullptr, boxes[1 - bcur]);
       if (rc) return rc;
+      bcur = 1 - bcur;
+      have_box = true;
       cur = nxt;
       if (ckpt) {
         rc = scatter_state(ctx, tl.ckpt + ((st + 1) / checkpoint_every) * 24 * N, s);
@@ -664,6 +678,7 @@ int run_steps(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, 
       if (ctx->sort_every > 0 && (st + 1) % ctx->sort_every == 0) {
         rc = resort_internal(ctx, s);
         if (rc) return rc;
+        have_box = false;  // new items: the next kernel reads x for its boxes
       }
     }
   }

@@ -70,6 +70,11 @@ struct SubstepArgs {
   // workgroups finished; the last one resets it and the queue head, so the
   // next launch needs no counter reset (NULL: the caller resets the queue)
   unsigned* done_counter;
+  // per-item base-cell boxes [item][lo xyz, hi xyz]: box_in, when set, is the
+  // box of the particles' current cells (skips the box pass); box_out, when
+  // set, receives a box containing the cells after this substep
+  const int* box_in;
+  int* box_out;
 };
 
 // --------------------------------------------------------------------------
@@ -297,6 +302,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   __shared__ int red[8 * (kBlock / 64)];
   __shared__ float fred[2 * (kBlock / 64)];
   __shared__ int item_s;
+  __shared__ int nbox_s[6];  // the item's box after this substep
 
   const int n = a.n;
   const int64_t N = a.N;
@@ -319,24 +325,34 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     const int start = a.chunk_start[item], end = a.chunk_start[item + 1];
     const int64_t gbase = (int64_t)a.chunk_batch[item] * n * n * n;
 
-    // 1. box of base cells
-    int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
-    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
-      int b[3];
-      float f[3];
-      bool in = true;
+    // 1. box of base cells: from the previous substep, or a pass over x
+    int box[6];
+    if (a.box_in) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
-      if (in) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          lo[k] = min(lo[k], b[k]);
-          hi[k] = max(hi[k], b[k]);
+      for (int k = 0; k < 6; ++k) box[k] = a.box_in[6 * item + k];
+    } else {
+      int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+      for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+        int b[3];
+        float f[3];
+        bool in = true;
+  #pragma unroll
+        for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
+        if (in) {
+  #pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            lo[k] = min(lo[k], b[k]);
+            hi[k] = max(hi[k], b[k]);
+          }
         }
       }
+      block_minmax(lo, hi, red, box);
     }
-    int box[6];
-    block_minmax(lo, hi, red, box);
+    // the next box starts as this one; particles that change cell widen it
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) nbox_s[k] = box[k];
+    }
     const bool empty = box[0] > box[3];
     // G2P tile: nodes box.lo .. box.hi + 2
     const int gx = box[3] - box[0] + 3, gy = box[4] - box[1] + 3, gz = box[5] - box[2] + 3;
@@ -423,6 +439,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
         const double mu = (double)prm.z, lam = (double)prm.w;
         double tau[9];
         bool ok = true;
+        int b0p = -1;  // base cell before this substep, 10 bits per axis (grid_res <= 1024)
 
         // -------------------------------------------------------- G2P
         if (MODE != kP2G) {
@@ -432,6 +449,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
           ok = in_grid;
+          if (in_grid) b0p = b0[0] | (b0[1] << 10) | (b0[2] << 20);
           if (!in_grid) {
             atomicAdd(&a.diag[1], 1ull);
             if (a.xo != a.x) {  // skipped: carry the state over unchanged
@@ -552,6 +570,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
           if (MODE == kP2G && !in_grid) atomicAdd(&a.diag[1], 1ull);
+          // a particle that changed cell may widen the item's next box
+          if (MODE == kFused && a.box_out && in_grid && (b1[0] | (b1[1] << 10) | (b1[2] << 20)) != b0p) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              atomicMin(&nbox_s[k], b1[k]);
+              atomicMax(&nbox_s[k + 3], b1[k]);
+            }
+          }
           if (ok && in_grid) {
             // A = m C - 4/dx^2 dt V0 tau, folded with dx for the node offsets
             mass = prm.x;
@@ -670,9 +696,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       }
     }
 
+    __syncthreads();  // the tile and the next box are complete
+    if (a.box_out && threadIdx.x < 6) a.box_out[6 * item + threadIdx.x] = nbox_s[threadIdx.x];
+
     // 4. flush
     if (lds_p) {
-      __syncthreads();
       const double is_mom = 1.0 / s_mom, is_mass = 1.0 / s_mass;
       for (int t = threadIdx.x; t < PT; t += kBlock) {
         const long long im = fx_value(ptile[3 * kTileCapMax + t]);

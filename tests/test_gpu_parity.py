@@ -209,6 +209,46 @@ def test_cube_lattice_100_substeps_positions():
     assert disp <= 1e-3
 
 
+def test_item_boxes_handed_between_substeps():
+    """Each substep kernel hands the next one a box of its particles' new
+    cells: the current box widened by the particles that changed cell.  A
+    rigidly translating and spinning cloud moving about 0.3 cells per
+    substep changes cells often.  The run without re-sorts, where boxes are
+    handed over for all 16 substeps, must match the run that re-sorts every
+    substep, where every kernel reads x for its boxes (same physics, other
+    item composition: rounding only), and the oracle."""
+    N, n, dt = 4000, 32, 1e-4
+    d = random_scene(91, N, n=n, dt=dt, cgrad=0.0, fdev=0.02, spread=0.3)
+    c = np.array([0.5, 0.5, 0.5], np.float32)
+    speed = 0.3 / n / dt  # 0.3 cells per substep
+    omega = np.array([0.0, 0.0, 1.0], np.float32) * (speed / 0.15) * 0.3
+    d["v"] = (np.array([0.6, 0.3, -0.5], np.float32) * speed + np.cross(omega, d["x"] - c)).astype(np.float32)
+    outs = []
+    for se in (1, 64):
+        ctx = B.mpm_init(n, dt, d["mats"], N, None, sort_every=se)
+        p = B.Particles.from_arrays(d["x"], d["v"], d["C"], d["F"], d["mass"], d["vol0"], d["log_E"], d["nu"],
+                                    d["mat_id"])
+        B.mpm_step_n(ctx, p, 16)
+        torch.cuda.synchronize()
+        diag = B.mpm_get_diagnostics(ctx)
+        assert diag["nonfinite"] == 0 and diag["out_of_grid"] == 0, diag
+        outs.append(p.state_numpy())
+    moved = np.abs(outs[1][0] - d["x"]).max() * n
+    assert moved > 3.0, moved  # particles crossed several cells
+    s_v = float(np.abs(outs[0][1]).max())
+    floors = (1.0 / n, s_v, s_v * n, 1.0)
+    for k in range(4):
+        e = rel_err(outs[1][k], outs[0][k], floors[k])
+        print("handed-over vs box pass", k, e, flush=True)
+        assert e <= 1e-5, (k, e)
+    params = O.Params(d["mass"], d["vol0"], d["log_E"], d["nu"], d["mat_id"], d["mats"], n, dt)
+    s0 = tuple(torch.as_tensor(np.asarray(a, np.float64)) for a in (d["x"], d["v"], d["C"], d["F"]))
+    xr = O.step_n(s0, params, 16)[0].numpy()
+    e = rel_err(outs[1][0], xr, 1.0 / n)
+    print("vs oracle x", e, flush=True)
+    assert e <= TOL_LONG_X
+
+
 def test_zero_particles_and_zero_steps():
     ctx = B.mpm_init(16, 1e-4, MATS_MIXED[:1], 0)
     p = B.Particles.from_arrays(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3, 3)), np.zeros((0, 3, 3)),
