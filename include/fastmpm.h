@@ -159,7 +159,8 @@ int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps,
 
 /* Bytes of the tape buffer for n_steps substeps checkpointed every K: the
  * checkpoints (96 B per particle each), one segment of K recomputed states
- * and their K grids (16 B per node each), and the adjoint scratch. */
+ * with their K grids (16 B per node each) and work-item boxes, and the
+ * adjoint scratch. */
 int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes);
 
 /* Reverse of the n_steps substeps taped by the last mpm_step_n call with

@@ -372,11 +372,13 @@ int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
 //   gl, gn       N each          parameter gradients of a segment, sorted order
 //   lnE, nu      N each          sorted copies of the parameters
 //   vhb          4 B n^3         adjoint of the grid velocity
+//   boxes        K x 6 items     per-item base-cell boxes of the segment's states (ints)
 struct TapeLayout {
   int64_t n_ckpt, K;
   float *ckpt, *seg, *adj, *adjc, *gl, *gn, *lnE, *nu;
   float4* vhb;
   float4* grids;  // K grids (mv, m): the P2G result of each recomputed state of a segment
+  int* boxes;     // K x (max_chunks + 1) x 6: item boxes of the recomputed states
   size_t bytes;
 };
 
@@ -401,6 +403,7 @@ TapeLayout tape_layout(mpm_ctx c, int32_t n_steps, int32_t K, void* base) {
   t.nu = take(N);
   t.vhb = reinterpret_cast<float4*>(take(4 * c->nodes));
   t.grids = reinterpret_cast<float4*>(take((int64_t)K * 4 * c->nodes));
+  t.boxes = reinterpret_cast<int*>(take((int64_t)K * 6 * (c->max_chunks + 1)));
   t.bytes = (size_t)(p - static_cast<char*>(base));
   return t;
 }
@@ -775,9 +778,13 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     auto gslot = [&](int j) { return tl.grids + (int64_t)j * ctx->nodes; };
     rc = fill_u32(ctx, gslot(0), 4 * ctx->nodes, s, -1, ctx->work_counter);
     if (rc) return rc;
+    // each kernel also records the item boxes of the state it produces,
+    // which the next kernel and the two adjoint kernels of that state reuse
+    auto bslot = [&](int j) { return tl.boxes + (int64_t)j * 6 * (ctx->max_chunks + 1); };
     {
       fmpm::SubstepArgs a = args_for(0, 0);
       a.grid_out = gslot(0);
+      a.box_out = bslot(0);
       fmpm::k_substep<fmpm::kP2G><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(ctx, "recompute P2G");
     }
@@ -787,6 +794,8 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::SubstepArgs a = args_for(j, j + 1);
       a.grid_in = gslot(j);
       a.grid_out = gslot(j + 1);
+      a.box_in = bslot(j);
+      a.box_out = bslot(j + 1);
       a.write_vc = 1;
       fmpm::k_substep<fmpm::kFused><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(ctx, "recompute substep");
@@ -828,7 +837,8 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       b.bound = ctx->cfg.bound;
       b.dt = ctx->cfg.dt;
       for (int k = 0; k < 3; ++k) b.g[k] = ctx->cfg.gravity[k];
-      fmpm::AdjItems items{ctx->dchunk_start, ctx->dchunk_batch, ctx->dn_chunks, ctx->work_counter, ctx->tile_cap};
+      fmpm::AdjItems items{ctx->dchunk_start, ctx->dchunk_batch, ctx->dn_chunks, ctx->work_counter, ctx->tile_cap,
+                           bslot(j)};
       fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       LAUNCH_CHECK(ctx, "k_adj_g2p");
       rc = fill_u32(ctx, ctx->work_counter, 1, s);  // the item queue again, for k_adj_p2g

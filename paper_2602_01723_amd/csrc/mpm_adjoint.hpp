@@ -362,9 +362,10 @@ struct AdjItems {
   const int* n_items;
   int* counter;           // zero at launch
   int tile_cap;
+  const int* box_in;      // per-item base-cell boxes of the state (NULL: a pass over x)
 };
 
-__global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
+__global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
   __shared__ double ptile[3 * kTileCapMax];
   __shared__ float gtile[3 * kTileCapMax];
   __shared__ int red[8 * (kBlock / 64)];
@@ -388,23 +389,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_g2p(AdjArgs a, AdjItems it) {
     if (item >= n_items) break;
     const int start = it.item_start[item], end = it.item_start[item + 1];
     const int64_t gbase = (int64_t)it.item_batch[item] * n * n * n;
-    int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
-    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
-      int b[3];
-      float f[3];
-      bool in = true;
+    int box[6];
+    if (it.box_in) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
-      if (in) {
+      for (int k = 0; k < 6; ++k) box[k] = it.box_in[6 * item + k];
+    } else {
+      int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+      for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+        int b[3];
+        float f[3];
+        bool in = true;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          lo[k] = min(lo[k], b[k]);
-          hi[k] = max(hi[k], b[k]);
+        for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
+        if (in) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            lo[k] = min(lo[k], b[k]);
+            hi[k] = max(hi[k], b[k]);
+          }
         }
       }
+      block_minmax(lo, hi, red, box);
     }
-    int box[6];
-    block_minmax(lo, hi, red, box);
     const bool empty = box[0] > box[3];
     const int gx = box[3] - box[0] + 3, gy = box[4] - box[1] + 3, gz = box[5] - box[2] + 3;
     // x stride padded like the forward P2G tile (the scatter's LDS banks)
@@ -754,23 +760,28 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_p2g(AdjArgs a, AdjItems it) {
     if (item >= n_items) break;
     const int start = it.item_start[item], end = it.item_start[item + 1];
     const int64_t gbase = (int64_t)it.item_batch[item] * n * n * n;
-    int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
-    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
-      int b[3];
-      float f[3];
-      bool in = true;
+    int box[6];
+    if (it.box_in) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
-      if (in) {
+      for (int k = 0; k < 6; ++k) box[k] = it.box_in[6 * item + k];
+    } else {
+      int lo[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, hi[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+      for (int i = start + (int)threadIdx.x; i < end; i += kBlock) {
+        int b[3];
+        float f[3];
+        bool in = true;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          lo[k] = min(lo[k], b[k]);
-          hi[k] = max(hi[k], b[k]);
+        for (int k = 0; k < 3; ++k) in &= cell_of(a.x[k * N + i], n, b[k], f[k]);
+        if (in) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            lo[k] = min(lo[k], b[k]);
+            hi[k] = max(hi[k], b[k]);
+          }
         }
       }
+      block_minmax(lo, hi, red, box);
     }
-    int box[6];
-    block_minmax(lo, hi, red, box);
     const bool empty = box[0] > box[3];
     const int gx = box[3] - box[0] + 3, gy = box[4] - box[1] + 3, gz = box[5] - box[2] + 3;
     const int GT = empty ? 0 : gx * gy * gz;
