@@ -282,6 +282,13 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
     tn = BT.per_particle(sc.extras["target_nu"], sc.batch_offsets)
     xt = BT.target_positions(sc, steps, tl, tn)
     ev = BT.Evaluation(sc, steps, K, xt)
+    # launch tuning for the batch: the autotuner's trial calls (forward, one
+    # checkpoint interval long) on the context's internal copies; the plain
+    # per-candidate solves use the same setting
+    from paper_2602_01723_amd import binding as B
+    tun = B.mpm_autotune(ev.ctx, ev.p, K)
+    tuning = {k: tun[k] for k in ("chunk", "sort_every", "workgroups", "tile_cap")}
+    log(f"  batched launch tuning: {tuning}")
     ev.run_eager()
     torch.cuda.synchronize()
     ev.capture()
@@ -294,7 +301,7 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
     t_batched = (time.perf_counter() - t0) / reps
     gl_b, _ = ev.gradients()
     log(f"  batched: {t_batched * 1e3:.1f} ms per evaluation of {n_batch} candidates")
-    plain = BT.plain_evaluations(sc, steps, K, xt)
+    plain = BT.plain_evaluations(sc, steps, K, xt, tuning=tuning)
     plain[0].run_eager()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -313,7 +320,7 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
         "workload": f"{n_batch} candidates, one fixed-corotated ellipsoid each on its own {sc.grid_res}^3 grid, "
                     f"{int(np.diff(sc.batch_offsets).min())}-{int(np.diff(sc.batch_offsets).max())} particles, "
                     f"{steps} substeps forward + adjoint, checkpoint every {K}",
-        "particles": sc.n, "substeps": steps,
+        "particles": sc.n, "substeps": steps, "tuning": {"autotuned": True, **tuning},
         "batched_grads_per_s": n_batch / t_batched, "plain_grads_per_s": n_batch / t_plain,
         "speedup": t_plain / t_batched, "batched_ms": t_batched * 1e3, "plain_ms": t_plain * 1e3,
         "fwd_bwd_particle_substeps_per_s": sc.n * steps / t_batched,

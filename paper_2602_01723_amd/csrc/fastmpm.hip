@@ -47,7 +47,7 @@ struct mpm_context {
   int *dchunk_start = nullptr, *dchunk_batch = nullptr, *dn_chunks = nullptr;  // by cell block, per sort
   uint32_t* nchk = nullptr;
   int* work_counter = nullptr;  // work-item queue head of the substep kernel
-  int item = 1024;              // particles per work item
+  int item = 768;               // particles per work item
   int64_t nblocks = 0;
   int64_t max_chunks = 0;
   int grid_blocks = 0;
@@ -963,7 +963,7 @@ int mpm_autotune(mpm_ctx ctx, const mpm_particles* p, int32_t trial_steps, void*
   double bms = 0.0;
   rc = trial(bt, &bms);
   // coordinate descent: work-item size, then workgroups, then sort interval
-  const int chunks[] = {256, 512, 1024, 2048};
+  const int chunks[] = {256, 512, 768, 1024, 1536, 2048};
   const int wgs[] = {256, 512, 768, 1024, 2048};
   const int sorts[] = {2, 4, 8, 16, 32, 64};
   for (int c : chunks) {
