@@ -329,19 +329,36 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
 
 
 def cpu_baseline(sc, n_sub=2):
-    """The FP64 oracle on `n_sub` substeps of the full workload, on the host."""
+    """The FP64 oracle on `n_sub` substeps of the full workload, on the host
+    with all threads; plus one substep of a 1/16-size copy of the workload on
+    a single thread (reported alongside, same unit)."""
     import torch
 
     from oracle import mpm_oracle as O
-    params = O.Params.from_scene(sc)
-    state = O.state_from_scene(sc)
-    t0 = time.perf_counter()
-    for _ in range(n_sub):
-        state = O.substep(state, params)
-    dt = time.perf_counter() - t0
-    return dict(value=sc.n * n_sub / dt, unit="particle-substeps/s", cores=torch.get_num_threads(), kind="oracle",
+    from paper_2602_01723_amd import scenes
+
+    def timed(scene, n, threads):
+        saved = torch.get_num_threads()
+        torch.set_num_threads(threads)
+        try:
+            params = O.Params.from_scene(scene)
+            state = O.state_from_scene(scene)
+            t0 = time.perf_counter()
+            for _ in range(n):
+                state = O.substep(state, params)
+            return time.perf_counter() - t0
+        finally:
+            torch.set_num_threads(saved)
+
+    cores = torch.get_num_threads()
+    dt = timed(sc, n_sub, cores)
+    small = scenes.make_scene("large_scene", n_total=max(sc.n // 16, 1000))
+    dt1 = timed(small, 1, 1)
+    return dict(value=sc.n * n_sub / dt, unit="particle-substeps/s", cores=cores, kind="oracle",
                 sample=f"{n_sub} substeps of the full {sc.n}-particle workload from its initial state "
-                       f"({dt:.1f} s, float64 PyTorch CPU)")
+                       f"({dt:.1f} s, float64 PyTorch CPU)",
+                one_core={"value": small.n / dt1, "cores": 1,
+                          "sample": f"1 substep of the {small.n}-particle copy of the workload ({dt1:.1f} s)"})
 
 
 def main():
@@ -487,7 +504,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         cpu = cpu_baseline(scenes.make_scene("large_scene", n_total=args.n_total))
-        log(f"  oracle: {cpu['value']:.3e} particle-substeps/s on {cpu['cores']} threads")
+        log(f"  oracle: {cpu['value']:.3e} particle-substeps/s on {cpu['cores']} threads, "
+            f"{cpu['one_core']['value']:.3e} on 1")
 
     out = {
         "metric": "particle-substeps/s (forward MLS-MPM substep)",
