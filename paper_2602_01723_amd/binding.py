@@ -76,6 +76,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2602_01723_amd.build` "
                            "(there is no other implementation of the substep)")
+    # torch's HIP runtime first: the library then binds to the same
+    # libamdhip64 (one runtime per process).  Loaded the other way round,
+    # torch would find the system runtime already in place and see no device.
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
     lib = ctypes.CDLL(path)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {

@@ -65,3 +65,34 @@ def test_skipped_particles_come_back_bit_for_bit():
     assert np.array_equal(vo[out_idx], sc.v[out_idx])
     assert np.array_equal(Co[out_idx], sc.C[out_idx])
     assert np.array_equal(Fo[out_idx], sc.F[out_idx])
+
+
+def test_large_n_unstaged_first_pass():
+    """Above 2048 destination buckets (N > 2^23) the first pass of the
+    permutation writes scattered instead of staging tiles in LDS.  9 M random
+    particles, one substep, identity vs shuffled caller order."""
+    N, n, dt = 9_000_000, 128, 5e-5
+    rng = np.random.default_rng(2024)
+    x, v, C, F = scenes.random_state(rng, N, n, spread=0.3, vel=0.2, cgrad=1.0, fdev=0.02)
+    mass = np.full(N, 1e-6, np.float32)
+    vol0 = np.full(N, 1e-9, np.float32)
+    log_E = np.full(N, np.log(1e5), np.float32)
+    nu = np.full(N, 0.3, np.float32)
+    mat = np.zeros(N, np.int32)
+    mats = [dict(elastic=0, plastic=0, yield_stress=0.0, friction_deg=0.0)]
+    outs = []
+    for order in (np.arange(N), rng.permutation(N)):
+        ctx = B.mpm_init(n, dt, mats, N, None)
+        p = B.Particles.from_arrays(x[order], v[order], C[order], F[order], mass[order], vol0[order], log_E[order],
+                                    nu[order], mat[order])
+        B.mpm_step_n(ctx, p, 2)
+        d = B.mpm_get_diagnostics(ctx)
+        assert d["nonfinite"] == 0 and d["out_of_grid"] == 0, d
+        inv = np.argsort(order)
+        outs.append([a[inv] for a in p.state_numpy()])
+        del ctx, p
+    s_v = max(float(np.abs(outs[0][1]).max()), 9.8 * dt)
+    floors = (1.0 / n, s_v, s_v * n, 1.0)
+    for k in range(4):
+        scale = max(float(np.abs(outs[0][k]).max()), floors[k])
+        assert np.abs(outs[1][k] - outs[0][k]).max() <= 2e-5 * scale, k
