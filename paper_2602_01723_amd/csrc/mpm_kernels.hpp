@@ -618,8 +618,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
         bnd_mom *= 0.421875f;
         bnd_mass = 0.421875f * fabsf(mass);
       }
+      // a bound that overflows float32 keeps its particle out of the tile and out of the scale
+      const bool fx_ok = bnd_mom <= 3.0e38f && bnd_mass <= 3.0e38f;
       if (scale_pass) {
-        float m2[2] = {wave_maxf(bnd_mom), wave_maxf(bnd_mass)};
+        float m2[2] = {wave_maxf(fx_ok ? bnd_mom : 0.0f), wave_maxf(fx_ok ? bnd_mass : 0.0f)};
         if ((threadIdx.x & 63) == 0) {
           fred[2 * (threadIdx.x >> 6)] = m2[0];
           fred[2 * (threadIdx.x >> 6) + 1] = m2[1];
@@ -638,7 +640,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       if (!scat) continue;
 
       const bool in_tile = lds_p && b1[0] >= plo[0] && b1[0] <= phi[0] && b1[1] >= plo[1] && b1[1] <= phi[1] &&
-                           b1[2] >= plo[2] && b1[2] <= phi[2] && bnd_mom <= lim_mom && bnd_mass <= lim_mass;
+                           b1[2] >= plo[2] && b1[2] <= phi[2] && fx_ok && bnd_mom <= lim_mom &&
+                           bnd_mass <= lim_mass;
       if (lds_p && !in_tile) atomicAdd(&a.diag[3], 1ull);
       float w[3][3];
       bspline_w(f1[0], w[0]);
