@@ -472,7 +472,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
             bspline_w(f0[2], wz);
             // vs = sum w v and M[c][b] = sum w v_c o_b, summed axis by axis
             // (the weight is a product of per-axis factors): z sums per
-            // (ox, oy) row, then y per ox plane, then x
+            // (ox, oy) row, then y per ox plane, then x.  The same sums as
+            // g2p_moments, written out here: through the helper's fetch
+            // callback this kernel needed 12 more registers and dropped to one
+            // wave per SIMD.
             float vs[3] = {0.f, 0.f, 0.f};
             float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
             const int sz = gy * gz;
