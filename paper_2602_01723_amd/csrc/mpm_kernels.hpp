@@ -478,45 +478,59 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
             // wave per SIMD.
             float vs[3] = {0.f, 0.f, 0.f};
             float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-            const int sz = gy * gz;
-            const int a0 = ((b0[0] - box[0]) * gy + (b0[1] - box[1])) * gz + (b0[2] - box[2]);
+            if (lds_g) {
+              const int sz = gy * gz;
+              const int a0 = ((b0[0] - box[0]) * gy + (b0[1] - box[1])) * gz + (b0[2] - box[2]);
 #pragma unroll
-            for (int ox = 0; ox < 3; ++ox) {
-              float s0[3] = {0.f, 0.f, 0.f}, sy[3] = {0.f, 0.f, 0.f}, sz1[3] = {0.f, 0.f, 0.f};  // per ox plane
+              for (int ox = 0; ox < 3; ++ox) {
+                float s0[3] = {0.f, 0.f, 0.f}, sy[3] = {0.f, 0.f, 0.f}, sz1[3] = {0.f, 0.f, 0.f};  // per ox plane
 #pragma unroll
-              for (int oy = 0; oy < 3; ++oy) {
-                const int row = a0 + ox * sz + oy * gz;
-                float r0[3] = {0.f, 0.f, 0.f}, r1[3] = {0.f, 0.f, 0.f};  // sum_z wz v, sum_z oz wz v
+                for (int oy = 0; oy < 3; ++oy) {
+                  const int row = a0 + ox * sz + oy * gz;
+                  float r0[3] = {0.f, 0.f, 0.f}, r1[3] = {0.f, 0.f, 0.f};  // sum_z wz v, sum_z oz wz v
 #pragma unroll
-                for (int oz = 0; oz < 3; ++oz) {
-                  float vi[3];
-                  if (lds_g) {
-                    vi[0] = gtile[row + oz];
-                    vi[1] = gtile[kTileCapMax + row + oz];
-                    vi[2] = gtile[2 * kTileCapMax + row + oz];
-                  } else {
-                    const int ix = b0[0] + ox, iy = b0[1] + oy, iz = b0[2] + oz;
-                    grid_velocity(a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, a, vi);
+                  for (int oz = 0; oz < 3; ++oz) {
+                    const float vi[3] = {gtile[row + oz], gtile[kTileCapMax + row + oz],
+                                         gtile[2 * kTileCapMax + row + oz]};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                      r0[c] = fmaf(wz[oz], vi[c], r0[c]);
+                      if (oz) r1[c] = fmaf((float)oz * wz[oz], vi[c], r1[c]);
+                    }
                   }
 #pragma unroll
                   for (int c = 0; c < 3; ++c) {
-                    r0[c] = fmaf(wz[oz], vi[c], r0[c]);
-                    if (oz) r1[c] = fmaf((float)oz * wz[oz], vi[c], r1[c]);
+                    s0[c] = fmaf(wy[oy], r0[c], s0[c]);
+                    if (oy) sy[c] = fmaf((float)oy * wy[oy], r0[c], sy[c]);
+                    sz1[c] = fmaf(wy[oy], r1[c], sz1[c]);
                   }
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                  s0[c] = fmaf(wy[oy], r0[c], s0[c]);
-                  if (oy) sy[c] = fmaf((float)oy * wy[oy], r0[c], sy[c]);
-                  sz1[c] = fmaf(wy[oy], r1[c], sz1[c]);
+                  vs[c] = fmaf(wx[ox], s0[c], vs[c]);
+                  if (ox) M[c][0] = fmaf((float)ox * wx[ox], s0[c], M[c][0]);
+                  M[c][1] = fmaf(wx[ox], sy[c], M[c][1]);
+                  M[c][2] = fmaf(wx[ox], sz1[c], M[c][2]);
                 }
               }
+            } else {
+              // the item's box exceeds the LDS tile (rare): node by node from
+              // the grid, in a loop kept rolled (code size)
+#pragma unroll 1
+              for (int o = 0; o < 27; ++o) {
+                const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+                const int ix = b0[0] + ox, iy = b0[1] + oy, iz = b0[2] + oz;
+                float vi[3];
+                grid_velocity(a.grid_in[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, a, vi);
+                const float w = sel3(wx, ox) * sel3(wy, oy) * sel3(wz, oz);
 #pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                vs[c] = fmaf(wx[ox], s0[c], vs[c]);
-                if (ox) M[c][0] = fmaf((float)ox * wx[ox], s0[c], M[c][0]);
-                M[c][1] = fmaf(wx[ox], sy[c], M[c][1]);
-                M[c][2] = fmaf(wx[ox], sz1[c], M[c][2]);
+                for (int c = 0; c < 3; ++c) {
+                  const float wv = w * vi[c];
+                  vs[c] += wv;
+                  M[c][0] = fmaf((float)ox, wv, M[c][0]);
+                  M[c][1] = fmaf((float)oy, wv, M[c][1]);
+                  M[c][2] = fmaf((float)oz, wv, M[c][2]);
+                }
               }
             }
             // C' = 4/dx^2 sum w v (x_i - x_p)^T = 4/dx (M - v f^T)
@@ -664,40 +678,46 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
         }
       const int sz = SX;
       const int a1 = (b1[0] - plo[0]) * SX + (b1[1] - plo[1]) * pz + (b1[2] - plo[2]);
+      if (in_tile) {
 #pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        const float ox = (float)r[0][kx];
-        float vx[3];
+        for (int kx = 0; kx < 3; ++kx) {
+          const float ox = (float)r[0][kx];
+          float vx[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) vx[c] = q[c] + Ad[3 * c] * ox;
+          for (int c = 0; c < 3; ++c) vx[c] = q[c] + Ad[3 * c] * ox;
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-          const float oy = (float)r[1][ky];
-          const float wxy = wr[0][kx] * wr[1][ky];
-          float vy[3];
+          for (int ky = 0; ky < 3; ++ky) {
+            const float oy = (float)r[1][ky];
+            const float wxy = wr[0][kx] * wr[1][ky];
+            float vy[3];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) vy[c] = vx[c] + Ad[3 * c + 1] * oy;
-          const int row = a1 + r[0][kx] * sz + r[1][ky] * pz;
+            for (int c = 0; c < 3; ++c) vy[c] = vx[c] + Ad[3 * c + 1] * oy;
+            const int row = a1 + r[0][kx] * sz + r[1][ky] * pz;
 #pragma unroll
-          for (int kz = 0; kz < 3; ++kz) {
-            const float oz = (float)r[2][kz];
-            const float wgt = wxy * wr[2][kz];
-            float val[4];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) val[c] = wgt * (vy[c] + Ad[3 * c + 2] * oz);
-            val[3] = wgt * mass;
-            if (in_tile) {
+            for (int kz = 0; kz < 3; ++kz) {
+              const float oz = (float)r[2][kz];
+              const float wgt = wxy * wr[2][kz];
               const int t = row + r[2][kz];
 #pragma unroll
-              for (int c = 0; c < 3; ++c) atomicAdd(&ptile[c * kTileCapMax + t], fx_bits(val[c], s_mom));
-              atomicAdd(&ptile[3 * kTileCapMax + t], fx_bits(val[3], s_mass));
-            } else {
-              const int ix = b1[0] + r[0][kx], iy = b1[1] + r[1][ky], iz = b1[2] + r[2][kz];
-              float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
-#pragma unroll
-              for (int c = 0; c < 4; ++c) atomicAdd(gp + c, val[c]);
+              for (int c = 0; c < 3; ++c)
+                atomicAdd(&ptile[c * kTileCapMax + t], fx_bits(wgt * (vy[c] + Ad[3 * c + 2] * oz), s_mom));
+              atomicAdd(&ptile[3 * kTileCapMax + t], fx_bits(wgt * mass, s_mass));
             }
           }
+        }
+      } else {
+        // outside the item's P2G tile or its fixed-point range (rare): FP32
+        // global atomics node by node, in a loop kept rolled (code size)
+#pragma unroll 1
+        for (int o = 0; o < 27; ++o) {
+          const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+          const float wgt = sel3(w[0], ox) * sel3(w[1], oy) * sel3(w[2], oz);
+          const int ix = b1[0] + ox, iy = b1[1] + oy, iz = b1[2] + oz;
+          float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            atomicAdd(gp + c, wgt * (q[c] + Ad[3 * c] * (float)ox + Ad[3 * c + 1] * (float)oy + Ad[3 * c + 2] * (float)oz));
+          atomicAdd(gp + 3, wgt * mass);
         }
       }
     }
