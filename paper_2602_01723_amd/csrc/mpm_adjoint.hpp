@@ -474,9 +474,36 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
           grid_velocity(a.grid[gbase + ((int64_t)ix * n + iy) * n + iz], ix, iy, iz, ga, out);
         }
       };
-      // B = sum w v (o - f)^T dx = dx (M - v f^T)
+      // B = sum w v (o - f)^T dx = dx (M - v f^T); the tile path sums axis
+      // by axis, the global-memory fallback node by node in a rolled loop
       float vs[3], M[3][3], B[3][3];
-      g2p_moments(w[0], w[1], w[2], node_v, vs, M);
+      if (lds) {
+        auto tile_v = [&](int ox, int oy, int oz, float* out) {
+          const int t = a0 + ox * sz + oy * gz + oz;
+          out[0] = gtile[t];
+          out[1] = gtile[kTileCapMax + t];
+          out[2] = gtile[2 * kTileCapMax + t];
+        };
+        g2p_moments(w[0], w[1], w[2], tile_v, vs, M);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vs[c] = M[c][0] = M[c][1] = M[c][2] = 0.f;
+#pragma unroll 1
+        for (int o = 0; o < 27; ++o) {
+          const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+          float vi[3];
+          node_v(ox, oy, oz, vi);
+          const float wt = sel3(w[0], ox) * sel3(w[1], oy) * sel3(w[2], oz);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float wv = wt * vi[c];
+            vs[c] += wv;
+            M[c][0] += (float)ox * wv;
+            M[c][1] += (float)oy * wv;
+            M[c][2] += (float)oz * wv;
+          }
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -585,10 +612,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
 // --------------------------------------------------------------------------
 // Reverse of the grid update and of P2G, stress and Lame parameters
 // --------------------------------------------------------------------------
-// One particle of the P2G / stress reverse; node(ix, iy, iz, gv, gb) fetches
-// the node's node_vim (mv / m, 1 / m) and grid-velocity adjoint.
-template <typename NodeFn>
-__device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn node) {
+// One particle of the P2G / stress reverse; tile(ix, iy, iz, gv, gb) and
+// glob(...) fetch the node's node_vim (mv / m, 1 / m) and grid-velocity
+// adjoint from the LDS tile (lds set) or from global memory.
+template <typename TileFn, typename GlobFn>
+__device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, bool lds, TileFn tile, GlobFn glob) {
   const int n = a.n;
   const int64_t N = a.N;
   const float inv_dx = (float)n, dx = 1.0f / (float)n, D = 4.0f * inv_dx * inv_dx;
@@ -662,43 +690,53 @@ __device__ __forceinline__ void adj_p2g_particle(const AdjArgs& a, int i, NodeFn
     for (int r = 0; r < 3; ++r) g[r] = mass * vp[r] - (Ad[3 * r] * f[0] + Ad[3 * r + 1] * f[1] + Ad[3 * r + 2] * f[2]);
     float S0[3] = {0.f, 0.f, 0.f};
     float M1[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    // one stencil node; ox, oy, oz are compile-time constants on the tile
+    // path and the selections fold away
+    auto visit = [&](int ox, int oy, int oz, const float4& gv, const float4& gb) {
+      const float im = gv.w;
+      if (!(im > 0.0f)) return;  // no mass, or a wall node: its velocity does not depend on mv, m
+      const float mvb[3] = {gb.x * im, gb.y * im, gb.z * im};
+      const float mb = -(gb.x * gv.x + gb.y * gv.y + gb.z * gv.z) * im;  // -(gb . mv) / m^2
+      float wb = mass * mb;
 #pragma unroll
-    for (int ox = 0; ox < 3; ++ox) {
-      float ax[3];
+      for (int r = 0; r < 3; ++r)
+        wb += mvb[r] * (((g[r] + Ad[3 * r] * (float)ox) + Ad[3 * r + 1] * (float)oy) + Ad[3 * r + 2] * (float)oz);
+      const float wx = sel3(w[0], ox), wy = sel3(w[1], oy), wz = sel3(w[2], oz);
+      const float wxy = wx * wy, wyz = wy * wz;
+      const float gw[3] = {sel3(dwi[0], ox) * wyz, wx * sel3(dwi[1], oy) * wz, wxy * sel3(dwi[2], oz)};
 #pragma unroll
-      for (int r = 0; r < 3; ++r) ax[r] = g[r] + Ad[3 * r] * (float)ox;
+      for (int c = 0; c < 3; ++c) xb[c] += wb * gw[c];
+      const float wt = wxy * wz;
 #pragma unroll
-      for (int oy = 0; oy < 3; ++oy) {
-        float ay[3];
+      for (int r = 0; r < 3; ++r) {
+        const float wm = wt * mvb[r];
+        S0[r] += wm;
+        if (ox) M1[r][0] += (float)ox * wm;
+        if (oy) M1[r][1] += (float)oy * wm;
+        if (oz) M1[r][2] += (float)oz * wm;
+      }
+    };
+    // one branch per particle: the tile path is unrolled, the global-memory
+    // fallback (items whose box exceeds the tile) stays a rolled loop so the
+    // rare path does not multiply the code
+    if (lds) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) ay[r] = ax[r] + Ad[3 * r + 1] * (float)oy;
-        const float wxy = w[0][ox] * w[1][oy];
+      for (int ox = 0; ox < 3; ++ox)
 #pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-          const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-          float4 gv, gb;
-          node(ix, iy, iz, gv, gb);
-          const float im = gv.w;
-          if (!(im > 0.0f)) continue;  // no mass, or a wall node: its velocity does not depend on mv, m
-          const float mvb[3] = {gb.x * im, gb.y * im, gb.z * im};
-          const float mb = -(gb.x * gv.x + gb.y * gv.y + gb.z * gv.z) * im;  // -(gb . mv) / m^2
-          float wb = mass * mb;
+        for (int oy = 0; oy < 3; ++oy)
 #pragma unroll
-          for (int r = 0; r < 3; ++r) wb += mvb[r] * (ay[r] + Ad[3 * r + 2] * (float)oz);
-          const float wyz = w[1][oy] * w[2][oz];
-          const float gw[3] = {dwi[0][ox] * wyz, w[0][ox] * dwi[1][oy] * w[2][oz], wxy * dwi[2][oz]};
-#pragma unroll
-          for (int c = 0; c < 3; ++c) xb[c] += wb * gw[c];
-          const float wt = wxy * w[2][oz];
-#pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            const float wm = wt * mvb[r];
-            S0[r] += wm;
-            if (ox) M1[r][0] += (float)ox * wm;
-            if (oy) M1[r][1] += (float)oy * wm;
-            if (oz) M1[r][2] += (float)oz * wm;
+          for (int oz = 0; oz < 3; ++oz) {
+            float4 gv, gb;
+            tile(b[0] + ox, b[1] + oy, b[2] + oz, gv, gb);
+            visit(ox, oy, oz, gv, gb);
           }
-        }
+    } else {
+#pragma unroll 1
+      for (int o = 0; o < 27; ++o) {
+        const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
+        float4 gv, gb;
+        glob(b[0] + ox, b[1] + oy, b[2] + oz, gv, gb);
+        visit(ox, oy, oz, gv, gb);
       }
     }
     float Ab[9];
@@ -796,18 +834,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_p2g(AdjArgs a, AdjItems it) {
       }
     }
     __syncthreads();
-    auto fetch = [&](int ix, int iy, int iz, float4& gm, float4& gb) {
-      if (lds) {
-        const int t = ((ix - box[0]) * gy + (iy - box[1])) * gz + (iz - box[2]);
-        gm = gm_t[t];
-        gb = gb_t[t];
-      } else {
-        const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
-        gm = node_vim(a.grid[node], ix, iy, iz, n, a.bound);
-        gb = a.vhb[node];
-      }
+    auto tile = [&](int ix, int iy, int iz, float4& gm, float4& gb) {
+      const int t = ((ix - box[0]) * gy + (iy - box[1])) * gz + (iz - box[2]);
+      gm = gm_t[t];
+      gb = gb_t[t];
     };
-    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) adj_p2g_particle(a, i, fetch);
+    auto glob = [&](int ix, int iy, int iz, float4& gm, float4& gb) {
+      const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
+      gm = node_vim(a.grid[node], ix, iy, iz, n, a.bound);
+      gb = a.vhb[node];
+    };
+    for (int i = start + (int)threadIdx.x; i < end; i += kBlock) adj_p2g_particle(a, i, lds, tile, glob);
   }
 }
 
