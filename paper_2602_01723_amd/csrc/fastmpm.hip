@@ -254,7 +254,7 @@ int perm_prepare(mpm_ctx c, const int* dest, hipStream_t s) {
   return MPM_OK;
 }
 
-// Apply the prepared permutation to up to 9 planes of N floats.
+// Apply the prepared permutation to up to 29 planes of N floats.
 int perm_apply(mpm_ctx c, const fmpm::PlaneSet& ps, hipStream_t s) {
   if (c->N == 0 || ps.planes == 0) return MPM_OK;
   const PermGeom g = perm_geom(c->N);
@@ -281,36 +281,39 @@ int perm_apply(mpm_ctx c, const fmpm::PlaneSet& ps, hipStream_t s) {
   return MPM_OK;
 }
 
-// Planes [k0, k0 + planes) of two [*][N] blocks.
-fmpm::PlaneSet plane_block(const float* in, float* out, int planes, int64_t N) {
-  fmpm::PlaneSet ps{};
-  ps.planes = planes;
+// Appends planes [0, planes) of two [*][N] blocks to a plane set (all of a
+// call's planes go through one pass-1 / pass-2 launch pair).
+void add_planes(fmpm::PlaneSet& ps, const float* in, float* out, int planes, int64_t N) {
   for (int k = 0; k < planes; ++k) {
-    ps.in[k] = in + k * N;
-    ps.out[k] = out + k * N;
+    ps.in[ps.planes] = in + k * N;
+    ps.out[ps.planes] = out + k * N;
+    ++ps.planes;
   }
+}
+
+// The five parameter arrays of p, bound for (mass, vol0, log E, nu, mat id
+// bits) planes at out[0..4].
+void add_params(fmpm::PlaneSet& ps, const mpm_particles* p, float* const out[5]) {
+  const float* in[5] = {p->mass, p->vol0, p->log_E, p->nu, reinterpret_cast<const float*>(p->mat_id)};
+  for (int k = 0; k < 5; ++k) {
+    ps.in[ps.planes] = in[k];
+    ps.out[ps.planes] = out[k];
+    ++ps.planes;
+  }
+}
+
+// x, v, C, F: four plane blocks (3, 3, 9, 9 planes) in one set
+fmpm::PlaneSet state_planes(const float* const in[4], float* const out[4], int64_t N) {
+  static constexpr int kPl[4] = {3, 3, 9, 9};
+  fmpm::PlaneSet ps{};
+  for (int k = 0; k < 4; ++k) add_planes(ps, in[k], out[k], kPl[k], N);
   return ps;
 }
 
-// The prepared permutation applied to a [planes][N] block, 9 planes at a time.
+// The prepared permutation applied to a [planes][N] block (planes <= 29).
 int perm_block(mpm_ctx c, const float* in, float* out, int planes, hipStream_t s) {
-  int rc = MPM_OK;
-  for (int k0 = 0; k0 < planes && !rc; k0 += fmpm::PlaneSet::kMax)
-    rc = perm_apply(c, plane_block(in + k0 * c->N, out + k0 * c->N, std::min(fmpm::PlaneSet::kMax, planes - k0), c->N),
-                    s);
-  return rc;
-}
-
-// The five parameter arrays of p through the prepared permutation, into
-// (mass, vol0, log E, nu, mat id bits) planes at out[0..4].
-int perm_params(mpm_ctx c, const mpm_particles* p, float* const out[5], hipStream_t s) {
   fmpm::PlaneSet ps{};
-  ps.planes = 5;
-  const float* in[5] = {p->mass, p->vol0, p->log_E, p->nu, reinterpret_cast<const float*>(p->mat_id)};
-  for (int k = 0; k < 5; ++k) {
-    ps.in[k] = in[k];
-    ps.out[k] = out[k];
-  }
+  add_planes(ps, in, out, planes, c->N);
   return perm_apply(c, ps, s);
 }
 
@@ -324,12 +327,12 @@ int gather_from_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   fmpm::k_invert<<<g, 256, 0, s>>>(c->perm, c->pdest, N);  // caller index -> slot
   LAUNCH_CHECK(c, "k_invert");
   rc = perm_prepare(c, c->pdest, s);
-  rc = rc ? rc : perm_block(c, p->x, c->xs, 3, s);
-  rc = rc ? rc : perm_block(c, p->v, c->vs, 3, s);
-  rc = rc ? rc : perm_block(c, p->C, c->Cs, 9, s);
-  rc = rc ? rc : perm_block(c, p->F, c->Fs, 9, s);
+  const float* const in[4] = {p->x, p->v, p->C, p->F};
+  float* const out[4] = {c->xs, c->vs, c->Cs, c->Fs};
+  fmpm::PlaneSet pls = state_planes(in, out, N);
   float* const pl[5] = {c->Fs2, c->Fs2 + N, c->Fs2 + 2 * N, c->Fs2 + 3 * N, c->Fs2 + 4 * N};
-  rc = rc ? rc : perm_params(c, p, pl, s);
+  add_params(pls, p, pl);
+  rc = rc ? rc : perm_apply(c, pls, s);
   if (rc) return rc;
   fmpm::k_params_planes<<<g, 256, 0, s>>>(c->prm, c->mat, c->pid, pl[0], pl[1], pl[2], pl[3], pl[4], c->perm, N);
   LAUNCH_CHECK(c, "k_params_planes");
@@ -357,11 +360,9 @@ int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   ProfScope ps(c, s, 5);
   // sorted slot j -> caller index pid[j]
   int rc = perm_prepare(c, c->pid, s);
-  rc = rc ? rc : perm_block(c, c->xs, p->x, 3, s);
-  rc = rc ? rc : perm_block(c, c->vs, p->v, 3, s);
-  rc = rc ? rc : perm_block(c, c->Cs, p->C, 9, s);
-  rc = rc ? rc : perm_block(c, c->Fs, p->F, 9, s);
-  return rc;
+  const float* const in[4] = {c->xs, c->vs, c->Cs, c->Fs};
+  float* const out[4] = {p->x, p->v, p->C, p->F};
+  return rc ? rc : perm_apply(c, state_planes(in, out, c->N), s);
 }
 
 // Tape layout (floats; N particles, B n^3 grid nodes):
@@ -425,11 +426,9 @@ int copy_f32(mpm_ctx c, float* out, const float* in, int64_t count, hipStream_t 
 int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
   const int64_t N = c->N;
   int rc = perm_prepare(c, c->pid, s);
-  rc = rc ? rc : perm_block(c, c->xs, out24, 3, s);
-  rc = rc ? rc : perm_block(c, c->vs, out24 + 3 * N, 3, s);
-  rc = rc ? rc : perm_block(c, c->Cs, out24 + 6 * N, 9, s);
-  rc = rc ? rc : perm_block(c, c->Fs, out24 + 15 * N, 9, s);
-  return rc;
+  const float* const in[4] = {c->xs, c->vs, c->Cs, c->Fs};
+  float* const out[4] = {out24, out24 + 3 * N, out24 + 6 * N, out24 + 15 * N};
+  return rc ? rc : perm_apply(c, state_planes(in, out, N), s);
 }
 
 template <int MODE>
@@ -750,9 +749,11 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     fmpm::k_invert<<<gp, 256, 0, s>>>(ctx->perm, ctx->pdest, N);  // caller index -> slot
     LAUNCH_CHECK(ctx, "k_invert");
     rc = perm_prepare(ctx, ctx->pdest, s);
-    rc = rc ? rc : perm_block(ctx, ck, slot(0), 24, s);
+    fmpm::PlaneSet pk{};
+    add_planes(pk, ck, slot(0), 24, N);
     float* const pl[5] = {ctx->Fs2, ctx->Fs2 + N, tl.lnE, tl.nu, ctx->Fs2 + 2 * N};
-    rc = rc ? rc : perm_params(ctx, p, pl, s);
+    add_params(pk, p, pl);
+    rc = rc ? rc : perm_apply(ctx, pk, s);
     if (rc) return rc;
     fmpm::k_params_planes<<<gp, 256, 0, s>>>(ctx->prm, ctx->mat, ctx->pid, pl[0], pl[1], pl[2], pl[3], pl[4],
                                               ctx->perm, N);
@@ -852,13 +853,10 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       float* gl_c = reinterpret_cast<float*>(ctx->keys);
       float* gn_c = reinterpret_cast<float*>(ctx->slots);
       rc = perm_prepare(ctx, ctx->pid, s);
-      rc = rc ? rc : perm_block(ctx, tl.adj, tl.adjc, 24, s);
       fmpm::PlaneSet pg{};
-      pg.planes = 2;
-      pg.in[0] = tl.gl;
-      pg.in[1] = tl.gn;
-      pg.out[0] = gl_c;
-      pg.out[1] = gn_c;
+      add_planes(pg, tl.adj, tl.adjc, 24, N);
+      add_planes(pg, tl.gl, gl_c, 1, N);
+      add_planes(pg, tl.gn, gn_c, 1, N);
       rc = rc ? rc : perm_apply(ctx, pg, s);
       if (rc) return rc;
       fmpm::k_add2<<<gp, 256, 0, s>>>(g_log_E, gl_c, g_nu, gn_c, N);

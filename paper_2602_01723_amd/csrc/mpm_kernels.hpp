@@ -951,7 +951,7 @@ __global__ void k_gather_planes(float* out, const float* in, const int* perm, in
 // atomic order; the output does not depend on it.
 // --------------------------------------------------------------------------
 struct PlaneSet {
-  static constexpr int kMax = 9;
+  static constexpr int kMax = 29;  // x, v, C, F and the five parameter arrays in one launch
   const float* in[kMax];
   float* out[kMax];
   int planes;
@@ -1104,18 +1104,30 @@ __global__ __launch_bounds__(512) void k_perm_pass1_staged(float* tmp, PlaneSet 
 
 // pass 2: workgroup b places bucket b's elements of each plane by
 // destination in LDS and writes out[c][b 2^shift ...] contiguously
+// (shift <= 14: each thread keeps its up to 16 LDS destinations over all planes)
 __global__ __launch_bounds__(1024) void k_perm_pass2(PlaneSet ps, const float* tmp, const int* dst_of_pos,
                                                      int64_t N, int shift) {
   extern __shared__ float buf[];  // 2^shift
+  constexpr int kPer = 16;
   const int64_t base = (int64_t)blockIdx.x << shift;
-  const int64_t cnt = min((int64_t)1 << shift, N - base);
-  for (int c = 0; c < ps.planes; ++c) {
-    for (int64_t k = threadIdx.x; k < cnt; k += 1024) {
-      const int64_t o = (int64_t)dst_of_pos[base + k] - base;
-      if (o >= 0 && o < cnt) buf[o] = tmp[c * N + base + k];
+  const int cnt = (int)min((int64_t)1 << shift, N - base);
+  int o[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int j = k * 1024 + (int)threadIdx.x;
+    o[k] = -1;
+    if (j < cnt) {
+      const int64_t d = (int64_t)dst_of_pos[base + j] - base;
+      if (d >= 0 && d < cnt) o[k] = (int)d;
     }
+  }
+  for (int c = 0; c < ps.planes; ++c) {
+    const float* t = tmp + c * N + base;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (o[k] >= 0) buf[o[k]] = t[k * 1024 + threadIdx.x];
     __syncthreads();
-    for (int64_t k = threadIdx.x; k < cnt; k += 1024) ps.out[c][base + k] = buf[k];
+    for (int k = threadIdx.x; k < cnt; k += 1024) ps.out[c][base + k] = buf[k];
     __syncthreads();
   }
 }
