@@ -1,12 +1,16 @@
 #!/usr/bin/env python3
 """Throughput of the MLS-MPM substep on one MI355X.
 
-A step is one call of mpm_step_n advancing every particle of the workload
-by `--substeps-per-step` substeps (the whole hot path: cell sort, stress,
-P2G, grid update, G2P, return map).  The timed region holds exactly
-`--steps` steps between two device synchronisations, with the particle
-state resident in HBM.  Prints one JSON line on stdout; progress goes to
-stderr.
+A step is one render frame: every particle of the workload advances by
+`--substeps-per-step` substeps (the whole hot path: cell sorts, stress,
+P2G, grid update, G2P, return map) through mpm_advance on the scene held in
+the context, and mpm_export_frame then writes the frame's positions and
+Gaussian covariances in the caller's order.  The scene is copied into the
+context (mpm_load) before warm-up.  The timed region holds exactly
+`--steps` steps between two device synchronisations.  The same frames
+through mpm_step_n (caller-order arrays in and out at every call) are timed
+after it and reported beside the headline.  Prints one JSON line on stdout;
+progress goes to stderr.
 
 Workload (default): 2,000,000 particles on twelve ellipsoid instances,
 128^3 grid, dt = 5e-5, fixed-corotated / von Mises / Drucker-Prager
@@ -67,8 +71,8 @@ def measured_traffic(n_particles):
 
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
-               "--steps 2 --warmup 1 --substeps-per-step 5 --no-autotune --no-cpu-baseline --no-batched --no-bgdo --no-models "
-               "--no-mcis")
+               "--steps 1 --warmup 1 --substeps-per-step 10 --no-autotune --no-step-n --no-cpu-baseline --no-batched "
+               "--no-bgdo --no-models --no-mcis")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
@@ -258,15 +262,27 @@ def summarize_counters(csv_paths, kernel="k_substep<1>", n_particles=2_000_000) 
     return out
 
 
-def copy_probe():
-    """A plain 256 MiB device copy, the calibration point of the HBM counters."""
+def copy_probe(reps=20):
+    """A plain 256 MiB device copy: the calibration point of the HBM counters,
+    and (timed over reps copies of the same size) the bandwidth a plain copy
+    attains on this device, in GB/s of bytes read + written."""
     import torch
     a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     b.copy_(a)
     torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
     del a, b
+    t = sorted(times)[len(times) // 2]
+    return 2 * 256 * 1024 * 1024 / t / 1e9
 
 
 def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
@@ -378,6 +394,8 @@ def main():
     ap.add_argument("--no-bgdo", action="store_true", help="skip the BGDO iteration timing")
     ap.add_argument("--no-models", action="store_true", help="skip the per-model fused-kernel timing")
     ap.add_argument("--no-mcis", action="store_true", help="skip the MCIS interior-fill timing")
+    ap.add_argument("--no-step-n", action="store_true",
+                    help="skip timing the same frames through mpm_step_n (caller-order I/O at every call)")
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched vs plain forward + adjoint and exit")
@@ -417,7 +435,8 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched_fwd_bwd": batched_vs_plain()}), flush=True)
         return
-    copy_probe()
+    copy_gbs = copy_probe()
+    log(f"  plain 256 MiB copy: {copy_gbs:.0f} GB/s (read + write)")
     log("generating workload ...")
     t = time.perf_counter()
     sc = scenes.make_scene("large_scene", n_total=args.n_total)
@@ -436,8 +455,20 @@ def main():
         tun = B.mpm_autotune(ctx, p, S)
         log(f"  autotuned in {time.perf_counter() - t:.1f} s: {tun}")
     tuning = B.mpm_get_tuning(ctx)
+    # one step = one render frame: S substeps of the scene held in the
+    # context (mpm_load, untimed, before warm-up), then the frame's positions
+    # and Gaussian covariances F Sigma0 F^T in the caller's order
+    cov0 = torch.tensor(np.ascontiguousarray(sc.cov0.T)).cuda()
+    x_out = torch.empty(3, sc.n, device="cuda")
+    cov_out = torch.empty(6, sc.n, device="cuda")
+
+    def frame():
+        B.mpm_advance(ctx, S)
+        B.mpm_export_frame(ctx, x_out, cov0, cov_out)
+
+    B.mpm_load(ctx, p)
     for w in range(args.warmup):
-        B.mpm_step_n(ctx, p, S)
+        frame()
         torch.cuda.synchronize()
         log(f"  warmup step {w + 1}/{args.warmup} done")
 
@@ -446,7 +477,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        B.mpm_step_n(ctx, p, S)
+        frame()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = B.mpm_profile_read(ctx)
@@ -459,6 +490,20 @@ def main():
     m, _, _ = B.grid_state(ctx)
     active = int((m > 0).sum().item())
     torch.cuda.synchronize()
+    step_n = None
+    if not args.no_step_n:
+        # the same frames through mpm_step_n: the caller's x, v, C, F and
+        # parameters in and x, v, C, F out at every call
+        B.mpm_step_n(ctx, p, S)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(args.steps):
+            B.mpm_step_n(ctx, p, S)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - ts
+        step_n = dict(value=sc.n * S * args.steps / te, ms_per_step=te / args.steps * 1e3,
+                      what="mpm_step_n per step: caller-order arrays in and out at every call, no frame export")
+        log(f"  mpm_step_n path: {step_n['value']:.3e} particle-substeps/s")
 
     value = sc.n * S * args.steps / elapsed
     fused_ms, fused_n = prof["fused_substep"]
@@ -469,7 +514,8 @@ def main():
     roofline = dict(bound="hbm", kernel="k_substep<fused>", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=traffic,
                     bytes_per_launch=bytes_launch, avg_launch_us=fused_avg_s * 1e6, launches=fused_n,
-                    active_nodes=active)
+                    active_nodes=active, copy_attained=copy_gbs,
+                    frac_of_copy=(achieved / copy_gbs) if achieved else None)
     breakdown = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]}
     log("  kernel time by class:", json.dumps(breakdown))
     log("  diagnostics:", diag)
@@ -526,11 +572,14 @@ def main():
             "particles": sc.n, "grid_res": sc.grid_res, "substeps_per_step": S,
             "tuning": {"autotuned": autotuned, **{k: tuning[k] for k in ("chunk", "sort_every", "workgroups",
                                                                          "tile_cap")}},
+            "step": "mpm_advance(S) + mpm_export_frame (x and covariances in the caller's order) on the "
+                    "scene held in the context; mpm_load untimed, before warm-up",
             "kernel_time_by_class_ms": breakdown,
             "diagnostics": {k: diag[k] for k in ("nonfinite", "out_of_grid", "tile_overflow", "tile_escapes")},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "step_n_caller_order": step_n,
         "batched_fwd_bwd": batched,
         "bgdo": bgdo,
         "per_model_fused": models,

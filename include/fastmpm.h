@@ -157,6 +157,37 @@ int mpm_substep(mpm_ctx ctx, const mpm_particles* p, void* stream);
 int mpm_step_n(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps,
                void* tape, int32_t checkpoint_every, void* stream);
 
+/* Resident stepping: the scene stays in the context between calls, in the
+ * library's cell-sorted order, so a frame loop (Alg. 1 stage-1 inner loop,
+ * one render frame every few substeps) moves only what the renderer reads.
+ *   mpm_load(ctx, p)        copies the caller's state and parameters in
+ *                           (the same arrays and rules as mpm_step_n); later
+ *                           changes to p take effect only through another
+ *                           mpm_load.
+ *   mpm_advance(ctx, n)     n >= 0 substeps of the resident state.  The
+ *                           grid of the next substep carries over between
+ *                           calls, so consecutive calls run fused substeps
+ *                           only; re-sorts follow sort_every across calls.
+ *   mpm_store(ctx, p)       writes x, v, C, F of the resident state to p's
+ *                           arrays in the caller's order (other arrays unread).
+ *   mpm_export_frame(ctx, x, cov0, cov)
+ *                           the frame's positions x [3][N] and Gaussian
+ *                           covariances cov [6][N] = F Sigma0 F^T (Sec. 3.2;
+ *                           cov0, cov as in mpm_export_covariance) in the
+ *                           caller's order; x or cov may be NULL (not both),
+ *                           cov0 is needed with cov.
+ * mpm_advance, mpm_store and mpm_export_frame return MPM_ESTATE when no state
+ * is resident: before mpm_load, and after any call that takes the context's
+ * internal state from elsewhere (mpm_step_n, mpm_substep, mpm_autotune,
+ * mpm_backward, mpm_graph_launch) or a failed mpm_advance.  None of the four
+ * may be captured into a graph (MPM_ESTATE).  Results match mpm_step_n from
+ * the same state up to FP32 rounding (the particle order at each substep
+ * differs, so global atomics add in another order). */
+int mpm_load(mpm_ctx ctx, const mpm_particles* p, void* stream);
+int mpm_advance(mpm_ctx ctx, int32_t n_steps, void* stream);
+int mpm_store(mpm_ctx ctx, const mpm_particles* p, void* stream);
+int mpm_export_frame(mpm_ctx ctx, float* x, const float* cov0, float* cov, void* stream);
+
 /* Bytes of the tape buffer for n_steps substeps checkpointed every K: the
  * checkpoints (96 B per particle each), one segment of K recomputed states
  * with their K grids (16 B per node each) and work-item boxes, and the

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_PKG, "libfastmpm.so")
 
 MPM_ABI_VERSION = 1
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_tape_size",
+EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_load",
+            "mpm_advance", "mpm_store", "mpm_export_frame", "mpm_tape_size",
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
             "mpm_set_tuning", "mpm_get_tuning", "mpm_autotune", "mpm_graph_begin", "mpm_graph_end",
             "mpm_graph_launch", "mpm_graph_destroy", "mpm_position_loss_grad", "mpm_bgdo_accumulate",
@@ -91,6 +92,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp)]),
         "mpm_substep": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp]),
         "mpm_step_n": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), i32, vp, i32, vp]),
+        "mpm_load": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp]),
+        "mpm_advance": (ctypes.c_int, [vp, i32, vp]),
+        "mpm_store": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp]),
+        "mpm_export_frame": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mpm_tape_size": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(sz)]),
         "mpm_backward": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp, i32] + [vp] * 10 + [vp]),
         "mpm_grid_state": (ctypes.c_int, [vp, vp, vp, vp, vp]),
@@ -247,6 +252,25 @@ def mpm_step_n(ctx: Context, p: Particles, n_steps: int, tape=None, checkpoint_e
     rc = load().mpm_step_n(ctx.handle, ctypes.byref(s), int(n_steps), _ptr(tape), int(checkpoint_every),
                            _stream(stream))
     _check(ctx, rc, "mpm_step_n")
+
+
+def mpm_load(ctx: Context, p: Particles, stream=None):
+    s = p.as_struct()
+    _check(ctx, load().mpm_load(ctx.handle, ctypes.byref(s), _stream(stream)), "mpm_load")
+
+
+def mpm_advance(ctx: Context, n_steps: int, stream=None):
+    _check(ctx, load().mpm_advance(ctx.handle, int(n_steps), _stream(stream)), "mpm_advance")
+
+
+def mpm_store(ctx: Context, p: Particles, stream=None):
+    s = p.as_struct()
+    _check(ctx, load().mpm_store(ctx.handle, ctypes.byref(s), _stream(stream)), "mpm_store")
+
+
+def mpm_export_frame(ctx: Context, x=None, cov0=None, cov=None, stream=None):
+    rc = load().mpm_export_frame(ctx.handle, _ptr(x), _ptr(cov0), _ptr(cov), _stream(stream))
+    _check(ctx, rc, "mpm_export_frame")
 
 
 def mpm_tape_size(ctx: Context, n_steps: int, checkpoint_every: int) -> int:

@@ -68,6 +68,14 @@ struct mpm_context {
   double prof_ms[MPM_PROFILE_CLASSES] = {0};
   int64_t prof_cnt[MPM_PROFILE_CLASSES] = {0};
 
+  // resident stepping (mpm_load / mpm_advance / mpm_store / mpm_export_frame)
+  bool resident = false;  // the internal sorted state holds the scene of the last mpm_load
+  bool primed = false;    // grid[res_cur] holds the P2G of the internal state
+  int res_cur = 0;        // grid rotation index
+  int res_bcur = 0;       // item-box buffer the next substep kernel reads
+  bool res_have_box = false;
+  int res_since_sort = 0;  // substeps since the internal state was last sorted
+
   bool capturing = false;  // between mpm_graph_begin and mpm_graph_end
   bool prof_saved = false;
   // the last taped forward (mpm_step_n with a tape)
@@ -620,6 +628,7 @@ int run_steps(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, 
     return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers the elastic models without plasticity");
   hipStream_t s = (hipStream_t)stream;
   ctx->last_stream = s;
+  ctx->resident = ctx->primed = false;  // the internal state is taken from the caller's arrays
   TapeLayout tl{};
   const int64_t N = ctx->N;
   if (tape) {
@@ -704,6 +713,121 @@ int mpm_substep(mpm_ctx ctx, const mpm_particles* p, void* stream) {
   return mpm_step_n(ctx, p, 1, nullptr, 0, stream);
 }
 
+int mpm_load(mpm_ctx ctx, const mpm_particles* p, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (ctx->capturing) return fail(ctx, MPM_ESTATE, "resident stepping is not captured into graphs");
+  int rc = check_particles(ctx, p);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  ctx->resident = ctx->primed = false;
+  if (ctx->N > 0) {
+    rc = gather_from_caller(ctx, p, s);
+    if (rc) return rc;
+  }
+  ctx->resident = true;
+  ctx->res_since_sort = 0;
+  return MPM_OK;
+}
+
+int mpm_advance(mpm_ctx ctx, int32_t n_steps, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (n_steps < 0) return fail(ctx, MPM_EINVAL, "n_steps < 0");
+  if (ctx->capturing) return fail(ctx, MPM_ESTATE, "resident stepping is not captured into graphs");
+  if (!ctx->resident) return fail(ctx, MPM_ESTATE, "no resident state: mpm_load first");
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  if (n_steps == 0 || ctx->N == 0) {
+    ctx->substeps += n_steps;
+    return MPM_OK;
+  }
+  int* boxes[2] = {ctx->item_box, ctx->item_box + 6 * (ctx->max_chunks + 1)};
+  int rc = MPM_OK;
+  if (!ctx->primed) {
+    // P2G of the loaded state into grid 0 (zeroed here); grid 1 is zeroed
+    // for the first fused kernel
+    rc = fill_u32(ctx, ctx->grid[0], 4 * ctx->nodes, s, 4, ctx->work_counter);
+    rc = rc ? rc : launch_substep<fmpm::kP2G>(ctx, nullptr, ctx->grid[0], 0, s, ctx->grid[1], nullptr, boxes[0]);
+    if (rc) {
+      ctx->resident = false;
+      return rc;
+    }
+    ctx->res_cur = 0;
+    ctx->res_bcur = 0;
+    ctx->res_have_box = true;
+    ctx->primed = true;
+  }
+  // fused substeps only: kernel k reads grid k % 3, writes grid (k + 1) % 3
+  // and zeroes grid (k + 2) % 3, and the rotation carries over to the next
+  // call.  The last kernel of the call also writes v and C, so the internal
+  // state is whole between calls.  A re-sort that falls due is done before
+  // the next kernel (the grid does not depend on the particle order).
+  int prev = ctx->res_cur;
+  for (int st = 0; st < n_steps; ++st) {
+    if (ctx->sort_every > 0 && ctx->res_since_sort >= ctx->sort_every) {
+      rc = resort_internal(ctx, s);
+      if (rc) break;
+      ctx->res_since_sort = 0;
+      ctx->res_have_box = false;
+    }
+    const int cur = ctx->res_cur, nxt = (cur + 1) % 3, clr = (cur + 2) % 3;
+    rc = launch_substep<fmpm::kFused>(ctx, ctx->grid[cur], ctx->grid[nxt], st == n_steps - 1 ? 1 : 0, s,
+                                      ctx->grid[clr], ctx->res_have_box ? boxes[ctx->res_bcur] : nullptr,
+                                      boxes[1 - ctx->res_bcur]);
+    if (rc) break;
+    ctx->res_bcur = 1 - ctx->res_bcur;
+    ctx->res_have_box = true;
+    prev = cur;
+    ctx->res_cur = nxt;
+    ++ctx->res_since_sort;
+  }
+  if (rc) {
+    ctx->resident = ctx->primed = false;
+    return rc;
+  }
+  ctx->last_grid = prev;
+  ctx->substeps += n_steps;
+  return MPM_OK;
+}
+
+int mpm_store(mpm_ctx ctx, const mpm_particles* p, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (ctx->capturing) return fail(ctx, MPM_ESTATE, "resident stepping is not captured into graphs");
+  if (!p) return fail(ctx, MPM_EINVAL, "particles is NULL");
+  if (!ctx->resident) return fail(ctx, MPM_ESTATE, "no resident state: mpm_load first");
+  if (ctx->N == 0) return MPM_OK;
+  if (!p->x || !p->v || !p->C || !p->F) return fail(ctx, MPM_EINVAL, "a state array is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  return scatter_to_caller(ctx, p, s);
+}
+
+int mpm_export_frame(mpm_ctx ctx, float* x, const float* cov0, float* cov, void* stream) {
+  if (!ctx) return MPM_EINVAL;
+  if (ctx->capturing) return fail(ctx, MPM_ESTATE, "resident stepping is not captured into graphs");
+  if (!ctx->resident) return fail(ctx, MPM_ESTATE, "no resident state: mpm_load first");
+  if (!x && !cov) return fail(ctx, MPM_EINVAL, "x and cov are both NULL");
+  if (cov && !cov0) return fail(ctx, MPM_EINVAL, "cov without cov0");
+  const int64_t N = ctx->N;
+  if (N == 0) return MPM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_stream = s;
+  ProfScope ps(ctx, s, 5);
+  // x, and F into the re-sort buffer, to caller order in one permutation;
+  // then the covariances elementwise in caller order
+  int rc = perm_prepare(ctx, ctx->pid, s);
+  fmpm::PlaneSet pl{};
+  if (x) add_planes(pl, ctx->xs, x, 3, N);
+  if (cov) add_planes(pl, ctx->Fs, ctx->Fs2, 9, N);
+  rc = rc ? rc : perm_apply(ctx, pl, s);
+  if (rc) return rc;
+  if (cov) {
+    fmpm::k_covariance<<<blocks_for(N, 256), 256, 0, s>>>(ctx->Fs2, cov0, cov, N);
+    LAUNCH_CHECK(ctx, "k_covariance");
+  }
+  return MPM_OK;
+}
+
 int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes) {
   if (!ctx || !bytes || n_steps < 0 || checkpoint_every < 1) return MPM_EINVAL;
   *bytes = tape_layout(ctx, n_steps, checkpoint_every, nullptr).bytes;
@@ -723,6 +847,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     return fail(ctx, MPM_ESTATE, "tape does not hold the last taped mpm_step_n of this length");
   hipStream_t s = (hipStream_t)stream;
   ctx->last_stream = s;
+  ctx->resident = ctx->primed = false;  // the recompute overwrites the internal state
   const int64_t N = ctx->N;
   const int K = ctx->tape_K;
   TapeLayout tl = tape_layout(ctx, n_steps, K, const_cast<void*>(tape));
@@ -1006,6 +1131,7 @@ int mpm_autotune(mpm_ctx ctx, const mpm_particles* p, int32_t trial_steps, void*
 struct mpm_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  mpm_ctx ctx = nullptr;
 };
 
 int mpm_graph_begin(mpm_ctx ctx, void* stream) {
@@ -1040,6 +1166,7 @@ int mpm_graph_end(mpm_ctx ctx, void* stream, mpm_graph* out) {
   mpm_graph g = new mpm_graph_s();
   g->graph = graph;
   g->exec = exec;
+  g->ctx = ctx;
   *out = g;
   return MPM_OK;
 }
@@ -1082,6 +1209,7 @@ int mpm_bgdo_apply(mpm_ctx ctx, float* log_E, const float* g_total, int32_t n_ke
 
 int mpm_graph_launch(mpm_graph g, void* stream) {
   if (!g) return MPM_EINVAL;
+  g->ctx->resident = g->ctx->primed = false;  // a replay rewrites the internal state
   return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? MPM_OK : MPM_EDEVICE;
 }
 

@@ -1,0 +1,155 @@
+"""Resident stepping through the C ABI: mpm_load copies a scene into the
+context once, mpm_advance runs substeps on it with the next substep's grid
+carried between calls (fused substeps only, re-sorts on the sort_every
+cadence across calls), mpm_store and mpm_export_frame bring state back in
+the caller's order.  Checked against the oracle, against mpm_step_n from the
+same state, and the frame export against mpm_store + mpm_export_covariance."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mpm_oracle as O
+from paper_2602_01723_amd import binding as B
+from paper_2602_01723_amd import scenes
+from tests.parity import TOL_LONG_X, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _particles(sc, order):
+    return B.Particles.from_arrays(sc.x[order], sc.v[order], sc.C[order], sc.F[order], sc.mass[order],
+                                   sc.vol0[order], sc.log_E[order], sc.nu[order], sc.mat_id[order])
+
+
+def _spd_cov(rng, N):
+    q = rng.normal(0, 1, (N, 3, 3))
+    S = q @ q.transpose(0, 2, 1) * 1e-4
+    return np.stack([S[:, 0, 0], S[:, 0, 1], S[:, 0, 2], S[:, 1, 1], S[:, 1, 2], S[:, 2, 2]], 0).astype(np.float32)
+
+
+def test_cube_lattice_resident_frames_match_oracle():
+    """100 substeps as five calls of 20, re-sorting every 8 substeps across
+    the call boundaries, against the oracle's 100 substeps."""
+    sc = scenes.make_scene("cube_lattice")
+    ctx = B.init_from_scene(sc, sort_every=8)
+    p = B.Particles.from_scene(sc)
+    B.mpm_load(ctx, p)
+    for _ in range(5):
+        B.mpm_advance(ctx, 20)
+    B.mpm_store(ctx, p)
+    torch.cuda.synchronize()
+    d = B.mpm_get_diagnostics(ctx)
+    assert d["nonfinite"] == 0 and d["out_of_grid"] == 0, d
+    xg = p.state_numpy()[0]
+    xr = O.step_n(O.state_from_scene(sc), O.Params.from_scene(sc), 100)[0].numpy()
+    err = np.abs(xg - xr).max() / np.abs(xr).max()
+    disp = np.linalg.norm((xg - sc.x) - (xr - sc.x)) / np.linalg.norm(xr - sc.x)
+    print("x rel", err, "displacement rel", disp, flush=True)
+    assert err <= TOL_LONG_X
+    assert disp <= 1e-3
+
+
+@pytest.mark.parametrize("sort_every", [5, 64])
+def test_resident_matches_step_n(sort_every):
+    """Mixed materials (plastic included), shuffled caller order, calls of
+    uneven length (7, 1, 12 substeps): the state after mpm_store, v and C
+    included, equals one mpm_step_n of 20 substeps up to the order of the
+    grid atomics."""
+    sc = scenes.make_scene("gaussian_cloud", n_total=60000)
+    sc.v = np.random.default_rng(4).normal(0, 0.5, sc.v.shape).astype(np.float32)
+    order = np.random.default_rng(3).permutation(sc.n)
+    ctx_a = B.init_from_scene(sc, sort_every=sort_every)
+    pa = _particles(sc, order)
+    B.mpm_load(ctx_a, pa)
+    for n in (7, 1, 12):
+        B.mpm_advance(ctx_a, n)
+    B.mpm_store(ctx_a, pa)
+    ctx_b = B.init_from_scene(sc, sort_every=sort_every)
+    pb = _particles(sc, order)
+    B.mpm_step_n(ctx_b, pb, 20)
+    torch.cuda.synchronize()
+    for c in (ctx_a, ctx_b):
+        d = B.mpm_get_diagnostics(c)
+        assert d["nonfinite"] == 0 and d["out_of_grid"] == 0, d
+    a, b = pa.state_numpy(), pb.state_numpy()
+    s_v = max(float(np.abs(b[1]).max()), 9.8 * sc.dt)
+    floors = (1.0 / sc.grid_res, s_v, s_v * sc.grid_res, 1.0)
+    for k in range(4):
+        e = rel_err(a[k], b[k], floors[k])
+        print("resident vs step_n", k, e, flush=True)
+        assert e <= 1e-5, (k, e)
+    moved = np.abs(a[0] - sc.x[order]).max() * sc.grid_res
+    assert moved > 0.05, moved
+
+
+def test_export_frame_matches_store_and_covariance():
+    """x and F Sigma0 F^T from the resident state equal, bit for bit, mpm_store's
+    x and mpm_export_covariance of mpm_store's F; x alone and cov alone too."""
+    sc = scenes.make_scene("gaussian_cloud", n_total=30000)
+    rng = np.random.default_rng(11)
+    order = rng.permutation(sc.n)
+    N = sc.n
+    ctx = B.init_from_scene(sc, sort_every=4)
+    p = _particles(sc, order)
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 9)
+    cov0 = torch.tensor(_spd_cov(rng, N)).cuda()
+    x_out = torch.empty(3, N, device="cuda")
+    cov_out = torch.empty(6, N, device="cuda")
+    B.mpm_export_frame(ctx, x_out, cov0, cov_out)
+    x_only = torch.empty(3, N, device="cuda")
+    B.mpm_export_frame(ctx, x_only, None, None)
+    cov_only = torch.empty(6, N, device="cuda")
+    B.mpm_export_frame(ctx, None, cov0, cov_only)
+    B.mpm_store(ctx, p)
+    ref_cov = torch.empty(6, N, device="cuda")
+    B.mpm_export_covariance(ctx, p.F, cov0, ref_cov)
+    torch.cuda.synchronize()
+    assert torch.equal(x_out, p.x) and torch.equal(x_only, p.x)
+    assert torch.equal(cov_out, ref_cov) and torch.equal(cov_only, ref_cov)
+    # the export leaves the resident state as it was: continuing matches
+    B.mpm_advance(ctx, 3)
+    B.mpm_export_frame(ctx, x_out, None, None)
+    B.mpm_store(ctx, p)
+    torch.cuda.synchronize()
+    assert torch.equal(x_out, p.x)
+
+
+def test_resident_state_rules():
+    sc = scenes.make_scene("gaussian_cloud", n_total=5000)
+    ctx = B.init_from_scene(sc)
+    p = B.Particles.from_scene(sc)
+    for call in (lambda: B.mpm_advance(ctx, 1), lambda: B.mpm_store(ctx, p),
+                 lambda: B.mpm_export_frame(ctx, p.x, None, None)):
+        with pytest.raises(B.MPMError) as e:  # nothing loaded
+            call()
+        assert e.value.status == B.MPM_ESTATE
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 0)
+    B.mpm_advance(ctx, 2)
+    with pytest.raises(B.MPMError) as e:
+        B.mpm_advance(ctx, -1)
+    assert e.value.status == B.MPM_EINVAL
+    with pytest.raises(B.MPMError) as e:
+        B.mpm_export_frame(ctx, None, None, None)
+    assert e.value.status == B.MPM_EINVAL
+    with pytest.raises(B.MPMError) as e:
+        B.mpm_export_frame(ctx, None, None, torch.empty(6, sc.n, device="cuda"))
+    assert e.value.status == B.MPM_EINVAL
+    B.mpm_step_n(ctx, p, 1)  # takes the internal state from the caller's arrays
+    with pytest.raises(B.MPMError) as e:
+        B.mpm_advance(ctx, 1)
+    assert e.value.status == B.MPM_ESTATE
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 1)
+    B.mpm_store(ctx, p)
+    torch.cuda.synchronize()
+
+
+def test_resident_zero_particles():
+    ctx = B.mpm_init(16, 1e-4, [dict(elastic=0, plastic=0, yield_stress=0.0, friction_deg=0.0)], 0)
+    p = B.Particles.from_arrays(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3, 3)), np.zeros((0, 3, 3)),
+                                np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0, np.int32))
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 3)
+    B.mpm_store(ctx, p)
