@@ -378,21 +378,12 @@ __device__ __forceinline__ void update_and_stress(const Material& mat, double mu
 #pragma unroll
     for (int k = 0; k < 9; ++k) Fs[k] = Ftr[k];
   }
-  if (mat.elastic >= kElasticNeoHookean) {
-    if (svd_plastic) {
-      double U[3][3], V[3][3], sig[3], eps[3];
-      svd3(Fs, U, sig, V);
-      return_map(mat, mu, lam, Fs, U, sig, V, Fout, eps);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Fout[k] = Fs[k];
-    }
-    if (want_stress) tau_closed_form(mat.elastic, Fout, mu, lam, tau);
-    return;
-  }
+  // one SVD call site for every model (the code is inlined per call site):
+  // von Mises / Drucker-Prager, Hencky, and the fixed-corotated fallback
+  const bool closed = mat.elastic >= kElasticNeoHookean;
   double R[9];
   bool have_R = false;
-  if (!svd_plastic && mat.elastic == kElasticFCR) {
+  if (!closed && !svd_plastic && mat.elastic == kElasticFCR) {
     if (!want_stress) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fout[k] = Fs[k];
@@ -401,7 +392,7 @@ __device__ __forceinline__ void update_and_stress(const Material& mat, double mu
     have_R = polar_rotation_newton(Fs, R);
   }
   double U[3][3], V[3][3], eps[3];
-  if (!have_R) {
+  if (svd_plastic || (!closed && !have_R)) {
     double sig[3];
     svd3(Fs, U, sig, V);
     if (svd_plastic) {
@@ -412,7 +403,7 @@ __device__ __forceinline__ void update_and_stress(const Material& mat, double mu
 #pragma unroll
       for (int k = 0; k < 3; ++k) eps[k] = log(fmax(sig[k], kSigmaMin));
     }
-    if (mat.elastic == kElasticFCR) {
+    if (!closed && mat.elastic == kElasticFCR) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -423,7 +414,9 @@ __device__ __forceinline__ void update_and_stress(const Material& mat, double mu
     for (int k = 0; k < 9; ++k) Fout[k] = Fs[k];
   }
   if (!want_stress) return;
-  if (mat.elastic == kElasticFCR)
+  if (closed)
+    tau_closed_form(mat.elastic, Fout, mu, lam, tau);
+  else if (mat.elastic == kElasticFCR)
     tau_fixed_corotated_R(Fout, R, mu, lam, tau);
   else
     tau_hencky_eps(U, eps, mu, lam, tau);
