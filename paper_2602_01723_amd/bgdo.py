@@ -2,8 +2,9 @@
 App. B.3-B.4), driven through the C ABI.
 
 Stage 1 advances the particles without gradients for `frames` frames of
-`substeps_per_frame` substeps (mpm_step_n) and keeps a device copy of the
-state at the start of every key frame.  Stage 2 takes, for each stored key
+`substeps_per_frame` substeps (the scene held in the context: mpm_load once,
+mpm_advance per frame) and keeps a device copy of the state at the start of
+every key frame (mpm_store).  Stage 2 takes, for each stored key
 frame, one substep from it (mpm_substep on a copy) and lets
 mpm_bgdo_accumulate add the per-particle term
     eta log(1 + |d|tau|/d log E|) - (1 - eta) (|F' - I|_F - delta_target),
@@ -41,10 +42,12 @@ def bgdo(ctx: B.Context, particles: B.Particles, frames: int, substeps_per_frame
         p = init.clone()
         p.log_E = particles.log_E
         stored = []
+        B.mpm_load(ctx, p, stream=stream)
         for frame in range(frames):  # stage 1: gradient-free forward run
             if frame in keys:
+                B.mpm_store(ctx, p, stream=stream)
                 stored.append(p.clone())
-            B.mpm_step_n(ctx, p, substeps_per_frame, stream=stream)
+            B.mpm_advance(ctx, substeps_per_frame, stream=stream)
         g_total = torch.zeros(particles.n, dtype=torch.float32, device=particles.log_E.device)
         for snap in stored:  # stage 2: one substep from each key frame
             nxt = snap.clone()
