@@ -153,3 +153,39 @@ def test_resident_zero_particles():
     B.mpm_load(ctx, p)
     B.mpm_advance(ctx, 3)
     B.mpm_store(ctx, p)
+
+
+@pytest.mark.parametrize("tile_cap", [0, 27])
+def test_resident_batched_scenes_match_step_n(tile_cap):
+    """Six scenes of uneven size on their own grids in one context (the
+    candidate batch), with tile_cap 27 also sending every item down the
+    global-memory node path: resident calls of 9 and 11 substeps against
+    one mpm_step_n of 20."""
+    sc = scenes.make_scene("candidate_batch", n_batch=6, n_min=1500, n_max=6000, grid_res=32, n_substeps=60,
+                           dt=2e-4, seed=7)
+    outs = []
+    for resident in (True, False):
+        ctx = B.init_from_scene(sc, sort_every=6)
+        if tile_cap:
+            B.mpm_set_tuning(ctx, tile_cap=tile_cap)
+        p = B.Particles.from_scene(sc)
+        if resident:
+            B.mpm_load(ctx, p)
+            B.mpm_advance(ctx, 9)
+            B.mpm_advance(ctx, 11)
+            B.mpm_store(ctx, p)
+        else:
+            B.mpm_step_n(ctx, p, 20)
+        torch.cuda.synchronize()
+        d = B.mpm_get_diagnostics(ctx)
+        assert d["nonfinite"] == 0 and d["out_of_grid"] == 0, d
+        if tile_cap:
+            assert d["tile_overflow"] > 0, d
+        outs.append(p.state_numpy())
+    a, b = outs
+    s_v = max(float(np.abs(b[1]).max()), 9.8 * sc.dt)
+    floors = (1.0 / sc.grid_res, s_v, s_v * sc.grid_res, 1.0)
+    for k in range(4):
+        e = rel_err(a[k], b[k], floors[k])
+        print("batched resident vs step_n", tile_cap, k, e, flush=True)
+        assert e <= 1e-5, (k, e)
