@@ -70,6 +70,44 @@ def measured_traffic(n_particles):
     return t["fused_fetch_kib"] * 1024.0 * f_scale + t["fused_write_kib"] * 1024.0 * w_scale
 
 
+# VALU issue of the fused kernel: one wave64 VALU instruction per SIMD every
+# 4 clocks (16 lanes), 4 SIMDs per CU, 256 CUs at 2.4 GHz = 39.32e12 lane
+# instructions/s.  The same issue rate gives the 78.6 TFLOP/s FP32 (unpacked)
+# and FP64 FMA peaks.
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+VALU_FILE = os.path.join(ROOT, "profiles", "fused_substep_large_scene_valu.json")
+VALU_COMMAND = ("cd /tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+                "SQ_INSTS_LDS SQ_WAIT_INST_ANY SQ_INSTS_SALU --kernel-include-regex k_substep -f csv -d <out>/pmc_p1 "
+                "-o p1 -- python3 <repo>/bench.py --steps 1 --warmup 1 --substeps-per-step 10 --no-autotune "
+                "--no-step-n --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis")
+
+
+def write_valu(p1_csv, n_particles=2_000_000):
+    """Summarise the p1 instruction-mix pass (SQ_INSTS_VALU) of the fused
+    kernel into VALU_FILE, stamped with the kernel source hash."""
+    c = summarize_counters([p1_csv], n_particles=n_particles)
+    out = {"kernel": "k_substep<1>", "particles": n_particles, "dispatches": c["dispatches"],
+           "valu_instructions_per_particle": c["valu_instructions_per_particle"],
+           "kernel_source_hash": kernel_source_hash(),
+           "command": VALU_COMMAND}
+    with open(VALU_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def measured_valu(n_particles):
+    """VALU lane instructions per particle of the fused kernel from the
+    committed counter summary, or None if the kernel sources changed since."""
+    try:
+        with open(VALU_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("particles") != n_particles:
+        return None
+    return t["valu_instructions_per_particle"]
+
+
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
                "--steps 1 --warmup 1 --substeps-per-step 10 --no-autotune --no-step-n --no-cpu-baseline --no-batched "
                "--no-bgdo --no-models --no-mcis")
@@ -403,6 +441,8 @@ def main():
                     help="per-dispatch counter means of the fused kernel from rocprofv3 --pmc runs, and exit")
     ap.add_argument("--summarize-batched-trace", metavar="TRACE_CSV",
                     help="per-kernel time of one batched evaluation in a rocprofv3 trace, and exit (no GPU use)")
+    ap.add_argument("--write-valu", metavar="P1_CSV",
+                    help="summarise the p1 instruction-mix counter run into the VALU file and exit (no GPU use)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
     args = ap.parse_args()
@@ -411,6 +451,9 @@ def main():
         return
     if args.summarize_batched_trace:
         print(summarize_batched_trace(args.summarize_batched_trace))
+        return
+    if args.write_valu:
+        print(json.dumps(write_valu(args.write_valu, n_particles=args.n_total)))
         return
     if args.write_traffic:
         print(json.dumps(write_traffic(*args.write_traffic, n_particles=args.n_total)))
@@ -516,6 +559,14 @@ def main():
                     bytes_per_launch=bytes_launch, avg_launch_us=fused_avg_s * 1e6, launches=fused_n,
                     active_nodes=active, copy_attained=copy_gbs,
                     frac_of_copy=(achieved / copy_gbs) if achieved else None)
+    # what does bound the kernel: VALU issue (counter-measured instructions
+    # per particle over the live launch time, against the issue peak)
+    ipp = measured_valu(sc.n)
+    if ipp and fused_n:
+        issued = ipp * sc.n / fused_avg_s
+        roofline["valu_issue"] = dict(instructions_per_particle=ipp, achieved=issued / 1e12,
+                                      peak=VALU_PEAK_LANE_INSTR / 1e12, unit="T lane-instructions/s",
+                                      frac=issued / VALU_PEAK_LANE_INSTR)
     breakdown = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]}
     log("  kernel time by class:", json.dumps(breakdown))
     log("  diagnostics:", diag)
