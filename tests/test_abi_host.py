@@ -81,6 +81,10 @@ def test_invalid_materials_and_offsets(lib):
 def test_null_arguments(lib):
     assert lib.mpm_init(None, None, 0, 0, None, None) == B.MPM_EINVAL
     assert lib.mpm_step_n(None, None, 1, None, 0, None) == B.MPM_EINVAL
+    assert lib.mpm_load(None, None, None) == B.MPM_EINVAL
+    assert lib.mpm_advance(None, 1, None) == B.MPM_EINVAL
+    assert lib.mpm_store(None, None, None) == B.MPM_EINVAL
+    assert lib.mpm_export_frame(None, None, None, None, None) == B.MPM_EINVAL
     assert lib.mpm_destroy(None) == B.MPM_EINVAL
     assert lib.mpm_get_diagnostics(None, None) == B.MPM_EINVAL
     assert lib.mpm_last_error(None) == b"NULL context"
