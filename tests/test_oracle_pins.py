@@ -679,3 +679,71 @@ def test_mcis_instances_union_and_limits():
     assert all(300 <= j < 900 for j in sel[300:].tolist())
     # the instance's own surface sets the distance
     assert torch.allclose(d[300:], O.mcis_distance(cand[300:], surf[150:]))
+
+
+# --------------------------------------------------------------------------
+# Gaussian covariance at a frame boundary (Sec. 3.2): Sigma = F Sigma0 F^T,
+# stored as (xx, xy, xz, yy, yz, zz)
+# --------------------------------------------------------------------------
+
+def _sym6(S):
+    return np.stack([S[:, 0, 0], S[:, 0, 1], S[:, 0, 2], S[:, 1, 1], S[:, 1, 2], S[:, 2, 2]], -1)
+
+
+def _full(c):
+    return np.stack([np.stack([c[:, 0], c[:, 1], c[:, 2]], -1), np.stack([c[:, 1], c[:, 3], c[:, 4]], -1),
+                     np.stack([c[:, 2], c[:, 4], c[:, 5]], -1)], 1)
+
+
+def test_covariance_closed_forms():
+    rng = np.random.default_rng(31)
+    N = 64
+    q = rng.normal(0, 1, (N, 3, 3))
+    S0 = q @ q.transpose(0, 2, 1) + 0.1 * np.eye(3)
+    c0 = _sym6(S0)
+    # identity: unchanged
+    out = O.covariance(torch.eye(3, dtype=F64).expand(N, 3, 3), c0).numpy()
+    assert np.allclose(out, c0, rtol=0, atol=1e-15)
+    # diagonal stretch s: every entry (i, j) scales by s_i s_j (catches a
+    # swapped component or a transposed product)
+    s = rng.uniform(0.5, 2.0, (N, 3))
+    out = _full(O.covariance(torch.tensor(np.einsum("ni,ij->nij", s, np.eye(3))), c0).numpy())
+    assert np.allclose(out, S0 * s[:, :, None] * s[:, None, :], rtol=1e-14, atol=0)
+    # rotation: the spectrum is kept, and the axes turn with F
+    for k in range(8):
+        Q = rot(rng).numpy()
+        d = np.sort(rng.uniform(0.1, 3.0, 3))
+        out = _full(O.covariance(torch.tensor(Q[None]), _sym6(np.diag(d)[None])).numpy())[0]
+        assert np.allclose(np.linalg.eigvalsh(out), d, rtol=1e-13)
+        assert np.allclose(out @ Q[:, 0], d[0] * Q[:, 0], atol=1e-12)
+
+
+def test_covariance_pushes_the_level_set_forward():
+    """Points on the unit level set x^T Sigma0^-1 x = 1, mapped by F, lie on
+    y^T Sigma^-1 y = 1; det Sigma = det(F)^2 det Sigma0."""
+    rng = np.random.default_rng(32)
+    for k in range(10):
+        q = rng.normal(0, 1, (3, 3))
+        S0 = q @ q.T + 0.2 * np.eye(3)
+        F = np.eye(3) + rng.normal(0, 0.3, (3, 3))
+        S = _full(O.covariance(torch.tensor(F[None]), _sym6(S0[None])).numpy())[0]
+        L = np.linalg.cholesky(S0)
+        u = rng.normal(0, 1, (3, 200))
+        x = L @ (u / np.linalg.norm(u, axis=0))  # x^T S0^-1 x = 1
+        y = F @ x
+        lvl = np.einsum("ip,ij,jp->p", y, np.linalg.inv(S), y)
+        assert np.allclose(lvl, 1.0, rtol=1e-11)
+        assert math.isclose(np.linalg.det(S), np.linalg.det(F) ** 2 * np.linalg.det(S0), rel_tol=1e-11)
+
+
+def test_covariance_of_mapped_samples():
+    """The covariance of F z for z ~ N(0, Sigma0) (200,000 samples) is
+    Sigma to sampling accuracy."""
+    rng = np.random.default_rng(33)
+    q = rng.normal(0, 1, (3, 3))
+    S0 = q @ q.T + 0.3 * np.eye(3)
+    F = np.eye(3) + rng.normal(0, 0.4, (3, 3))
+    z = rng.multivariate_normal(np.zeros(3), S0, 200_000)
+    emp = np.cov((z @ F.T).T)
+    S = _full(O.covariance(torch.tensor(F[None]), _sym6(S0[None])).numpy())[0]
+    assert np.abs(emp - S).max() <= 0.02 * np.abs(S).max()
