@@ -189,3 +189,57 @@ def test_resident_batched_scenes_match_step_n(tile_cap):
         e = rel_err(a[k], b[k], floors[k])
         print("batched resident vs step_n", tile_cap, k, e, flush=True)
         assert e <= 1e-5, (k, e)
+
+
+def test_resident_calls_and_graphs():
+    """The resident calls refuse graph capture, and replaying a graph that
+    holds mpm_step_n replaces the internal state, which ends residency."""
+    sc = scenes.make_scene("gaussian_cloud", n_total=5000)
+    ctx = B.init_from_scene(sc)
+    p = B.Particles.from_scene(sc)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    B.mpm_graph_begin(ctx, stream)
+    try:
+        with pytest.raises(B.MPMError) as e:
+            B.mpm_load(ctx, p, stream=stream)
+        assert e.value.status == B.MPM_ESTATE
+        B.mpm_step_n(ctx, p, 2, stream=stream)
+    finally:
+        g = B.mpm_graph_end(ctx, stream, keep=(p,))
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 1)
+    torch.cuda.synchronize()
+    g.launch(stream)
+    stream.synchronize()
+    with pytest.raises(B.MPMError) as e:
+        B.mpm_advance(ctx, 1)
+    assert e.value.status == B.MPM_ESTATE
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 1)
+    torch.cuda.synchronize()
+
+
+def test_resident_tuning_change_between_calls():
+    """A new item size set between calls takes effect at the next re-sort;
+    the state still matches mpm_step_n."""
+    sc = scenes.make_scene("gaussian_cloud", n_total=40000)
+    sc.v = np.random.default_rng(8).normal(0, 0.5, sc.v.shape).astype(np.float32)
+    ctx = B.init_from_scene(sc, sort_every=4)
+    p = B.Particles.from_scene(sc)
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 5)
+    B.mpm_set_tuning(ctx, chunk=256, workgroups=300)
+    B.mpm_advance(ctx, 7)
+    B.mpm_store(ctx, p)
+    ref_ctx = B.init_from_scene(sc, sort_every=4)
+    q = B.Particles.from_scene(sc)
+    B.mpm_step_n(ref_ctx, q, 12)
+    torch.cuda.synchronize()
+    a, b = p.state_numpy(), q.state_numpy()
+    s_v = max(float(np.abs(b[1]).max()), 9.8 * sc.dt)
+    floors = (1.0 / sc.grid_res, s_v, s_v * sc.grid_res, 1.0)
+    for k in range(4):
+        e = rel_err(a[k], b[k], floors[k])
+        print("retuned resident vs step_n", k, e, flush=True)
+        assert e <= 1e-5, (k, e)
