@@ -1086,12 +1086,24 @@ __global__ __launch_bounds__(512) void k_perm_pass1_staged(float* tmp, PlaneSet 
   }
   // planes kPermPlanes blockIdx.y ... (+ kPermPlanes - 1): fewer planes per
   // workgroup put more workgroups in flight, more share the prologue
-  const int c1 = min(ps.planes, (int)(blockIdx.y + 1) * kPermPlanes);
-  for (int c = blockIdx.y * kPermPlanes; c < c1; ++c) {
-    const float* in = ps.in[c] + s0;
+  // the next plane's loads are issued before this plane's LDS round trip
+  const int c0 = blockIdx.y * kPermPlanes;
+  const int c1 = min(ps.planes, c0 + kPermPlanes);
+  float nxt[kSrc];
+#pragma unroll
+  for (int k = 0; k < kSrc; ++k) nxt[k] = loc[k] >= 0 ? ps.in[c0][s0 + k * 512 + threadIdx.x] : 0.0f;
+  for (int c = c0; c < c1; ++c) {
+    float cur[kSrc];
+#pragma unroll
+    for (int k = 0; k < kSrc; ++k) cur[k] = nxt[k];
+    if (c + 1 < c1) {
+      const float* in = ps.in[c + 1] + s0;
+#pragma unroll
+      for (int k = 0; k < kSrc; ++k) nxt[k] = loc[k] >= 0 ? in[k * 512 + threadIdx.x] : 0.0f;
+    }
 #pragma unroll
     for (int k = 0; k < kSrc; ++k)
-      if (loc[k] >= 0) buf[loc[k]] = in[k * 512 + threadIdx.x];
+      if (loc[k] >= 0) buf[loc[k]] = cur[k];
     __syncthreads();
     float* out = tmp + c * N;
     for (int l = threadIdx.x; l < nt; l += 512) {
@@ -1121,11 +1133,22 @@ __global__ __launch_bounds__(1024) void k_perm_pass2(PlaneSet ps, const float* t
       if (d >= 0 && d < cnt) o[k] = (int)d;
     }
   }
+  // the next plane's loads are issued before this plane's LDS round trip
+  float nxt[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) nxt[k] = o[k] >= 0 ? tmp[base + k * 1024 + threadIdx.x] : 0.0f;
   for (int c = 0; c < ps.planes; ++c) {
-    const float* t = tmp + c * N + base;
+    float cur[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) cur[k] = nxt[k];
+    if (c + 1 < ps.planes) {
+      const float* t = tmp + (c + 1) * N + base;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) nxt[k] = o[k] >= 0 ? t[k * 1024 + threadIdx.x] : 0.0f;
+    }
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
-      if (o[k] >= 0) buf[o[k]] = t[k * 1024 + threadIdx.x];
+      if (o[k] >= 0) buf[o[k]] = cur[k];
     __syncthreads();
     for (int k = threadIdx.x; k < cnt; k += 1024) ps.out[c][base + k] = buf[k];
     __syncthreads();
