@@ -21,15 +21,29 @@ from tests.parity import TOL_SUBSTEP, rel_err
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def fullsize_step():
+@pytest.fixture(scope="module", params=["step_n", "resident"])
+def fullsize_step(request):
+    """The substep after 40 others, through mpm_step_n (as configured by
+    default), or through the resident frame loop that bench.py times
+    (re-sort every 32 substeps; the last substep's G2P reads the grid that
+    the previous mpm_advance call left behind)."""
     sc = scenes.make_scene("large_scene")
-    ctx = B.init_from_scene(sc)
     p = B.Particles.from_scene(sc)
-    B.mpm_step_n(ctx, p, 40)  # deform the bodies first (2 re-sorts, work-item tables rebuilt)
-    torch.cuda.synchronize()
-    state0 = p.state_numpy()
-    B.mpm_substep(ctx, p)
+    if request.param == "step_n":
+        ctx = B.init_from_scene(sc)
+        B.mpm_step_n(ctx, p, 40)  # deform the bodies first (re-sorts, work-item tables rebuilt)
+        torch.cuda.synchronize()
+        state0 = p.state_numpy()
+        B.mpm_substep(ctx, p)
+    else:
+        ctx = B.init_from_scene(sc, sort_every=32)
+        B.mpm_load(ctx, p)
+        B.mpm_advance(ctx, 40)
+        B.mpm_store(ctx, p)
+        torch.cuda.synchronize()
+        state0 = p.state_numpy()
+        B.mpm_advance(ctx, 1)
+        B.mpm_store(ctx, p)
     torch.cuda.synchronize()
     m, mv, v = (t.cpu().numpy().astype(np.float64) for t in B.grid_state(ctx))
     diag = B.mpm_get_diagnostics(ctx)
