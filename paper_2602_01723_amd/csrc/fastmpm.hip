@@ -926,9 +926,10 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::k_substep<fmpm::kFused><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(ctx, "recompute substep");
     }
-    // (3) adjoint of the segment's final state, in sorted order
-    rc = perm_prepare(ctx, ctx->pdest, s);  // caller index -> slot, as in (1)
-    rc = rc ? rc : perm_block(ctx, tl.adjc, tl.adj, 24, s);
+    // (3) adjoint of the segment's final state, in sorted order, through
+    // the permutation (1) prepared (caller index -> slot; the recompute
+    // leaves it in place)
+    rc = perm_block(ctx, tl.adjc, tl.adj, 24, s);
     rc = rc ? rc : fill_u32(ctx, tl.gl, N, s);
     rc = rc ? rc : fill_u32(ctx, tl.gn, N, s);
     if (rc) return rc;
