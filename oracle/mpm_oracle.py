@@ -29,11 +29,15 @@ What it computes, step by step, in float64 with plain PyTorch CPU ops:
       Gaussian weight with floor, normalised probability,
       sampling without replacement by exponential keys
 
-The adjoint is torch autograd through the same steps (``adjoint``), with the
-polar factor of the fixed-corotated model computed by the Newton iteration
-X <- (X + X^-T) / 2 instead of an SVD, whose derivative is undefined at
-repeated singular values (e.g. F = I).  It is restricted to the elastic
-(identity-plasticity) models and to det F > 0.
+The adjoint is torch autograd through the same steps (``adjoint``), with
+SVD-free forms of the pieces whose SVD derivative is undefined at repeated
+singular values (e.g. F = I): the polar factor of the fixed-corotated model
+by the Newton iteration X <- (X + X^-T) / 2, the Hencky log strain by the
+matrix logarithm of F F^T, and the von Mises / Drucker-Prager return maps
+written as matrix functions of F (see ``_return_flow_differentiable``).  It
+covers every elastic model and every return map, for det F > 0 (the
+singular-value floor of the log strain is not applied there: it acts only
+below sigma = 1e-4).
 
 Readings of points the paper leaves open:
   * grid nodes sit at i*dx, i in [0, n); base = floor(x/dx - 0.5) per axis,
@@ -425,7 +429,7 @@ def covariance(F, cov0_6):
 
 
 # ---------------------------------------------------------------------------
-# Adjoint (autograd through the elastic substep)
+# Adjoint (autograd through the substep)
 # ---------------------------------------------------------------------------
 
 def polar_rotation_newton(F, iters=40):
@@ -444,13 +448,12 @@ def _tau_fcr_differentiable(F, mu, lam):
         + (lam * J * (J - 1.0))[:, None, None] * eye
 
 
-def _tau_hencky_differentiable(F, mu, lam):
-    """Hencky tau = mu log(F F^T) + (lam/2) tr(log(F F^T)) I, the log of the
-    SPD matrix b = F F^T taken by inverse scaling and squaring (square roots
-    by the Denman-Beavers iteration, then the log series), so no SVD enters
-    the derivative."""
-    b = F @ F.transpose(-1, -2)
-    eye = torch.eye(3, dtype=F.dtype).expand_as(b)
+def _log_spd(b):
+    """Logarithm of symmetric positive definite 3x3 matrices by inverse
+    scaling and squaring: eight square roots (Denman-Beavers iteration) bring
+    b close to I, then the log series, scaled back by 2^8.  No SVD enters the
+    derivative."""
+    eye = torch.eye(3, dtype=b.dtype).expand_as(b)
     k = 0
     Y = b
     # square roots until close to I
@@ -467,9 +470,100 @@ def _tau_hencky_differentiable(F, mu, lam):
     for j in range(1, 30):
         P = P @ X
         L = L + ((-1.0) ** (j + 1) / j) * P
-    logb = (2.0 ** k) * L
+    return (2.0 ** k) * L
+
+
+def _tau_hencky_differentiable(F, mu, lam):
+    """Hencky tau = mu log(F F^T) + (lam/2) tr(log(F F^T)) I, with the matrix
+    log of b = F F^T from ``_log_spd``."""
+    b = F @ F.transpose(-1, -2)
+    eye = torch.eye(3, dtype=F.dtype).expand_as(b)
+    logb = _log_spd(b)
     tr = logb.diagonal(dim1=-2, dim2=-1).sum(-1)
     return mu[:, None, None] * logb + (0.5 * lam * tr)[:, None, None] * eye
+
+
+# Return maps as matrix functions of F (for the adjoint).  With F = U diag(s) V^T,
+# L = log S = (1/2) log(F^T F) = V diag(eps) V^T, m = tr(eps)/3 = log(J)/3 and
+# |eps_hat| = |L - m I|_F, a flow step eps' = eps - dgamma eps_hat / |eps_hat|
+# (App. A.2 von Mises and Drucker-Prager) is eps' = (1 - c) m + c eps with
+# c = 1 - dgamma / |eps_hat|, so that
+#   F' = U diag(exp(eps')) V^T = exp((1 - c) m) U diag(s^c) V^T
+#      = exp((1 - c) m) F exp((c - 1) L),
+# using U diag(s^c) V^T = F V diag(s^(c-1)) V^T.  The Drucker-Prager tension
+# case F' = U V^T is c = 0 without the volumetric factor: F exp(-L).
+
+def _log_stretch(F):
+    """L = (1/2) log(F^T F) and m = tr(L) / 3."""
+    L = 0.5 * _log_spd(F.transpose(-1, -2) @ F)
+    return L, L.diagonal(dim1=-2, dim2=-1).sum(-1) / 3.0
+
+
+def _dev_norm(L, m):
+    """|eps_hat| = |L - m I|_F (differentiable where it is nonzero)."""
+    return torch.linalg.matrix_norm(L - m[:, None, None] * torch.eye(3, dtype=L.dtype))
+
+
+def _return_flow_differentiable(F, L, m, c, volumetric=True):
+    """exp((1 - c) m) F exp((c - 1) L) (volumetric factor dropped if not volumetric)."""
+    out = F @ torch.linalg.matrix_exp((c - 1.0)[:, None, None] * L)
+    if volumetric:
+        out = torch.exp((1.0 - c) * m)[:, None, None] * out
+    return out
+
+
+def _return_von_mises_differentiable(F, mu, yield_stress):
+    """c = 1 - dgamma / |eps_hat| = yield / (2 mu |eps_hat|) where dgamma > 0."""
+    L, m = _log_stretch(F)
+    with torch.no_grad():
+        y = _dev_norm(L, m) - yield_stress / (2.0 * mu) > 0
+    out = F
+    if bool(y.any()):
+        c = yield_stress / (2.0 * mu[y] * _dev_norm(L[y], m[y]))
+        out = out.index_put((y.nonzero()[:, 0],), _return_flow_differentiable(F[y], L[y], m[y], c))
+    return out
+
+
+def _return_drucker_prager_differentiable(F, mu, lam, friction_deg):
+    """Tension (tr eps = 3m > 0): F' = U V^T.  Else, with
+    beta = (3 lam + 2 mu) / (2 mu) alpha, c = 1 - dgamma / |eps_hat|
+    = -3 beta m / |eps_hat| where dgamma = |eps_hat| + 3 beta m > 0."""
+    L, m = _log_stretch(F)
+    beta = (3.0 * lam + 2.0 * mu) / (2.0 * mu) * drucker_prager_alpha(friction_deg)
+    with torch.no_grad():
+        tension = m > 0
+        y = (~tension) & (_dev_norm(L, m) + 3.0 * beta * m > 0)
+    out = F
+    if bool(tension.any()):
+        zero = torch.zeros_like(m[tension])
+        out = out.index_put((tension.nonzero()[:, 0],),
+                            _return_flow_differentiable(F[tension], L[tension], m[tension], zero, volumetric=False))
+    if bool(y.any()):
+        c = -3.0 * beta[y] * m[y] / _dev_norm(L[y], m[y])
+        out = out.index_put((y.nonzero()[:, 0],), _return_flow_differentiable(F[y], L[y], m[y], c))
+    return out
+
+
+def _plasticity_differentiable(F, mu, lam, mat_id, materials):
+    """The return maps of ``plasticity`` in differentiable form (fluid and
+    sigma plasticity are differentiable as written)."""
+    out = F
+    for k, mat in enumerate(materials):
+        sel = mat_id == k
+        if not bool(sel.any()) or mat["plastic"] == PLASTIC_NONE:
+            continue
+        if mat["plastic"] == PLASTIC_VON_MISES:
+            val = _return_von_mises_differentiable(F[sel], mu[sel], mat["yield_stress"])
+        elif mat["plastic"] == PLASTIC_DRUCKER_PRAGER:
+            val = _return_drucker_prager_differentiable(F[sel], mu[sel], lam[sel], mat["friction_deg"])
+        elif mat["plastic"] == PLASTIC_FLUID:
+            val = return_fluid(F[sel])
+        elif mat["plastic"] == PLASTIC_SIGMA:
+            val = return_sigma(F[sel])
+        else:
+            raise ValueError(f"unknown plastic model {mat['plastic']}")
+        out = out.index_put((sel.nonzero()[:, 0],), val)
+    return out
 
 
 def _kirchhoff_differentiable(F, mu, lam, mat_id, materials):
@@ -478,8 +572,6 @@ def _kirchhoff_differentiable(F, mu, lam, mat_id, materials):
         sel = mat_id == k
         if not bool(sel.any()):
             continue
-        if mat["plastic"] != PLASTIC_NONE:
-            raise NotImplementedError("the adjoint oracle covers the elastic models only")
         # the closed-form models are differentiable as written; the polar and
         # log factors get SVD-free forms
         fn = {ELASTIC_FCR: _tau_fcr_differentiable, ELASTIC_HENCKY: _tau_hencky_differentiable}.get(
@@ -500,7 +592,10 @@ def substep_differentiable(state, p: Params, log_E, nu):
         tau = _kirchhoff_differentiable(Fb, mu, lam, p.mat_id[sl], p.materials)
         m, mv = p2g(xb, vb, Cb, tau, p.mass[sl], p.vol0[sl], p.n, p.dt)
         vg = grid_update(m, mv, p.n, p.dt, p.gravity, p.bound)
-        outs.append(g2p(xb, Fb, vg, p.n, p.dt))  # identity plasticity
+        x1, v1, C1, Ftr = g2p(xb, Fb, vg, p.n, p.dt)
+        if bool((torch.linalg.det(Ftr.detach()) <= 0).any()):
+            raise ValueError("adjoint oracle needs det F > 0")
+        outs.append((x1, v1, C1, _plasticity_differentiable(Ftr, mu, lam, p.mat_id[sl], p.materials)))
     return tuple(torch.cat([o[i] for o in outs]) for i in range(4))
 
 

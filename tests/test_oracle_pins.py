@@ -506,12 +506,54 @@ def _small_elastic_scene(rng, N=150, n=16, dt=2e-4, mats=None, mat_id=None):
     return (x, v, C, F), p
 
 
-@pytest.mark.parametrize("elastic", [0, 1, 2, 3, 4, 5])
-def test_adjoint_matches_central_differences(elastic):
+PLASTIC_CASES = [
+    [dict(elastic=1, plastic=O.PLASTIC_VON_MISES, yield_stress=100.0, friction_deg=0.0)],
+    [dict(elastic=0, plastic=O.PLASTIC_VON_MISES, yield_stress=200.0, friction_deg=0.0)],
+    [dict(elastic=1, plastic=O.PLASTIC_DRUCKER_PRAGER, yield_stress=0.0, friction_deg=30.0)],
+    [dict(elastic=0, plastic=O.PLASTIC_FLUID, yield_stress=0.0, friction_deg=0.0)],
+    [dict(elastic=1, plastic=O.PLASTIC_SIGMA, yield_stress=0.0, friction_deg=0.0)],
+    [dict(elastic=0, plastic=0, yield_stress=0.0, friction_deg=0.0),
+     dict(elastic=1, plastic=O.PLASTIC_VON_MISES, yield_stress=100.0, friction_deg=0.0),
+     dict(elastic=1, plastic=O.PLASTIC_DRUCKER_PRAGER, yield_stress=0.0, friction_deg=25.0),
+     dict(elastic=2, plastic=O.PLASTIC_SIGMA, yield_stress=0.0, friction_deg=0.0)],
+]
+
+
+def test_differentiable_return_maps_match_svd_return_maps():
+    """The matrix-function forms of the von Mises and Drucker-Prager return
+    maps equal the SVD forms (App. A.2), in yield, tension and elastic cases."""
+    rng = np.random.default_rng(13)
+    N = 400
+    F = torch.tensor(np.eye(3) + rng.normal(0, 0.1, (N, 3, 3)))
+    assert bool((torch.linalg.det(F) > 0).all())
+    mu = torch.tensor(rng.uniform(1e4, 1e5, N))
+    lam = torch.tensor(rng.uniform(1e4, 1e5, N))
+    vm = O.return_von_mises(F, mu, 8e3)
+    moved = (vm - F).abs().amax((1, 2)) > 0
+    assert 0 < int(moved.sum()) < N  # both branches present
+    assert torch.allclose(O._return_von_mises_differentiable(F, mu, 8e3), vm, rtol=0, atol=1e-12)
+    dp = O.return_drucker_prager(F, mu, lam, 30.0)
+    tr = torch.log(torch.linalg.svdvals(F)).sum(-1)
+    assert bool((tr > 0).any()) and bool((tr < 0).any())
+    assert torch.allclose(O._return_drucker_prager_differentiable(F, mu, lam, 30.0), dp, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("mats", [[dict(elastic=e, plastic=0, yield_stress=0.0, friction_deg=0.0)]
+                                  for e in range(6)] + PLASTIC_CASES,
+                         ids=[f"elastic{e}" for e in range(6)] + ["vm_hencky", "vm_fcr", "dp", "fluid", "sigma",
+                                                                  "mixed"])
+def test_adjoint_matches_central_differences(mats):
+    """The oracle's autograd adjoint against central differences of its SVD
+    forward, along random +-1 directions of log E and nu and a random x0
+    direction.  Plastic cases use small steps so that no particle crosses a
+    yield surface between the two evaluations."""
     rng = np.random.default_rng(12)
-    mats = [dict(elastic=elastic, plastic=0, yield_stress=0.0, friction_deg=0.0)]
-    state0, p = _small_elastic_scene(rng, mats=mats)
+    plastic = any(m["plastic"] for m in mats)
+    mat_id = rng.integers(0, len(mats), 150) if len(mats) > 1 else None
+    state0, p = _small_elastic_scene(rng, mats=mats, mat_id=mat_id)
     steps = 6
+    if plastic:  # larger strains, so the return maps act
+        state0 = state0[:3] + (torch.tensor(np.eye(3) + rng.normal(0, 0.06, (150, 3, 3))),)
     xt = state0[0] + 0.01 * torch.tensor(rng.normal(0, 1, state0[0].shape))
     # forward agrees with the SVD-based oracle
     ref = O.step_n(state0, p, steps)
@@ -529,7 +571,7 @@ def test_adjoint_matches_central_differences(elastic):
 
     d = torch.tensor(rng.choice([-1.0, 1.0], N))
     for name, g in (("logE", res["g_logE"]), ("nu", res["g_nu"])):
-        h = 1e-3 if name == "logE" else 1e-4
+        h = (1e-3 if name == "logE" else 1e-4) * (1e-1 if plastic else 1.0)
         base_l, base_n = p.log_E, p.nu
         if name == "logE":
             fd = (loss(base_l + h * d, base_n) - loss(base_l - h * d, base_n)) / (2 * h)
