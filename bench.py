@@ -323,6 +323,41 @@ def copy_probe(reps=20):
     return 2 * 256 * 1024 * 1024 / t / 1e9
 
 
+def batched_setup(n_batch=64, steps=100, K=20):
+    """The candidate batch, its targets and one Evaluation of all candidates
+    in one context, autotuned (the autotuner's trial calls: forward, one
+    checkpoint interval long, on the context's internal copies)."""
+    from paper_2602_01723_amd import batch as BT
+    from paper_2602_01723_amd import binding as B
+    from paper_2602_01723_amd import scenes
+    sc = scenes.make_scene("candidate_batch", n_batch=n_batch, n_substeps=steps)
+    tl = BT.per_particle(sc.extras["target_log_E"], sc.batch_offsets)
+    tn = BT.per_particle(sc.extras["target_nu"], sc.batch_offsets)
+    xt = BT.target_positions(sc, steps, tl, tn)
+    ev = BT.Evaluation(sc, steps, K, xt)
+    tun = B.mpm_autotune(ev.ctx, ev.p, K)
+    tuning = {k: tun[k] for k in ("chunk", "sort_every", "workgroups", "tile_cap")}
+    log(f"  batched launch tuning: {tuning}")
+    return sc, xt, ev, tuning
+
+
+def batched_graph_only(n_batch=64, steps=100, K=20, reps=3):
+    """The batched forward + adjoint graph alone (for counter runs of the
+    adjoint kernels): capture, then `reps` replays."""
+    import torch
+    sc, _, ev, tuning = batched_setup(n_batch, steps, K)
+    ev.capture()
+    ev.run_graph()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ev.run_graph()
+        torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    log(f"  batched: {t * 1e3:.1f} ms per evaluation of {n_batch} candidates")
+    return {"particles": sc.n, "substeps": steps, "batched_ms": t * 1e3, "tuning": tuning}
+
+
 def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
     """Forward + adjoint of n_batch candidates (own 48^3 grid each): one
     hipGraph for the whole batch against per-candidate eager solves."""
@@ -330,19 +365,8 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
     import torch
 
     from paper_2602_01723_amd import batch as BT
-    from paper_2602_01723_amd import scenes
-    sc = scenes.make_scene("candidate_batch", n_batch=n_batch, n_substeps=steps)
-    tl = BT.per_particle(sc.extras["target_log_E"], sc.batch_offsets)
-    tn = BT.per_particle(sc.extras["target_nu"], sc.batch_offsets)
-    xt = BT.target_positions(sc, steps, tl, tn)
-    ev = BT.Evaluation(sc, steps, K, xt)
-    # launch tuning for the batch: the autotuner's trial calls (forward, one
-    # checkpoint interval long) on the context's internal copies; the plain
-    # per-candidate solves use the same setting
-    from paper_2602_01723_amd import binding as B
-    tun = B.mpm_autotune(ev.ctx, ev.p, K)
-    tuning = {k: tun[k] for k in ("chunk", "sort_every", "workgroups", "tile_cap")}
-    log(f"  batched launch tuning: {tuning}")
+    sc, xt, ev, tuning = batched_setup(n_batch, steps, K)
+    # the plain per-candidate solves use the batch's launch tuning
     ev.run_eager()
     torch.cuda.synchronize()
     ev.capture()
@@ -437,6 +461,9 @@ def main():
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched vs plain forward + adjoint and exit")
+    ap.add_argument("--adjoint-counters", action="store_true",
+                    help="replay only the batched forward + adjoint graph (no plain leg) and exit: the run "
+                         "that counter passes over the adjoint kernels profile")
     ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_CSV",
                     help="per-dispatch counter means of the fused kernel from rocprofv3 --pmc runs, and exit")
     ap.add_argument("--summarize-batched-trace", metavar="TRACE_CSV",
@@ -477,6 +504,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps({"batched_fwd_bwd": batched_vs_plain()}), flush=True)
+        return
+    if args.adjoint_counters:
+        print(json.dumps({"batched_graph": batched_graph_only()}), flush=True)
         return
     copy_gbs = copy_probe()
     log(f"  plain 256 MiB copy: {copy_gbs:.0f} GB/s (read + write)")

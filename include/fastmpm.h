@@ -16,9 +16,10 @@
  *  - Argument and configuration checks run on the host, before any device
  *    work, and return MPM_EINVAL without touching device memory.
  *  - Device pointers are caller-owned (allocate them with hipMalloc or a
- *    PyTorch CUDA tensor).  The library never frees them.  The context owns
- *    its internal workspace, allocated by mpm_init and released by
- *    mpm_destroy; no other call allocates device memory.
+ *    PyTorch CUDA tensor).  The library never frees them, and allocates no
+ *    device memory of its own: a context's buffers live in the workspace the
+ *    caller hands to mpm_init (size from mpm_workspace_size), MCIS takes a
+ *    workspace per call, and the tape of the adjoint is caller-owned too.
  *  - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
  *    void*; NULL = the null stream) and is asynchronous unless stated.
  *  - One context may be used by one stream at a time; calls on a context
@@ -52,7 +53,7 @@ typedef struct mpm_context* mpm_ctx;
 typedef enum {
   MPM_OK = 0,
   MPM_EINVAL = -1,       /* bad argument or configuration (nothing was enqueued) */
-  MPM_ENOMEM = -2,       /* device allocation failed, or a caller buffer is too small */
+  MPM_ENOMEM = -2,       /* a caller buffer (workspace, tape) is smaller than required */
   MPM_EDEVICE = -3,      /* a HIP runtime call failed */
   MPM_ESTATE = -4,       /* call out of order (e.g. backward without a taped forward) */
   MPM_EUNSTABLE = -5,    /* device counters saw NaN/Inf or a stencil leaving the grid */
@@ -124,11 +125,17 @@ typedef struct {
 } mpm_particles;
 
 typedef struct {
-  int64_t nonfinite;     /* particle-substeps that produced a NaN/Inf x or F */
-  int64_t out_of_grid;   /* particle-substeps whose stencil left the grid (skipped) */
-  int64_t tile_overflow; /* work items whose box exceeded the LDS tiles (global-memory transfers) */
-  int64_t tile_escapes;  /* particles that left their item's P2G tile in one substep (global atomics) */
-  int64_t substeps;      /* substeps run since mpm_init */
+  int64_t nonfinite;      /* particle-substeps that produced a NaN/Inf x or F */
+  int64_t out_of_grid;    /* particle-substeps whose stencil left the grid (skipped) */
+  int64_t tile_overflow;  /* work items whose box exceeded the LDS tiles (global-memory transfers) */
+  int64_t tile_escapes;   /* particles that left their item's P2G tile in one substep (global atomics) */
+  int64_t substeps;       /* substeps run since mpm_init */
+  int64_t cfl_violations; /* particle-substeps whose G2P velocity moves more than half a cell:
+                             |v'| dt / dx > 1/2 */
+  double max_cfl;         /* largest |v'| dt / dx seen since mpm_init */
+  double max_wave_cfl;    /* largest c dt / dx of the particles handed in since mpm_init, with
+                             c^2 = (lam + 2 mu) V0 / m the squared P-wave speed (the explicit
+                             update is unstable once this is well above 1) */
 } mpm_diag;
 
 /* Status code as text (static storage). */
@@ -137,14 +144,26 @@ const char* mpm_status_string(int status);
 /* Text of the last error on this context (static per context; never NULL). */
 const char* mpm_last_error(mpm_ctx ctx);
 
+/* Bytes of device workspace a context for n_particles particles under cfg
+ * needs (cell-sorted particle copies 204 B + permutation staging 128 B per
+ * particle, three grids of 16 B per node, sort bins and work-item tables).
+ * Host only; MPM_EINVAL for an invalid cfg or count. */
+int mpm_workspace_size(const mpm_config* cfg, int64_t n_particles, size_t* bytes);
+
 /* Create a context for n_particles particles split into cfg->n_batch scenes
  * by batch_offsets (host array of n_batch + 1 int64, offsets[0] = 0,
  * non-decreasing, offsets[n_batch] = n_particles; NULL allowed when
  * n_batch == 1).  Copies the material table (n_materials >= 1).
- * Allocates the internal workspace (grids, sort and particle buffers) on the
- * current HIP device.  On success *out holds the context. */
+ * workspace: caller-owned device memory on the current HIP device, 256-byte
+ * aligned, of workspace_bytes >= mpm_workspace_size bytes; the context keeps
+ * its grids, sort and particle buffers there, so it must stay allocated and
+ * untouched until mpm_destroy.  The library allocates no device memory.
+ * MPM_EINVAL for invalid arguments or a NULL / misaligned workspace,
+ * MPM_ENOMEM when workspace_bytes is too small.  On success *out holds the
+ * context (Sec. 3.2 MPM state; App. A.1 grid). */
 int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_materials,
-             int64_t n_particles, const int64_t* batch_offsets, mpm_ctx* out);
+             int64_t n_particles, const int64_t* batch_offsets, void* workspace, size_t workspace_bytes,
+             mpm_ctx* out);
 
 /* One substep: stress -> P2G -> grid update -> G2P -> return map, updating
  * x, v, C, F in place.  Equivalent to mpm_step_n(ctx, p, 1, NULL, stream). */
@@ -190,12 +209,15 @@ int mpm_export_frame(mpm_ctx ctx, float* x, const float* cov0, float* cov, void*
 
 /* Bytes of the tape buffer for n_steps substeps checkpointed every K: the
  * checkpoints (96 B per particle each), one segment of K recomputed states
- * with their K grids (16 B per node each) and work-item boxes, and the
- * adjoint scratch. */
+ * (K + 1 when a material has a return map) with their K grids (16 B per
+ * node each) and work-item boxes, and the adjoint scratch. */
 int mpm_tape_size(mpm_ctx ctx, int32_t n_steps, int32_t checkpoint_every, size_t* bytes);
 
 /* Reverse of the n_steps substeps taped by the last mpm_step_n call with
- * the same tape (any elastic model, identity plasticity only; det F > 0).  Inputs: the
+ * the same tape: every elastic model and every return map (the von Mises and
+ * Drucker-Prager maps through the SVD of F_trial, fluid and sigma through
+ * det F_trial; at a yield surface the one-sided derivative of the branch the
+ * forward pass took).  Inputs: the
  * adjoints of the final x, v, C, F (device [3][N], [3][N], [9][N], [9][N];
  * any may be NULL = zero).  Outputs (overwritten): g_log_E[N], g_nu[N] and,
  * when non-NULL, the adjoints of the initial state g_x0, g_v0, g_C0, g_F0.
@@ -214,7 +236,9 @@ int mpm_grid_state(mpm_ctx ctx, float* m, float* mv, float* v, void* stream);
 int mpm_export_covariance(mpm_ctx ctx, const float* F, const float* cov0, float* cov,
                           int64_t n, void* stream);
 
-/* Synchronises the context's last stream and reads the device counters. */
+/* Synchronises the context's last stream and reads the device counters.
+ * Returns MPM_EUNSTABLE when any particle-substep was non-finite, left the
+ * grid or broke the CFL watch (cfl_violations > 0), else MPM_OK. */
 int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out);
 
 /* Launch tuning.  chunk = particles per work item, cut from one 4^3-cell
@@ -323,7 +347,8 @@ int mpm_profile(mpm_ctx ctx, int32_t enable);
  * timed launches per class (arrays of MPM_PROFILE_CLASSES) and resets them. */
 int mpm_profile_read(mpm_ctx ctx, double* ms, int64_t* launches);
 
-/* Release the context and its workspace (synchronises the device). */
+/* Release the context (synchronises the device); the caller may then free
+ * the workspace. */
 int mpm_destroy(mpm_ctx ctx);
 
 #ifdef __cplusplus

@@ -30,7 +30,7 @@ def loss_weights(offsets) -> np.ndarray:
 class Evaluation:
     """Forward + loss + adjoint of one context (all scenes of `sc`)."""
 
-    def __init__(self, sc, steps: int, K: int, x_target, log_E=None, nu=None, tuning=None):
+    def __init__(self, sc, steps: int, K: int, x_target, log_E=None, nu=None, tuning=None, stream=None):
         import torch
         self.sc = sc
         self.steps = int(steps)
@@ -51,7 +51,7 @@ class Evaluation:
         self.g_log_E = torch.empty(N, device="cuda")
         self.g_nu = torch.empty(N, device="cuda")
         self.graph = None
-        self.stream = torch.cuda.Stream()
+        self.stream = torch.cuda.Stream() if stream is None else stream
 
     def reset(self):
         """Restore the initial particle state (eager copies)."""
@@ -122,10 +122,13 @@ def per_particle(values_per_scene, offsets) -> np.ndarray:
 
 
 def plain_evaluations(sc, steps, K, x_target, tuning=None) -> List[Evaluation]:
-    """One single-scene Evaluation per candidate of the batched scene `sc`."""
+    """One single-scene Evaluation per candidate of the batched scene `sc`,
+    all on one shared stream (they run one after the other)."""
+    import torch
+    stream = torch.cuda.Stream()
     evs = []
     for b in range(sc.n_batch):
         sub = sc.subset(b)
         lo, hi = int(sc.batch_offsets[b]), int(sc.batch_offsets[b + 1])
-        evs.append(Evaluation(sub, steps, K, np.asarray(x_target)[lo:hi], tuning=tuning))
+        evs.append(Evaluation(sub, steps, K, np.asarray(x_target)[lo:hi], tuning=tuning, stream=stream))
     return evs

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libfastmpm.so")
 
 MPM_ABI_VERSION = 1
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_load",
+EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_workspace_size", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_load",
             "mpm_advance", "mpm_store", "mpm_export_frame", "mpm_tape_size",
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
             "mpm_set_tuning", "mpm_get_tuning", "mpm_autotune", "mpm_graph_begin", "mpm_graph_end",
@@ -63,7 +63,8 @@ class mpm_tuning(ctypes.Structure):
 
 class mpm_diag(ctypes.Structure):
     _fields_ = [("nonfinite", ctypes.c_int64), ("out_of_grid", ctypes.c_int64), ("tile_overflow", ctypes.c_int64),
-                ("tile_escapes", ctypes.c_int64), ("substeps", ctypes.c_int64)]
+                ("tile_escapes", ctypes.c_int64), ("substeps", ctypes.c_int64), ("cfl_violations", ctypes.c_int64),
+                ("max_cfl", ctypes.c_double), ("max_wave_cfl", ctypes.c_double)]
 
 
 _lib = None
@@ -88,8 +89,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "mpm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "mpm_last_error": (ctypes.c_char_p, [vp]),
+        "mpm_workspace_size": (ctypes.c_int, [ctypes.POINTER(mpm_config), i64, ctypes.POINTER(sz)]),
         "mpm_init": (ctypes.c_int, [ctypes.POINTER(mpm_config), ctypes.POINTER(mpm_material), i32, i64,
-                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp)]),
+                                    ctypes.POINTER(ctypes.c_int64), vp, sz, ctypes.POINTER(vp)]),
         "mpm_substep": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp]),
         "mpm_step_n": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), i32, vp, i32, vp]),
         "mpm_load": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp]),
@@ -141,18 +143,21 @@ def _stream(stream=None) -> Optional[int]:
 
 
 class Context:
-    """Owns an mpm_ctx; destroyed on close() / garbage collection."""
+    """Owns an mpm_ctx and the device workspace it lives in (a torch
+    tensor); destroyed on close() / garbage collection."""
 
-    def __init__(self, handle, n_particles, n_batch, grid_res):
+    def __init__(self, handle, n_particles, n_batch, grid_res, workspace=None):
         self.handle = handle
         self.n_particles = n_particles
         self.n_batch = n_batch
         self.grid_res = grid_res
+        self.workspace = workspace
 
     def close(self):
         if self.handle:
             load().mpm_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -219,22 +224,39 @@ class Particles:
         return Particles(**{k: getattr(self, k).clone() for k in self.__dataclass_fields__})
 
 
+def make_config(grid_res, dt, n_batch=1, gravity=(0.0, -9.8, 0.0), bound=3, sort_every=0) -> mpm_config:
+    return mpm_config(MPM_ABI_VERSION, int(grid_res), int(bound), int(n_batch), float(dt),
+                      (ctypes.c_float * 3)(*[float(g) for g in gravity]), int(sort_every), 0)
+
+
+def mpm_workspace_size(cfg: mpm_config, n_particles: int) -> int:
+    out = ctypes.c_size_t()
+    _check(None, load().mpm_workspace_size(ctypes.byref(cfg), int(n_particles), ctypes.byref(out)),
+           "mpm_workspace_size")
+    return int(out.value)
+
+
 def mpm_init(grid_res, dt, materials: Sequence[dict], n_particles, batch_offsets=None, gravity=(0.0, -9.8, 0.0),
              bound=3, sort_every=0) -> Context:
+    """Create a context; its device workspace is a torch uint8 tensor on the
+    current device, held by the returned Context."""
+    import torch
     lib = load()
     n_batch = 1 if batch_offsets is None else len(batch_offsets) - 1
-    cfg = mpm_config(MPM_ABI_VERSION, int(grid_res), int(bound), int(n_batch), float(dt),
-                     (ctypes.c_float * 3)(*[float(g) for g in gravity]), int(sort_every), 0)
+    cfg = make_config(grid_res, dt, n_batch, gravity, bound, sort_every)
     mats = (mpm_material * len(materials))(*[mpm_material(int(m["elastic"]), int(m["plastic"]),
                                                           float(m.get("yield_stress", 0.0)),
                                                           float(m.get("friction_deg", 0.0))) for m in materials])
     offs = None
     if batch_offsets is not None:
         offs = (ctypes.c_int64 * len(batch_offsets))(*[int(b) for b in batch_offsets])
+    nbytes = mpm_workspace_size(cfg, n_particles)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     h = ctypes.c_void_p()
-    rc = lib.mpm_init(ctypes.byref(cfg), mats, len(materials), int(n_particles), offs, ctypes.byref(h))
+    rc = lib.mpm_init(ctypes.byref(cfg), mats, len(materials), int(n_particles), offs, _ptr(ws), nbytes,
+                      ctypes.byref(h))
     _check(None, rc, "mpm_init")
-    return Context(h, int(n_particles), n_batch, int(grid_res))
+    return Context(h, int(n_particles), n_batch, int(grid_res), ws)
 
 
 def init_from_scene(sc, sort_every=0) -> Context:
@@ -315,7 +337,8 @@ def mpm_get_diagnostics(ctx: Context) -> dict:
     d = mpm_diag()
     rc = load().mpm_get_diagnostics(ctx.handle, ctypes.byref(d))
     out = dict(nonfinite=d.nonfinite, out_of_grid=d.out_of_grid, tile_overflow=d.tile_overflow,
-               tile_escapes=d.tile_escapes, substeps=d.substeps, status=rc)
+               tile_escapes=d.tile_escapes, substeps=d.substeps, cfl_violations=d.cfl_violations,
+               max_cfl=d.max_cfl, max_wave_cfl=d.max_wave_cfl, status=rc)
     if rc not in (MPM_OK, MPM_EUNSTABLE):
         _check(ctx, rc, "mpm_get_diagnostics")
     return out

@@ -1,9 +1,9 @@
 // libfastmpm.so: host side of the C ABI declared in include/fastmpm.h.
 //
-// A context holds the configuration, the material table and the internal
-// workspace: cell-sorted copies of the particle state, two grids (the one a
-// kernel reads and the one it accumulates into), the counting-sort buffers
-// and the device diagnostics counters.  mpm_step_n sorts the caller's
+// A context holds the configuration, the material table and pointers into
+// the caller's workspace: cell-sorted copies of the particle state, three
+// grids in rotation, the counting-sort and permutation buffers and the
+// device diagnostics counters.  The library allocates no device memory.  mpm_step_n sorts the caller's
 // particles by cell, runs the substeps on the sorted copies (re-sorting
 // every `sort_every` substeps) and writes the state back in caller order.
 #include <hip/hip_runtime.h>
@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fastmpm.h"
@@ -21,6 +22,11 @@
 #include "mcis_kernels.hpp"
 
 using fmpm::kBlock;
+
+// device counters: 0 non-finite, 1 out of grid, 2 tile overflow, 3 tile
+// escapes, 4 CFL violations, 5 max (|v'| dt / dx)^2 and 6 max (c dt / dx)^2
+// (float bits in the low word), 7 unused
+constexpr int kDiagSlots = 8;
 
 struct mpm_context {
   mpm_config cfg{};
@@ -59,7 +65,7 @@ struct mpm_context {
   const int* pdest_cur = nullptr;  // destinations of the prepared permutation
   unsigned long long* diag = nullptr;
   fmpm::Material* d_mats = nullptr;
-  std::vector<void*> allocations;
+  size_t workspace_bytes = 0;  // of the caller's workspace, which holds every device buffer above
 
   // kernel timing (mpm_profile): event pairs recorded around launches
   bool prof_on = false;
@@ -115,20 +121,6 @@ int hip_fail(mpm_ctx ctx, const char* what, hipError_t e) {
     if (e_ != hipSuccess) return hip_fail((ctx), (name), e_);   \
   } while (0)
 
-template <typename T>
-int alloc(mpm_ctx ctx, T** p, int64_t count) {
-  *p = nullptr;
-  if (count <= 0) count = 1;
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, MPM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  }
-  ctx->allocations.push_back(q);
-  *p = static_cast<T*>(q);
-  return MPM_OK;
-}
 
 constexpr int kProfPairs = 4096;
 
@@ -186,6 +178,8 @@ fmpm::SubstepArgs make_args(mpm_ctx c) {
   a.n_materials = c->n_mat;
   a.mats = c->d_mats;
   a.done_counter = c->done_counter;
+  const double vmax = 0.5 / ((double)c->cfg.dt * (double)c->n);  // |v| dt / dx = 1/2
+  a.cfl_v2 = (float)(vmax * vmax);
   return a;
 }
 
@@ -342,7 +336,8 @@ int gather_from_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
   add_params(pls, p, pl);
   rc = rc ? rc : perm_apply(c, pls, s);
   if (rc) return rc;
-  fmpm::k_params_planes<<<g, 256, 0, s>>>(c->prm, c->mat, c->pid, pl[0], pl[1], pl[2], pl[3], pl[4], c->perm, N);
+  fmpm::k_params_planes<<<g, 256, 0, s>>>(c->prm, c->mat, c->pid, pl[0], pl[1], pl[2], pl[3], pl[4], c->perm, N,
+                                          c->diag);
   LAUNCH_CHECK(c, "k_params_planes");
   return MPM_OK;
 }
@@ -377,6 +372,7 @@ int scatter_to_caller(mpm_ctx c, const mpm_particles* p, hipStream_t s) {
 //   checkpoints  n_ckpt x 24 N   state at substeps 0, K, 2K, ... in caller order
 //                                (x 3N, v 3N, C 9N, F 9N)
 //   segment      K x 24 N        recomputed states of one segment, sorted order
+//                                (K + 1 when a material has a return map)
 //   adj, adjc    24 N each       state adjoint, sorted / caller order
 //   gl, gn       N each          parameter gradients of a segment, sorted order
 //   lnE, nu      N each          sorted copies of the parameters
@@ -391,6 +387,8 @@ struct TapeLayout {
   size_t bytes;
 };
 
+bool has_plastic(mpm_ctx c);
+
 TapeLayout tape_layout(mpm_ctx c, int32_t n_steps, int32_t K, void* base) {
   TapeLayout t{};
   const int64_t N = std::max<int64_t>(c->N, 1);
@@ -403,7 +401,7 @@ TapeLayout tape_layout(mpm_ctx c, int32_t n_steps, int32_t K, void* base) {
     return reinterpret_cast<float*>(q);
   };
   t.ckpt = take(t.n_ckpt * 24 * N);
-  t.seg = take((int64_t)K * 24 * N);
+  t.seg = take((int64_t)(K + (has_plastic(c) ? 1 : 0)) * 24 * N);
   t.adj = take(24 * N);
   t.adjc = take(24 * N);
   t.gl = take(N);
@@ -417,10 +415,13 @@ TapeLayout tape_layout(mpm_ctx c, int32_t n_steps, int32_t K, void* base) {
   return t;
 }
 
-bool adjoint_supported(mpm_ctx c) {
+// Whether any material has a return map: the backward then also reverses
+// the return maps, which needs the segment's states one substep further
+// (one more tape slot) to form each F_trial from F_k and C_{k+1}.
+bool has_plastic(mpm_ctx c) {
   for (int k = 0; k < c->n_mat; ++k)
-    if (c->mats[k].plastic != MPM_PLASTIC_NONE) return false;
-  return true;
+    if (c->mats[k].plastic != MPM_PLASTIC_NONE) return true;
+  return false;
 }
 
 int copy_f32(mpm_ctx c, float* out, const float* in, int64_t count, hipStream_t s) {
@@ -464,6 +465,103 @@ int check_particles(mpm_ctx ctx, const mpm_particles* p) {
   return MPM_OK;
 }
 
+// Sizes derived from the configuration (shared by mpm_workspace_size and mpm_init).
+struct Geometry {
+  int n = 0, nb = 0;
+  int64_t N = 0, nodes = 0, bins = 0, n_bsum = 0, nblocks = 0, max_chunks = 0, chunk_cap = 0;
+};
+
+// Host-side checks of the configuration and the batch offsets (off receives
+// them); MPM_EINVAL on any violation.
+int check_config(const mpm_config* cfg, int64_t n_particles, const int64_t* batch_offsets, std::vector<int64_t>* off,
+                 Geometry* g) {
+  if (!cfg) return MPM_EINVAL;
+  if (cfg->abi_version != MPM_ABI_VERSION) return MPM_EINVAL;
+  if (cfg->grid_res < 8 || cfg->grid_res > 1024) return MPM_EINVAL;
+  if (cfg->bound < 0 || 2 * cfg->bound + 3 > cfg->grid_res) return MPM_EINVAL;
+  if (cfg->n_batch < 1) return MPM_EINVAL;
+  if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt)) return MPM_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(cfg->gravity[k])) return MPM_EINVAL;
+  if (cfg->sort_every < 0 || cfg->flags != 0) return MPM_EINVAL;
+  if (n_particles < 0 || n_particles > (int64_t)0x7fffff00) return MPM_EINVAL;
+  if (off) {
+    if (batch_offsets) {
+      off->assign(batch_offsets, batch_offsets + cfg->n_batch + 1);
+    } else {
+      if (cfg->n_batch != 1) return MPM_EINVAL;
+      *off = {0, n_particles};
+    }
+    if ((*off)[0] != 0 || off->back() != n_particles) return MPM_EINVAL;
+    for (int b = 0; b < cfg->n_batch; ++b)
+      if ((*off)[b + 1] < (*off)[b]) return MPM_EINVAL;
+  }
+  g->n = cfg->grid_res;
+  g->nb = (g->n + 3) / 4;
+  g->N = n_particles;
+  g->bins = (int64_t)cfg->n_batch * g->nb * g->nb * g->nb * 64;
+  if (g->bins >= ((int64_t)1 << 32)) return MPM_EINVAL;
+  g->n_bsum = (g->bins + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  g->nodes = (int64_t)cfg->n_batch * g->n * g->n * g->n;
+  g->nblocks = (int64_t)cfg->n_batch * g->nb * g->nb * g->nb;
+  g->max_chunks = (n_particles + 63) / 64 + std::min<int64_t>(n_particles, g->nblocks) + 1;  // items >= 64
+  g->chunk_cap = (n_particles + kBlock - 1) / kBlock + cfg->n_batch;  // per-scene chunks of kBlock
+  return MPM_OK;
+}
+
+// Points the context's device buffers into the workspace at base (or, with
+// base NULL, only measures); returns the bytes used.  Every buffer starts
+// on a 256-byte boundary.
+size_t carve(mpm_ctx c, const Geometry& g, char* base) {
+  size_t off = 0;
+  auto take = [&](auto& ptr, int64_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(ptr)>>;
+    const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    if (base) ptr = reinterpret_cast<T*>(base + off);
+    off += (bytes + 255) & ~(size_t)255;
+  };
+  const int64_t N = std::max<int64_t>(g.N, 1);
+  take(c->xs, 3 * N);
+  take(c->vs, 3 * N);
+  take(c->Cs, 9 * N);
+  take(c->Fs, 9 * N);
+  take(c->xs2, 3 * N);
+  take(c->Fs2, 9 * N);
+  take(c->prm, N);
+  take(c->prm2, N);
+  take(c->mat, N);
+  take(c->mat2, N);
+  take(c->pid, N);
+  take(c->pid2, N);
+  take(c->perm, N);
+  take(c->keys, N);
+  take(c->slots, N);
+  for (int k = 0; k < 3; ++k) take(c->grid[k], g.nodes);
+  take(c->done_counter, 1);
+  take(c->item_box, 2 * 6 * (g.max_chunks + 1));
+  take(c->count, g.bins);
+  take(c->bsum, g.n_bsum);
+  take(c->chunk_start, g.chunk_cap + 1);
+  take(c->chunk_batch, g.chunk_cap);
+  take(c->diag, kDiagSlots);
+  take(c->dchunk_start, g.max_chunks + 1);
+  take(c->dchunk_batch, g.max_chunks + 1);
+  take(c->dn_chunks, 1);
+  take(c->nchk, g.nblocks);
+  take(c->work_counter, 1);
+  take(c->d_mats, fmpm::kMaxMaterials);
+  const PermGeom pg = perm_geom(N);
+  take(c->pdest, N);
+  if (pg.bucketed) {
+    take(c->ppos, N);
+    take(c->pdop, N);
+    take(c->ptmp, (int64_t)fmpm::PlaneSet::kMax * N);
+    take(c->pcount, pg.entries);
+    take(c->pbsum, (pg.entries + fmpm::kScanTile - 1) / fmpm::kScanTile);
+  }
+  return off;
+}
+
 }  // namespace
 
 extern "C" {
@@ -475,31 +573,26 @@ const char* mpm_status_string(int status) {
 
 const char* mpm_last_error(mpm_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
 
+int mpm_workspace_size(const mpm_config* cfg, int64_t n_particles, size_t* bytes) {
+  if (!bytes) return MPM_EINVAL;
+  Geometry g;
+  const int rc = check_config(cfg, n_particles, nullptr, nullptr, &g);
+  if (rc) return rc;
+  mpm_context tmp;
+  *bytes = carve(&tmp, g, nullptr);
+  return MPM_OK;
+}
+
 int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_materials, int64_t n_particles,
-             const int64_t* batch_offsets, mpm_ctx* out) {
+             const int64_t* batch_offsets, void* workspace, size_t workspace_bytes, mpm_ctx* out) {
   if (!out) return MPM_EINVAL;
   *out = nullptr;
   if (!cfg || !materials) return MPM_EINVAL;
-  if (cfg->abi_version != MPM_ABI_VERSION) return MPM_EINVAL;
-  if (cfg->grid_res < 8 || cfg->grid_res > 1024) return MPM_EINVAL;
-  if (cfg->bound < 0 || 2 * cfg->bound + 3 > cfg->grid_res) return MPM_EINVAL;
-  if (cfg->n_batch < 1) return MPM_EINVAL;
-  if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt)) return MPM_EINVAL;
-  for (int k = 0; k < 3; ++k)
-    if (!std::isfinite(cfg->gravity[k])) return MPM_EINVAL;
-  if (cfg->sort_every < 0 || cfg->flags != 0) return MPM_EINVAL;
-  if (n_materials < 1 || n_materials > fmpm::kMaxMaterials) return MPM_EINVAL;
-  if (n_particles < 0 || n_particles > (int64_t)0x7fffff00) return MPM_EINVAL;
   std::vector<int64_t> off;
-  if (batch_offsets) {
-    off.assign(batch_offsets, batch_offsets + cfg->n_batch + 1);
-  } else {
-    if (cfg->n_batch != 1) return MPM_EINVAL;
-    off = {0, n_particles};
-  }
-  if (off[0] != 0 || off.back() != n_particles) return MPM_EINVAL;
-  for (int b = 0; b < cfg->n_batch; ++b)
-    if (off[b + 1] < off[b]) return MPM_EINVAL;
+  Geometry g;
+  int rc = check_config(cfg, n_particles, batch_offsets, &off, &g);
+  if (rc) return rc;
+  if (n_materials < 1 || n_materials > fmpm::kMaxMaterials) return MPM_EINVAL;
   fmpm::Material mats[fmpm::kMaxMaterials]{};
   for (int k = 0; k < n_materials; ++k) {
     const mpm_material& m = materials[k];
@@ -514,10 +607,10 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     const double sp = std::sin((double)m.friction_deg * M_PI / 180.0);
     mats[k].dp_alpha = (float)(std::sqrt(2.0 / 3.0) * 2.0 * sp / (3.0 - sp));
   }
-  const int n = cfg->grid_res;
-  const int nb = (n + 3) / 4;
-  const int64_t bins = (int64_t)cfg->n_batch * nb * nb * nb * 64;
-  if (bins >= ((int64_t)1 << 32)) return MPM_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & 255u)) return MPM_EINVAL;
+  mpm_context probe;
+  const size_t need = carve(&probe, g, nullptr);
+  if (workspace_bytes < need) return MPM_ENOMEM;
 
   mpm_ctx c = new mpm_context();
   c->cfg = *cfg;
@@ -526,11 +619,11 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   c->N = n_particles;
   c->B = cfg->n_batch;
   c->offsets = off;
-  c->n = n;
-  c->nb = nb;
-  c->nodes = (int64_t)cfg->n_batch * n * n * n;
-  c->bins = bins;
-  c->n_bsum = (bins + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  c->n = g.n;
+  c->nb = g.nb;
+  c->nodes = g.nodes;
+  c->bins = g.bins;
+  c->n_bsum = g.n_bsum;
   if (cfg->sort_every > 0) c->sort_every = cfg->sort_every;
 
   std::vector<int> cs, cb;
@@ -541,64 +634,18 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     }
   cs.push_back((int)n_particles);
   c->n_chunks = (int)cb.size();
-  c->nblocks = (int64_t)c->B * nb * nb * nb;
-  c->max_chunks = (n_particles + 63) / 64 + std::min<int64_t>(n_particles, c->nblocks) + 1;  // items >= 64
+  c->nblocks = g.nblocks;
+  c->max_chunks = g.max_chunks;
   c->grid_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(c->max_chunks, 256 * 2));
+  c->workspace_bytes = carve(c, g, static_cast<char*>(workspace));
 
-  const int64_t N = std::max<int64_t>(n_particles, 1);
-  int rc = MPM_OK;
-  rc = rc ? rc : alloc(c, &c->xs, 3 * N);
-  rc = rc ? rc : alloc(c, &c->vs, 3 * N);
-  rc = rc ? rc : alloc(c, &c->Cs, 9 * N);
-  rc = rc ? rc : alloc(c, &c->Fs, 9 * N);
-  rc = rc ? rc : alloc(c, &c->xs2, 3 * N);
-  rc = rc ? rc : alloc(c, &c->Fs2, 9 * N);
-  rc = rc ? rc : alloc(c, &c->prm, N);
-  rc = rc ? rc : alloc(c, &c->prm2, N);
-  rc = rc ? rc : alloc(c, &c->mat, N);
-  rc = rc ? rc : alloc(c, &c->mat2, N);
-  rc = rc ? rc : alloc(c, &c->pid, N);
-  rc = rc ? rc : alloc(c, &c->pid2, N);
-  rc = rc ? rc : alloc(c, &c->perm, N);
-  rc = rc ? rc : alloc(c, &c->keys, N);
-  rc = rc ? rc : alloc(c, &c->slots, N);
-  rc = rc ? rc : alloc(c, &c->grid[0], c->nodes);
-  rc = rc ? rc : alloc(c, &c->grid[1], c->nodes);
-  rc = rc ? rc : alloc(c, &c->grid[2], c->nodes);
-  rc = rc ? rc : alloc(c, &c->done_counter, 1);
-  rc = rc ? rc : alloc(c, &c->item_box, 2 * 6 * (c->max_chunks + 1));
-  rc = rc ? rc : alloc(c, &c->count, bins);
-  rc = rc ? rc : alloc(c, &c->bsum, c->n_bsum);
-  rc = rc ? rc : alloc(c, &c->chunk_start, (int64_t)cs.size());
-  rc = rc ? rc : alloc(c, &c->chunk_batch, (int64_t)std::max<size_t>(cb.size(), 1));
-  rc = rc ? rc : alloc(c, &c->diag, 8);
-  rc = rc ? rc : alloc(c, &c->dchunk_start, c->max_chunks + 1);
-  rc = rc ? rc : alloc(c, &c->dchunk_batch, c->max_chunks + 1);
-  rc = rc ? rc : alloc(c, &c->dn_chunks, 1);
-  rc = rc ? rc : alloc(c, &c->nchk, c->nblocks);
-  rc = rc ? rc : alloc(c, &c->work_counter, 1);
-  rc = rc ? rc : alloc(c, &c->d_mats, fmpm::kMaxMaterials);
-  {
-    const PermGeom pg = perm_geom(N);
-    rc = rc ? rc : alloc(c, &c->pdest, N);
-    if (pg.bucketed) {
-      rc = rc ? rc : alloc(c, &c->ppos, N);
-      rc = rc ? rc : alloc(c, &c->pdop, N);
-      rc = rc ? rc : alloc(c, &c->ptmp, (int64_t)fmpm::PlaneSet::kMax * N);
-      rc = rc ? rc : alloc(c, &c->pcount, pg.entries);
-      rc = rc ? rc : alloc(c, &c->pbsum, (pg.entries + fmpm::kScanTile - 1) / fmpm::kScanTile);
-    }
-  }
-  if (rc) {
-    mpm_destroy(c);
-    return rc;
-  }
   hipError_t e = hipMemcpy(c->chunk_start, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess && !cb.empty())
     e = hipMemcpy(c->chunk_batch, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(c->diag, 0, 8 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->diag, 0, kDiagSlots * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->dn_chunks, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemset(c->done_counter, 0, sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(c->work_counter, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(c->d_mats, c->mats, sizeof(c->mats), hipMemcpyHostToDevice);
   if (e == hipSuccess && n_particles > 0) {
     fmpm::k_iota<<<blocks_for(n_particles, 256), 256>>>(c->pid, n_particles);
@@ -607,7 +654,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   if (e == hipSuccess) e = hipMemset(c->grid[0], 0, (size_t)c->nodes * sizeof(float4));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
-    mpm_destroy(c);
+    delete c;
     return MPM_EDEVICE;
   }
   *out = c;
@@ -624,8 +671,6 @@ int run_steps(mpm_ctx ctx, const mpm_particles* p, int32_t n_steps, void* tape, 
   int rc = MPM_OK;
   if (n_steps < 0) return fail(ctx, MPM_EINVAL, "n_steps < 0");
   if (tape && checkpoint_every < 1) return fail(ctx, MPM_EINVAL, "checkpoint_every < 1 with a tape");
-  if (tape && !adjoint_supported(ctx))
-    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers the elastic models without plasticity");
   hipStream_t s = (hipStream_t)stream;
   ctx->last_stream = s;
   ctx->resident = ctx->primed = false;  // the internal state is taken from the caller's arrays
@@ -841,8 +886,6 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
   if (!p || !tape || !g_log_E || !g_nu) return fail(ctx, MPM_EINVAL, "NULL argument");
   if (ctx->N > 0 && (!p->mass || !p->vol0 || !p->log_E || !p->nu || !p->mat_id))
     return fail(ctx, MPM_EINVAL, "a parameter array is NULL");
-  if (!adjoint_supported(ctx))
-    return fail(ctx, MPM_EUNSUPPORTED, "the adjoint covers the elastic models without plasticity");
   if (tape != ctx->tape_ptr || n_steps != ctx->tape_n)
     return fail(ctx, MPM_ESTATE, "tape does not hold the last taped mpm_step_n of this length");
   hipStream_t s = (hipStream_t)stream;
@@ -881,7 +924,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     rc = rc ? rc : perm_apply(ctx, pk, s);
     if (rc) return rc;
     fmpm::k_params_planes<<<gp, 256, 0, s>>>(ctx->prm, ctx->mat, ctx->pid, pl[0], pl[1], pl[2], pl[3], pl[4],
-                                              ctx->perm, N);
+                                              ctx->perm, N, ctx->diag);
     LAUNCH_CHECK(ctx, "backward gather");
     // (2) recompute the segment: slot j holds the state of substep k0 + j
     // and grid slot j its P2G (the grid the forward pass read at that
@@ -926,6 +969,16 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::k_substep<fmpm::kFused><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(ctx, "recompute substep");
     }
+    // with return maps: the state after the segment's last substep as well
+    // (slot L), whose C forms that substep's F_trial
+    const bool plastic = has_plastic(ctx);
+    if (plastic) {
+      fmpm::SubstepArgs a = args_for(L - 1, L);
+      a.grid_in = gslot(L - 1);
+      a.box_in = bslot(L - 1);
+      fmpm::k_substep<fmpm::kG2P><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
+      LAUNCH_CHECK(ctx, "recompute G2P");
+    }
     // (3) adjoint of the segment's final state, in sorted order, through
     // the permutation (1) prepared (caller index -> slot; the recompute
     // leaves it in place)
@@ -966,6 +1019,12 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       for (int k = 0; k < 3; ++k) b.g[k] = ctx->cfg.gravity[k];
       fmpm::AdjItems items{ctx->dchunk_start, ctx->dchunk_batch, ctx->dn_chunks, ctx->work_counter, ctx->tile_cap,
                            bslot(j)};
+      if (plastic) {  // adjoint of F_{j+1} -> adjoint of F_trial
+        fmpm::k_adj_return_map<<<gp, 256, 0, s>>>(b.x, b.F, slot(j + 1) + 6 * N, ctx->prm, ctx->mat, ctx->d_mats,
+                                                   ctx->n_mat, tl.lnE, tl.nu, ctx->cfg.dt, ctx->n, b.aF, tl.gl,
+                                                   tl.gn, N);
+        LAUNCH_CHECK(ctx, "k_adj_return_map");
+      }
       fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       LAUNCH_CHECK(ctx, "k_adj_g2p");
       rc = fill_u32(ctx, ctx->work_counter, 1, s);  // the item queue again, for k_adj_p2g
@@ -1018,14 +1077,22 @@ int mpm_export_covariance(mpm_ctx ctx, const float* F, const float* cov0, float*
 int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out) {
   if (!ctx || !out) return MPM_EINVAL;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
-  unsigned long long h[8];
+  unsigned long long h[kDiagSlots];
   HIP_TRY(ctx, hipMemcpy(h, ctx->diag, sizeof(h), hipMemcpyDeviceToHost));
   out->nonfinite = (int64_t)h[0];
   out->out_of_grid = (int64_t)h[1];
   out->tile_overflow = (int64_t)h[2];
   out->tile_escapes = (int64_t)h[3];
   out->substeps = ctx->substeps;
-  return (h[0] || h[1]) ? MPM_EUNSTABLE : MPM_OK;
+  out->cfl_violations = (int64_t)h[4];
+  const double scale = (double)ctx->cfg.dt * (double)ctx->n;  // dt / dx
+  float v2, c2;
+  const uint32_t b5 = (uint32_t)h[5], b6 = (uint32_t)h[6];
+  std::memcpy(&v2, &b5, 4);
+  std::memcpy(&c2, &b6, 4);
+  out->max_cfl = std::sqrt((double)v2) * scale;
+  out->max_wave_cfl = std::sqrt((double)c2) * scale;
+  return (h[0] || h[1] || h[4]) ? MPM_EUNSTABLE : MPM_OK;
 }
 
 int mpm_set_tuning(mpm_ctx ctx, const mpm_tuning* t) {
@@ -1256,7 +1323,6 @@ int mpm_destroy(mpm_ctx ctx) {
   if (!ctx) return MPM_EINVAL;
   (void)hipDeviceSynchronize();
   for (auto& e : ctx->prof_ev) (void)hipEventDestroy(e);
-  for (void* q : ctx->allocations) (void)hipFree(q);
   delete ctx;
   return MPM_OK;
 }
@@ -1278,22 +1344,21 @@ struct McisLayout {
 
 constexpr int64_t kMcisMaxCells = (int64_t)1 << 27;  // per cell array (0.5 GB of uint32)
 
-int mcis_layout(int32_t K, int64_t S, int64_t M, double sigma, double eps, McisLayout& L) {
-  if (K < 1 || S < 0 || M < 0 || M >= ((int64_t)1 << 32) || S >= ((int64_t)1 << 32)) return MPM_EINVAL;
-  if (!(sigma > 0.0) || !(eps > 0.0 && eps < 1.0) || !std::isfinite(sigma)) return MPM_EINVAL;
-  const double rs = sigma * std::sqrt(-2.0 * std::log(eps)) * (1.0 + 1e-9);
+// Workspace layout for K instances, S surface points, M candidates; the
+// fine grid is the finest (most rings per search radius, at most
+// kMcisRings) within the cell budget and, when max_bytes is nonzero, within
+// max_bytes of workspace.  The search result does not depend on the rings.
+int mcis_layout(int32_t K, int64_t S, int64_t M, double sigma, double eps, McisLayout& L, size_t max_bytes = 0);
+
+int mcis_layout_rings(int32_t K, int64_t S, int64_t M, double rs, int rings, McisLayout& L) {
   L.g.hc = rs * (1.0 + 1e-9);
   L.g.r2 = rs * rs;
   L.g.gc = (int)std::max(1.0, std::ceil(1.0 / L.g.hc));
   L.coarse_cells = (int64_t)K * L.g.gc * L.g.gc * L.g.gc;
-  // the finest grid (most rings per search radius) that stays within the cell budget
-  for (int rings = fmpm::kMcisRings; rings >= 1; --rings) {
-    L.g.rings = rings;
-    L.g.hf = rs * (1.0 + 1e-9) / rings;
-    L.g.gf = (int)std::max(1.0, std::ceil(1.0 / L.g.hf));
-    L.fine_cells = (int64_t)K * L.g.gf * L.g.gf * L.g.gf;
-    if (L.fine_cells < kMcisMaxCells) break;
-  }
+  L.g.rings = rings;
+  L.g.hf = rs * (1.0 + 1e-9) / rings;
+  L.g.gf = (int)std::max(1.0, std::ceil(1.0 / L.g.hf));
+  L.fine_cells = (int64_t)K * L.g.gf * L.g.gf * L.g.gf;
   if (L.fine_cells >= kMcisMaxCells || L.coarse_cells >= kMcisMaxCells) return MPM_EINVAL;  // sigma too small
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -1326,6 +1391,18 @@ int mcis_layout(int32_t K, int64_t S, int64_t M, double sigma, double eps, McisL
   L.bad = take(8);
   L.total = off;
   return MPM_OK;
+}
+
+int mcis_layout(int32_t K, int64_t S, int64_t M, double sigma, double eps, McisLayout& L, size_t max_bytes) {
+  if (K < 1 || S < 0 || M < 0 || M >= ((int64_t)1 << 32) || S >= ((int64_t)1 << 32)) return MPM_EINVAL;
+  if (!(sigma > 0.0) || !(eps > 0.0 && eps < 1.0) || !std::isfinite(sigma)) return MPM_EINVAL;
+  const double rs = sigma * std::sqrt(-2.0 * std::log(eps)) * (1.0 + 1e-9);
+  int rc = MPM_EINVAL;
+  for (int rings = fmpm::kMcisRings; rings >= 1; --rings) {
+    rc = mcis_layout_rings(K, S, M, rs, rings, L);
+    if (rc == MPM_OK && (max_bytes == 0 || L.total <= max_bytes)) return MPM_OK;
+  }
+  return max_bytes && rc == MPM_OK ? MPM_ENOMEM : MPM_EINVAL;
 }
 
 #define MCIS_TRY(call)                                  \
@@ -1363,15 +1440,19 @@ int mpm_mcis_workspace_size(int32_t n_instances, int64_t n_surface, int64_t n_ca
   return MPM_OK;
 }
 
-int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* surface_offsets,
-                    const float* candidates, const int64_t* candidate_offsets, const double* u,
-                    const int64_t* n_select, double sigma, double eps, void* workspace, size_t workspace_bytes,
-                    int64_t* out_index, double* d_out, void* stream) {
-  const int K = n_instances;
-  if (K < 1 || !surface_offsets || !candidate_offsets || !n_select) return MPM_EINVAL;
-  const int64_t S = surface_offsets[K], M = candidate_offsets[K];
-  if (surface_offsets[0] != 0 || candidate_offsets[0] != 0) return MPM_EINVAL;
-  std::vector<int64_t> out_off(K), prefix(K), rank(K);
+namespace {
+
+// MCIS steps 1-5 on `workspace` (layout L); out_off, prefix, rank are host
+// arrays of K int64 (see mcis_prepare).
+int mcis_run(int32_t K, const float* surface, const int64_t* surface_offsets, const float* candidates,
+             const int64_t* candidate_offsets, const double* u, double sigma, double eps, const McisLayout& L,
+             void* workspace, const int64_t* out_off, const int64_t* prefix, const int64_t* rank, int64_t* out_index,
+             double* d_out, hipStream_t s);
+
+// Host checks of the per-instance counts; fills each instance's output
+// offset and the start of its radix select (prefix, rank).
+int mcis_prepare(int32_t K, const int64_t* surface_offsets, const int64_t* candidate_offsets, const int64_t* n_select,
+                 int64_t* out_off, int64_t* prefix, int64_t* rank) {
   int64_t total_sel = 0;
   for (int k = 0; k < K; ++k) {
     const int64_t ns = surface_offsets[k + 1] - surface_offsets[k], nc = candidate_offsets[k + 1] - candidate_offsets[k];
@@ -1389,13 +1470,15 @@ int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* su
       rank[k] = n_select[k];
     }
   }
-  McisLayout L;
-  int rc = mcis_layout(K, S, M, sigma, eps, L);
-  if (rc) return rc;
-  if (M == 0) return MPM_OK;
-  if (!candidates || !u || !out_index || (S > 0 && !surface)) return MPM_EINVAL;
-  if (!workspace || workspace_bytes < L.total) return MPM_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
+  return MPM_OK;
+}
+
+int mcis_run(int32_t K, const float* surface, const int64_t* surface_offsets, const float* candidates,
+             const int64_t* candidate_offsets, const double* u, double sigma, double eps, const McisLayout& L,
+             void* workspace, const int64_t* out_off, const int64_t* prefix, const int64_t* rank, int64_t* out_index,
+             double* d_out, hipStream_t s) {
+  const int64_t S = surface_offsets[K], M = candidate_offsets[K];
+  int rc = MPM_OK;
   char* w = static_cast<char*>(workspace);
   auto at = [&](size_t o) { return static_cast<void*>(w + o); };
   int64_t* d_so = (int64_t*)at(L.so);
@@ -1418,9 +1501,9 @@ int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* su
 
   MCIS_TRY(hipMemcpyAsync(d_so, surface_offsets, 8 * (size_t)(K + 1), hipMemcpyHostToDevice, s));
   MCIS_TRY(hipMemcpyAsync(d_co, candidate_offsets, 8 * (size_t)(K + 1), hipMemcpyHostToDevice, s));
-  MCIS_TRY(hipMemcpyAsync(d_out_off, out_off.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
-  MCIS_TRY(hipMemcpyAsync(d_prefix, prefix.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
-  MCIS_TRY(hipMemcpyAsync(d_rank, rank.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_out_off, out_off, 8 * (size_t)K, hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_prefix, prefix, 8 * (size_t)K, hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_rank, rank, 8 * (size_t)K, hipMemcpyHostToDevice, s));
   if ((rc = mcis_fill(d_start, L.fine_cells + 1, s)) || (rc = mcis_fill(d_cstart, L.fine_cells + 2, s)) ||
       (rc = mcis_fill(d_coarse, L.coarse_cells, s)) ||
       (rc = mcis_fill(d_hist, 256 * (int64_t)K, s)) || (rc = mcis_fill(d_bad, 2, s)))
@@ -1470,3 +1553,27 @@ int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* su
   MCIS_TRY(hipStreamSynchronize(s));
   return bad ? MPM_EINVAL : MPM_OK;
 }
+
+}  // namespace
+
+int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* surface_offsets,
+                    const float* candidates, const int64_t* candidate_offsets, const double* u,
+                    const int64_t* n_select, double sigma, double eps, void* workspace, size_t workspace_bytes,
+                    int64_t* out_index, double* d_out, void* stream) {
+  const int K = n_instances;
+  if (K < 1 || !surface_offsets || !candidate_offsets || !n_select) return MPM_EINVAL;
+  const int64_t S = surface_offsets[K], M = candidate_offsets[K];
+  if (surface_offsets[0] != 0 || candidate_offsets[0] != 0) return MPM_EINVAL;
+  std::vector<int64_t> out_off(K), prefix(K), rank(K);
+  int rc = mcis_prepare(K, surface_offsets, candidate_offsets, n_select, out_off.data(), prefix.data(), rank.data());
+  if (rc) return rc;
+  McisLayout L;
+  rc = mcis_layout(K, S, M, sigma, eps, L);
+  if (rc) return rc;
+  if (M == 0) return MPM_OK;
+  if (!candidates || !u || !out_index || (S > 0 && !surface)) return MPM_EINVAL;
+  if (!workspace || workspace_bytes < L.total) return MPM_EINVAL;
+  return mcis_run(K, surface, surface_offsets, candidates, candidate_offsets, u, sigma, eps, L, workspace,
+                  out_off.data(), prefix.data(), rank.data(), out_index, d_out, (hipStream_t)stream);
+}
+

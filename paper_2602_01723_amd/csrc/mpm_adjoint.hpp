@@ -1,6 +1,6 @@
-// Reverse-mode (adjoint) kernels of the MLS-MPM substep for elastic
-// particles with identity plasticity (fixed-corotated, Hencky, Neo-Hookean,
-// StVK, fluid and volume models)
+// Reverse-mode (adjoint) kernels of the MLS-MPM substep: the stresses of the
+// fixed-corotated, Hencky, Neo-Hookean, StVK, fluid and volume models and
+// the von Mises, Drucker-Prager, fluid and sigma return maps
 // (included once, by fastmpm.hip after mpm_kernels.hpp).
 //
 // Forward substep k on state s_k = (x, v, C, F), per particle p and node i:
@@ -346,6 +346,212 @@ __device__ __forceinline__ void tau_hencky_adjoint(const double* F, const double
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Fb[3 * i + j] += 2.0 * (bb[3 * i] * F[j] + bb[3 * i + 1] * F[3 + j] + bb[3 * i + 2] * F[6 + j]);
+}
+
+// Adjoint of the plastic return map F' = Z(F_trial) (App. A.2, App. B.2):
+// Fbo is the cotangent of F', Fb receives that of F_trial, and the adjoints
+// of mu and lam are added to mub, lamb.
+//  * fluid, sigma: F' = cbrt(J) I, so Fb = tr(Fbo) cof(F) / (3 cbrt(J)^2)
+//    (zero where sigma plasticity clamps J).
+//  * von Mises, Drucker-Prager: with F = U diag(s) V^T, eps = log s,
+//    m = mean(eps), n = eps_hat / |eps_hat|, a flow step is
+//    F' = U diag(g) V^T, g_k = exp(m + r n_k), r = yield / (2 mu) (von Mises)
+//    or r = -3 beta m, beta = (3 lam + 2 mu) / (2 mu) alpha (Drucker-Prager);
+//    the Drucker-Prager tension case is g = 1.  For a function of this form,
+//    with G = U^T Fbo V:
+//      Pb_ii = s_i^-1 sum_k G_kk g_k d eps'_k / d eps_i,
+//      Pb_ij = (a + b)/2 G_ij + (a - b)/2 G_ji  (i != j),
+//      a = (g_i - g_j) / (s_i - s_j),  b = (g_i + g_j) / (s_i + s_j),
+//    and Fb = U Pb V^T.  a is taken as g_j / s_j * expm1(c L) / expm1(L),
+//    L = eps_i - eps_j, c = r / |eps_hat| (g_i = K s_i^c), which stays exact
+//    as s_i -> s_j.  Singular values under the log floor do not move eps.
+__device__ __forceinline__ void return_map_adjoint(const Material& mat, double mu, double lam, const double* F,
+                                                   const double* Fbo, double* Fb, double& mub, double& lamb) {
+  if (mat.plastic == kPlasticFluid || mat.plastic == kPlasticSigma) {
+    const double J = det3(F);
+    if (mat.plastic == kPlasticSigma && (J < kSigmaJLo || J > kSigmaJHi)) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fb[k] = 0.0;
+      return;
+    }
+    const double c = cbrt(J);
+    const double kf = (Fbo[0] + Fbo[4] + Fbo[8]) / (3.0 * c * c);
+    Fb[0] = kf * (F[4] * F[8] - F[5] * F[7]);
+    Fb[1] = kf * (F[5] * F[6] - F[3] * F[8]);
+    Fb[2] = kf * (F[3] * F[7] - F[4] * F[6]);
+    Fb[3] = kf * (F[2] * F[7] - F[1] * F[8]);
+    Fb[4] = kf * (F[0] * F[8] - F[2] * F[6]);
+    Fb[5] = kf * (F[1] * F[6] - F[0] * F[7]);
+    Fb[6] = kf * (F[1] * F[5] - F[2] * F[4]);
+    Fb[7] = kf * (F[2] * F[3] - F[0] * F[5]);
+    Fb[8] = kf * (F[0] * F[4] - F[1] * F[3]);
+    return;
+  }
+  if (mat.plastic != kPlasticVonMises && mat.plastic != kPlasticDruckerPrager) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fb[k] = Fbo[k];
+    return;
+  }
+  double U[3][3], V[3][3], sg[3], e[3];
+  svd3(F, U, sg, V);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) e[k] = log(fmax(sg[k], kSigmaMin));
+  const double tr = e[0] + e[1] + e[2];
+  const double m = tr * (1.0 / 3.0);
+  const double eh[3] = {e[0] - m, e[1] - m, e[2] - m};
+  const double nrm = sqrt(eh[0] * eh[0] + eh[1] * eh[1] + eh[2] * eh[2]);
+  // the branch the forward return map took
+  bool tension = false;
+  double r = 0.0, drde = 0.0, beta = 0.0;
+  if (mat.plastic == kPlasticVonMises) {
+    r = (double)mat.yield_stress / (2.0 * mu);
+    if (!(nrm - r > 0.0)) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fb[k] = Fbo[k];
+      return;
+    }
+  } else if (tr > 0.0) {
+    tension = true;
+  } else {
+    beta = (3.0 * lam + 2.0 * mu) / (2.0 * mu) * (double)mat.dp_alpha;
+    if (!(nrm + beta * tr > 0.0)) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fb[k] = Fbo[k];
+      return;
+    }
+    r = -beta * tr;
+    drde = -beta;
+  }
+  // G = U^T Fbo V
+  double G[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t += U[a][i] * Fbo[3 * a + b] * V[b][j];
+      G[i][j] = t;
+    }
+  double g[3] = {1.0, 1.0, 1.0}, P[3][3];
+  const double cc = tension ? 0.0 : r / nrm;
+  if (tension) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) P[i][i] = 0.0;
+  } else {
+    double n[3], h[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      n[k] = eh[k] / nrm;
+      g[k] = exp(m + r * n[k]);
+      h[k] = G[k][k] * g[k];
+    }
+    const double H = h[0] + h[1] + h[2];
+    const double nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double d = H * (1.0 / 3.0) + cc * (h[i] - H * (1.0 / 3.0) - n[i] * nh) + drde * nh;
+      P[i][i] = (sg[i] > kSigmaMin) ? d / sg[i] : 0.0;
+    }
+    // r-bar = n . h
+    if (mat.plastic == kPlasticVonMises) {
+      mub += -nh * r / mu;
+    } else {
+      const double bb = -tr * nh;  // beta-bar
+      const double al = (double)mat.dp_alpha;
+      lamb += bb * 1.5 * al / mu;
+      mub += -bb * 1.5 * al * lam / (mu * mu);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 3; ++j) {
+      double a = 0.0;
+      if (!tension) {
+        if (sg[i] > kSigmaMin && sg[j] > kSigmaMin) {
+          const double L = e[i] - e[j];
+          const double ratio = (fabs(L) < 1e-6) ? cc * (1.0 + 0.5 * (cc - 1.0) * L) : expm1(cc * L) / expm1(L);
+          a = g[j] / sg[j] * ratio;
+        } else if (sg[i] != sg[j]) {
+          a = (g[i] - g[j]) / (sg[i] - sg[j]);
+        }
+      }
+      double den = sg[i] + sg[j];
+      if (fabs(den) < 1e-12) den = (den < 0.0) ? -1e-12 : 1e-12;
+      const double b = (g[i] + g[j]) / den;
+      const double gij = G[i][j], gji = G[j][i];
+      P[i][j] = 0.5 * (a + b) * gij + 0.5 * (a - b) * gji;
+      P[j][i] = 0.5 * (a + b) * gji + 0.5 * (a - b) * gij;
+    }
+  // Fb = U P V^T
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t += U[i][a] * P[a][b] * V[j][b];
+      Fb[3 * i + j] = t;
+    }
+}
+
+// Reverse of one substep's return map, particle-parallel: on entry aF holds
+// the adjoint of F_{k+1}, on exit that of F_trial = (I + dt C') F_k, formed
+// from F_k and C' = C_{k+1} of the recomputed states the way the forward
+// pass formed it; the adjoints of mu and lam go into the parameter
+// gradients.  Particles without a return map, and particles the forward
+// pass skipped, keep aF.
+__global__ __launch_bounds__(256) void k_adj_return_map(const float* x, const float* F, const float* Cn, const float4* prm, const int* mat,
+                                 const Material* mats, int n_materials, const float* lnE, const float* nu, float dt,
+                                 int n, float* aF, float* g_lnE, float* g_nu, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int mid = mat[i];
+  mid = (mid >= 0 && mid < n_materials) ? mid : 0;
+  const Material mt = mats[mid];
+  if (mt.plastic == kPlasticNone) return;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int b;
+    float f;
+    ok &= cell_of(x[k * N + i], n, b, f);
+  }
+  if (!ok) return;
+  double Fd[9], Cp[9], Fbo[9], Ftr[9], Fb[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Fd[k] = (double)F[k * N + i];
+    Cp[k] = (double)Cn[k * N + i];
+    Fbo[k] = (double)aF[k * N + i];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double acc = Fd[3 * r + c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc += (double)dt * Cp[3 * r + k] * Fd[3 * k + c];
+      Ftr[3 * r + c] = acc;
+    }
+  const float4 pm = prm[i];
+  const double mu = (double)pm.z, lam = (double)pm.w;
+  double mub = 0.0, lamb = 0.0;
+  return_map_adjoint(mt, mu, lam, Ftr, Fbo, Fb, mub, lamb);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) aF[k * N + i] = (float)Fb[k];
+  if (mub != 0.0 || lamb != 0.0) {
+    const double E = exp((double)lnE[i]);
+    const double nv = (double)nu[i];
+    const double den = (1.0 + nv) * (1.0 - 2.0 * nv);
+    g_lnE[i] += (float)(mub * mu + lamb * lam);
+    g_nu[i] += (float)(-mub * mu / (1.0 + nv) + lamb * E * (1.0 + 2.0 * nv * nv) / (den * den));
+  }
 }
 
 // --------------------------------------------------------------------------

@@ -75,6 +75,9 @@ struct SubstepArgs {
   // set, receives a box containing the cells after this substep
   const int* box_in;
   int* box_out;
+  // CFL watch: G2P velocities with |v'|^2 above cfl_v2 (|v'| dt / dx > 1/2)
+  // are counted in diag[4]; the largest |v'|^2 goes to diag[5]
+  float cfl_v2;
 };
 
 // --------------------------------------------------------------------------
@@ -90,6 +93,23 @@ __device__ __forceinline__ float wave_maxf(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   return v;
+}
+
+__device__ __forceinline__ unsigned wave_sum_u(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// The CFL watch of one wave: adds its count of violations to diag[4] and
+// raises diag[5] (float bits, non-negative) to its largest |v|^2.
+__device__ __forceinline__ void cfl_flush(unsigned long long* diag, float v2max, unsigned count) {
+  const float m = wave_maxf(v2max);
+  const unsigned c = wave_sum_u(count);
+  if ((threadIdx.x & 63) == 0) {
+    if (c) atomicAdd(&diag[4], (unsigned long long)c);
+    if (m > 0.0f) atomicMax(reinterpret_cast<unsigned*>(&diag[5]), __float_as_uint(m));
+  }
 }
 
 // 64-bit fixed point of the P2G tile.  fx_bits(v, s) = bits of
@@ -316,6 +336,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     for (int64_t t = c0 + threadIdx.x; t < c1; t += kBlock) a.grid_clear[t] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
 
+  float v2max = 0.0f;  // CFL watch over this lane's particles
+  unsigned cfl_count = 0;
   for (;;) {
     __syncthreads();  // tiles and item_s are reused
     if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1);
@@ -543,6 +565,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
               vp[k] = vs[k];
               xp[k] = xp[k] + a.dt * vs[k];
             }
+            const float v2 = vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2];
+            v2max = fmaxf(v2max, v2);
+            cfl_count += (v2 > a.cfl_v2) ? 1u : 0u;
             // F_trial = (I + dt C') F, in double
             double Ftr[9];
 #pragma unroll
@@ -742,6 +767,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       }
     }
   }
+  if (MODE != kP2G) cfl_flush(a.diag, v2max, cfl_count);
   // the queue is drained: the last workgroup out resets the counters
   if (a.done_counter && threadIdx.x == 0) {
     __threadfence();
@@ -1165,18 +1191,30 @@ __global__ void k_scatter_planes(PlaneSet ps, const int* dest, int64_t N) {
 
 // internal particle parameters from the sorted parameter planes (mat id as
 // int bits); pid = caller index per slot
+// Parameters in sorted order: prm = (mass, V0, mu, lam) with the Lame
+// parameters from (log E, nu) in float64, the material id and the caller
+// index.  diag[6] (float bits) is raised to the largest squared P-wave speed
+// c^2 = (lam + 2 mu) V0 / m of the particles (the stiffness bound of the
+// elastic CFL condition c dt / dx < 1).
 __global__ void k_params_planes(float4* prm, int* mat, int* pid, const float* mass, const float* vol0,
                                 const float* log_E, const float* nu, const float* mat_bits, const int* perm,
-                                int64_t N) {
+                                int64_t N, unsigned long long* diag) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const double E = exp((double)log_E[j]);
-  const double nv = (double)nu[j];
-  const double mu = E / (2.0 * (1.0 + nv));
-  const double la = E * nv / ((1.0 + nv) * (1.0 - 2.0 * nv));
-  prm[j] = make_float4(mass[j], vol0[j], (float)mu, (float)la);
-  mat[j] = __float_as_int(mat_bits[j]);
-  pid[j] = perm[j];
+  float c2 = 0.0f;
+  if (j < N) {
+    const double E = exp((double)log_E[j]);
+    const double nv = (double)nu[j];
+    const double mu = E / (2.0 * (1.0 + nv));
+    const double la = E * nv / ((1.0 + nv) * (1.0 - 2.0 * nv));
+    prm[j] = make_float4(mass[j], vol0[j], (float)mu, (float)la);
+    mat[j] = __float_as_int(mat_bits[j]);
+    pid[j] = perm[j];
+    const double w = (la + 2.0 * mu) * (double)vol0[j] / (double)mass[j];
+    c2 = (w > 0.0 && w < 3.0e38) ? (float)w : 0.0f;
+  }
+  c2 = wave_maxf(c2);
+  if (diag && (threadIdx.x & 63) == 0 && c2 > 0.0f)
+    atomicMax(reinterpret_cast<unsigned*>(&diag[6]), __float_as_uint(c2));
 }
 
 __global__ void k_gather_misc(float4* prm_out, int* mat_out, int* pid_out, const float4* prm_in, const int* mat_in,

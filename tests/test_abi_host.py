@@ -48,13 +48,44 @@ def _cfg(**kw):
                         base["sort_every"], base["flags"])
 
 
-def _init(lib, cfg, mats=None, n=10, offsets=None):
+def _init(lib, cfg, mats=None, n=10, offsets=None, workspace=None, nbytes=0):
     mats = mats or [B.mpm_material(0, 0, 0.0, 0.0)]
     arr = (B.mpm_material * len(mats))(*mats)
     h = ctypes.c_void_p()
     offs = None if offsets is None else (ctypes.c_int64 * len(offsets))(*offsets)
-    rc = lib.mpm_init(ctypes.byref(cfg), arr, len(mats), n, offs, ctypes.byref(h))
+    rc = lib.mpm_init(ctypes.byref(cfg), arr, len(mats), n, offs, workspace, nbytes, ctypes.byref(h))
     return rc, h
+
+
+def _ws_size(lib, cfg, n):
+    out = ctypes.c_size_t()
+    rc = lib.mpm_workspace_size(ctypes.byref(cfg), n, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_workspace_size(lib):
+    """The workspace grows with the particle count and the grid; invalid
+    configurations are refused on the host."""
+    rc, small = _ws_size(lib, _cfg(), 1000)
+    assert rc == B.MPM_OK and small > 0 and small % 256 == 0
+    rc, big = _ws_size(lib, _cfg(), 100_000)
+    assert rc == B.MPM_OK and big > small + 100_000 * 300  # >= 332 B per particle of buffers
+    rc, grid = _ws_size(lib, _cfg(grid_res=64), 1000)
+    assert rc == B.MPM_OK and grid > small + 3 * 16 * (64 ** 3 - 32 ** 3)  # three float4 grids
+    assert _ws_size(lib, _cfg(grid_res=4), 10)[0] == B.MPM_EINVAL
+    assert _ws_size(lib, _cfg(), -1)[0] == B.MPM_EINVAL
+    assert lib.mpm_workspace_size(ctypes.byref(_cfg()), 10, None) == B.MPM_EINVAL
+
+
+def test_workspace_checks_before_any_device_work(lib):
+    """NULL or misaligned workspaces are invalid; one byte short is MPM_ENOMEM.
+    The addresses below are never dereferenced: the checks run on the host."""
+    cfg = _cfg()
+    _, need = _ws_size(lib, cfg, 10)
+    assert _init(lib, cfg, workspace=None, nbytes=need)[0] == B.MPM_EINVAL
+    assert _init(lib, cfg, workspace=0x100001, nbytes=need)[0] == B.MPM_EINVAL
+    rc, h = _init(lib, cfg, workspace=0x100000, nbytes=need - 1)
+    assert rc == B.MPM_ENOMEM and not h.value
 
 
 @pytest.mark.parametrize("kw", [dict(abi_version=2), dict(grid_res=4), dict(grid_res=4096), dict(bound=-1),
@@ -79,7 +110,7 @@ def test_invalid_materials_and_offsets(lib):
 
 
 def test_null_arguments(lib):
-    assert lib.mpm_init(None, None, 0, 0, None, None) == B.MPM_EINVAL
+    assert lib.mpm_init(None, None, 0, 0, None, None, 0, None) == B.MPM_EINVAL
     assert lib.mpm_step_n(None, None, 1, None, 0, None) == B.MPM_EINVAL
     assert lib.mpm_load(None, None, None) == B.MPM_EINVAL
     assert lib.mpm_advance(None, 1, None) == B.MPM_EINVAL

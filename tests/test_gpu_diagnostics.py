@@ -47,20 +47,53 @@ def test_particle_outside_stencil_box_is_counted_and_skipped():
     assert np.isfinite(xo).all()
 
 
-def test_overstiff_material_trips_the_instability_counters():
+def test_overstiff_material_trips_the_cfl_watch_before_it_blows_up():
     """E0 = 3e10 (the paper's failing initial guess) with dt = 1e-4 violates
-    the elastic CFL bound by orders of magnitude: the run blows up and the
-    device counters report it."""
+    the elastic CFL bound by orders of magnitude.  The wave-speed figure says
+    so from the start; the velocity watch (|v'| dt / dx > 1/2) trips in a
+    substep at which every particle is still finite and on the grid, and the
+    run blows up later."""
     sc = _cube(E=3e10)
     v = sc.v.copy()
     v[:, 1] = -2.0
     ctx = B.init_from_scene(sc)
     p = B.Particles.from_arrays(sc.x, v, sc.C, sc.F, sc.mass, sc.vol0, sc.log_E, sc.nu, sc.mat_id)
-    for _ in range(10):
-        B.mpm_step_n(ctx, p, 20)
+    tripped_at, blown_at = None, None
+    for k in range(1, 201):
+        B.mpm_step_n(ctx, p, 1)
+        d = B.mpm_get_diagnostics(ctx)
+        if k == 1:
+            assert d["max_wave_cfl"] > 10.0, d  # c dt / dx of E = 3e10
+        if tripped_at is None and d["cfl_violations"] > 0:
+            tripped_at = k
+            print("CFL watch tripped at substep", k, d, flush=True)
+            assert d["nonfinite"] == 0 and d["out_of_grid"] == 0 and d["status"] == B.MPM_EUNSTABLE, d
+            assert np.isfinite(p.state_numpy()[0]).all()
+        if d["nonfinite"] + d["out_of_grid"] > 0:
+            blown_at = k
+            break
+    print("blown up at substep", blown_at, d, flush=True)
+    assert tripped_at is not None and (blown_at is None or tripped_at < blown_at)
+
+
+def test_cfl_figures_of_a_free_fall():
+    """A lattice cube at rest with F = I falls freely (no stress): after k
+    substeps every particle has |v| = k dt g, so the largest |v| dt / dx is
+    k dt^2 g n; the P-wave figure is sqrt((lam + 2 mu) V0 / m) dt n."""
+    sc = _cube()
+    ctx = B.init_from_scene(sc)
+    p = B.Particles.from_scene(sc)
+    k = 12
+    B.mpm_step_n(ctx, p, k)
     d = B.mpm_get_diagnostics(ctx)
-    print(d, flush=True)
-    assert d["nonfinite"] + d["out_of_grid"] > 0 and d["status"] == B.MPM_EUNSTABLE
+    n, dt = sc.grid_res, sc.dt
+    want = k * dt * dt * 9.8 * n
+    E, nu = math.exp(float(sc.log_E[0])), float(sc.nu[0])
+    c = math.sqrt(E * (1 - nu) / ((1 + nu) * (1 - 2 * nu)) * float(sc.vol0[0]) / float(sc.mass[0]))
+    print(d, want, c * dt * n, flush=True)
+    assert d["status"] == B.MPM_OK and d["cfl_violations"] == 0
+    assert abs(d["max_cfl"] - want) <= 1e-5 * want
+    assert abs(d["max_wave_cfl"] - c * dt * n) <= 1e-6 * c * dt * n
 
 
 def test_resume_matches_one_long_call():

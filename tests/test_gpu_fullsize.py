@@ -16,7 +16,7 @@ import torch
 from oracle import mpm_oracle as O
 from paper_2602_01723_amd import binding as B
 from paper_2602_01723_amd import scenes
-from tests.parity import TOL_SUBSTEP, rel_err
+from tests.parity import TOL_SUBSTEP, dx_tolerance, elem_err, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -80,10 +80,10 @@ def test_fullsize_p2g_sampled_nodes(fullsize_step):
     mr, mvr = mr.numpy()[nodes], mvr.numpy()[nodes]
     s_m = float(sc.mass.mean())
     s_v = max(float(np.abs(state0[1]).max()), 9.8 * sc.dt)
-    e_m = rel_err(m[nodes], mr, s_m)
-    e_mv = rel_err(mv[nodes], mvr, s_m * s_v)
-    print("sampled nodes", len(nodes), "particles", len(sub), "err m", e_m, "err mv", e_mv, flush=True)
-    assert e_m <= TOL_SUBSTEP and e_mv <= TOL_SUBSTEP
+    errs = dict(m=rel_err(m[nodes], mr, s_m), mv=rel_err(mv[nodes], mvr, s_m * s_v),
+                m_e=elem_err(m[nodes], mr, s_m), mv_e=elem_err(mv[nodes], mvr, s_m * s_v))
+    print("sampled nodes", len(nodes), "particles", len(sub), errs, flush=True)
+    assert max(errs.values()) <= TOL_SUBSTEP, errs
 
 
 def test_fullsize_grid_update_and_g2p_sampled_particles(fullsize_step):
@@ -92,7 +92,9 @@ def test_fullsize_grid_update_and_g2p_sampled_particles(fullsize_step):
     vr = O.grid_update(torch.tensor(m), torch.tensor(mv), n, sc.dt, sc.gravity, sc.bound).numpy()
     sel = m > 1e-6 * m.max()
     s_v = max(float(np.abs(vr).max()), 9.8 * sc.dt)
-    assert rel_err(v[sel], vr[sel], s_v) <= TOL_SUBSTEP
+    e_v = (rel_err(v[sel], vr[sel], s_v), elem_err(v[sel], vr[sel], s_v))
+    print("grid update", e_v, flush=True)
+    assert max(e_v) <= TOL_SUBSTEP
     rng = np.random.default_rng(1)
     pick = rng.choice(sc.n, 20000, replace=False)
     params = O.Params(sc.mass[pick], sc.vol0[pick], sc.log_E[pick], sc.nu[pick], sc.mat_id[pick], sc.materials, n,
@@ -103,7 +105,15 @@ def test_fullsize_grid_update_and_g2p_sampled_particles(fullsize_step):
     mu, lam = O.lame(params.log_E, params.nu)
     F1 = O.plasticity(Ftr, mu, lam, params.mat_id, params.materials)
     sv = max(float(v1.abs().max()), 9.8 * sc.dt)
-    errs = dict(x=rel_err(state1[0][pick], x1.numpy(), 1.0 / n), v=rel_err(state1[1][pick], v1.numpy(), sv),
-                C=rel_err(state1[2][pick], C1.numpy(), sv * n), F=rel_err(state1[3][pick], F1.numpy(), 1.0))
-    print("sampled particles", len(pick), errs, flush=True)
+    errs = {}
+    for k, g, r, s in (("x", state1[0][pick], x1.numpy(), 1.0 / n), ("v", state1[1][pick], v1.numpy(), sv),
+                       ("C", state1[2][pick], C1.numpy(), sv * n), ("F", state1[3][pick], F1.numpy(), 1.0)):
+        errs[k] = rel_err(g, r, s)
+        errs[k + "_e"] = elem_err(g, r, s)
+    d_g = state1[0][pick].astype(np.float64) - x0.numpy()
+    d_r = x1.numpy() - x0.numpy()
+    e_dx = elem_err(d_g, d_r, sc.dt * sv)
+    dx_tol = dx_tolerance(x1.numpy(), sc.dt, sv)
+    print("sampled particles", len(pick), errs, "dx_e", e_dx, "bound", dx_tol, flush=True)
     assert max(errs.values()) <= TOL_SUBSTEP, errs
+    assert e_dx <= dx_tol
