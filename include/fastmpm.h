@@ -53,7 +53,8 @@ typedef struct mpm_context* mpm_ctx;
 typedef enum {
   MPM_OK = 0,
   MPM_EINVAL = -1,       /* bad argument or configuration (nothing was enqueued) */
-  MPM_ENOMEM = -2,       /* a caller buffer (workspace, tape) is smaller than required */
+  MPM_ENOMEM = -2,       /* a caller buffer (workspace, tape), or the fixed scratch of
+                            mpm_mcis_select_static, is smaller than required */
   MPM_EDEVICE = -3,      /* a HIP runtime call failed */
   MPM_ESTATE = -4,       /* call out of order (e.g. backward without a taped forward) */
   MPM_EUNSTABLE = -5,    /* device counters saw NaN/Inf or a stencil leaving the grid */
@@ -335,6 +336,23 @@ int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* su
                     const float* candidates, const int64_t* candidate_offsets, const double* u,
                     const int64_t* n_select, double sigma, double eps, void* workspace, size_t workspace_bytes,
                     int64_t* out_index, double* d_out, void* stream);
+
+/* mpm_mcis_select without allocation, for callers that cannot allocate
+ * device memory (serving loops, code that may not call hipMalloc): the same
+ * operation, arguments and results as mpm_mcis_select, with the workspace
+ * taken from a fixed 64 MiB device array that the library holds on each GPU
+ * it runs on until the process ends (no workspace arguments).  Supports at
+ * most 256 instances and inputs whose layout fits the array (about 2M
+ * candidates plus surface points; the search grid is coarsened to fit,
+ * which leaves the result unchanged).  MPM_ENOMEM for inputs beyond that,
+ * MPM_EINVAL as for mpm_mcis_select, MPM_EDEVICE if the array's device
+ * address cannot be obtained.  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (other host threads, other streams)
+ * race and must not be issued.  Synchronises `stream` before returning. */
+int mpm_mcis_select_static(int32_t n_instances, const float* surface, const int64_t* surface_offsets,
+                           const float* candidates, const int64_t* candidate_offsets, const double* u,
+                           const int64_t* n_select, double sigma, double eps, int64_t* out_index, double* d_out,
+                           void* stream);
 
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, by class: 0 fused G2P+P2G substep kernel, 1 P2G-only kernel,

@@ -26,7 +26,8 @@ EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_workspace_size", "mpm_in
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
             "mpm_set_tuning", "mpm_get_tuning", "mpm_autotune", "mpm_graph_begin", "mpm_graph_end",
             "mpm_graph_launch", "mpm_graph_destroy", "mpm_position_loss_grad", "mpm_bgdo_accumulate",
-            "mpm_bgdo_apply", "mpm_mcis_workspace_size", "mpm_mcis_select", "mpm_profile", "mpm_profile_read",
+            "mpm_bgdo_apply", "mpm_mcis_workspace_size", "mpm_mcis_select", "mpm_mcis_select_static", "mpm_profile",
+            "mpm_profile_read",
             "mpm_destroy")
 PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io", "unused",
                    "other_fill")
@@ -117,6 +118,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_mcis_select": (ctypes.c_int, [i32, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64), vp,
                                            ctypes.POINTER(i64), ctypes.c_double, ctypes.c_double, vp, sz, vp, vp,
                                            vp]),
+        "mpm_mcis_select_static": (ctypes.c_int, [i32, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64), vp,
+                                                  ctypes.POINTER(i64), ctypes.c_double, ctypes.c_double, vp, vp, vp]),
         "mpm_graph_destroy": (ctypes.c_int, [vp]),
         "mpm_profile": (ctypes.c_int, [vp, i32]),
         "mpm_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -445,6 +448,22 @@ def mpm_mcis_select(surface, surface_offsets, candidates, candidate_offsets, u, 
     if rc:
         _check(None, rc, "mpm_mcis_select")
     return out[:sum(int(v) for v in n_select)], d
+
+
+def mpm_mcis_select_static(surface, surface_offsets, candidates, candidate_offsets, u, n_select, out, sigma=0.02,
+                           eps=1e-6, d=None, stream=None):
+    """mpm_mcis_select on the library's fixed device scratch: no workspace is
+    allocated; `out` (int64 device tensor of sum(n_select) entries) and the
+    optional `d` (float64 device tensor of M entries) are the caller's."""
+    lib = load()
+    K = len(n_select)
+    so = (ctypes.c_int64 * (K + 1))(*[int(v) for v in surface_offsets])
+    co = (ctypes.c_int64 * (K + 1))(*[int(v) for v in candidate_offsets])
+    ns = (ctypes.c_int64 * K)(*[int(v) for v in n_select])
+    rc = lib.mpm_mcis_select_static(K, _ptr(surface) if int(so[K]) else None, so, _ptr(candidates), co, _ptr(u), ns,
+                                    float(sigma), float(eps), _ptr(out), _ptr(d), _stream(stream))
+    if rc:
+        _check(None, rc, "mpm_mcis_select_static")
 
 
 def mpm_profile(ctx: Context, enable: bool = True):

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1577,3 +1578,65 @@ int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* su
                   out_off.data(), prefix.data(), rank.data(), out_index, d_out, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------------------
+// MCIS without allocation (mpm_mcis_select_static): the workspace is a
+// file-scope device array of fixed size.  Its host-side name is only a
+// stand-in; the device address comes from hipGetSymbolAddress, looked up
+// once per device on the first call there, and is what the kernels get.
+// ---------------------------------------------------------------------------
+constexpr size_t kMcisStaticBytes = (size_t)64 << 20;  // per device
+constexpr int kMcisStaticMaxInstances = 256;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kMcisStaticBytes];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return MPM_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return MPM_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MPM_OK;
+}
+
+}  // namespace
+
+int mpm_mcis_select_static(int32_t n_instances, const float* surface, const int64_t* surface_offsets,
+                           const float* candidates, const int64_t* candidate_offsets, const double* u,
+                           const int64_t* n_select, double sigma, double eps, int64_t* out_index, double* d_out,
+                           void* stream) {
+  const int K = n_instances;
+  if (K < 1 || K > kMcisStaticMaxInstances || !surface_offsets || !candidate_offsets || !n_select)
+    return MPM_EINVAL;
+  const int64_t S = surface_offsets[K], M = candidate_offsets[K];
+  if (surface_offsets[0] != 0 || candidate_offsets[0] != 0) return MPM_EINVAL;
+  int64_t out_off[kMcisStaticMaxInstances], prefix[kMcisStaticMaxInstances], rank[kMcisStaticMaxInstances];
+  int rc = mcis_prepare(K, surface_offsets, candidate_offsets, n_select, out_off, prefix, rank);
+  if (rc) return rc;
+  McisLayout L;
+  rc = mcis_layout(K, S, M, sigma, eps, L, kMcisStaticBytes);  // MPM_ENOMEM beyond the fixed scratch
+  if (rc) return rc;
+  if (M == 0) return MPM_OK;
+  if (!candidates || !u || !out_index || (S > 0 && !surface)) return MPM_EINVAL;
+  void* ws = nullptr;
+  rc = static_scratch(&ws);
+  if (rc) return rc;
+  return mcis_run(K, surface, surface_offsets, candidates, candidate_offsets, u, sigma, eps, L, ws, out_off, prefix,
+                  rank, out_index, d_out, (hipStream_t)stream);
+}
