@@ -35,6 +35,20 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = 116
 # per active grid node: its accumulated (mv, m) written once and read once
 BYTES_PER_ACTIVE_NODE = 32
+# LDS atomic adds of the P2G tile per particle-substep: 27 nodes x 4 channels
+LDS_ADDS_PER_PARTICLE = 108
+# algorithmic bytes of the adjoint kernels per particle-substep:
+#   k_adj_g2p reads x 12, F 36 and the adjoints of x, v, C, F (96); writes
+#     those of x and F (48)
+#   k_adj_p2g reads x, v, C, F (96), params 16, material 4, log E 4, nu 4,
+#     the adjoints of x and F (48) and the parameter gradients (8); writes
+#     the adjoints of x, v, C, F (96) and the parameter gradients (8)
+ADJ_G2P_BYTES = 192
+ADJ_P2G_BYTES = 284
+# one particle-substep of the taped forward + backward: the forward's fused
+# kernel (116), its recompute that also writes v and C (164) and the two
+# adjoint kernels
+FWD_BWD_BYTES = 116 + 164 + ADJ_G2P_BYTES + ADJ_P2G_BYTES
 
 
 KERNEL_SOURCES = ("paper_2602_01723_amd/csrc/mpm_kernels.hpp", "paper_2602_01723_amd/csrc/mpm_math.hpp")
@@ -79,7 +93,7 @@ VALU_FILE = os.path.join(ROOT, "profiles", "fused_substep_large_scene_valu.json"
 VALU_COMMAND = ("cd /tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
                 "SQ_INSTS_LDS SQ_WAIT_INST_ANY SQ_INSTS_SALU --kernel-include-regex k_substep -f csv -d <out>/pmc_p1 "
                 "-o p1 -- python3 <repo>/bench.py --steps 1 --warmup 1 --substeps-per-step 10 --no-autotune "
-                "--no-step-n --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis")
+                "--no-step-n --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis --no-configs --no-atomics")
 
 
 def write_valu(p1_csv, n_particles=2_000_000):
@@ -110,7 +124,7 @@ def measured_valu(n_particles):
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
                "--steps 1 --warmup 1 --substeps-per-step 10 --no-autotune --no-step-n --no-cpu-baseline --no-batched "
-               "--no-bgdo --no-models --no-mcis")
+               "--no-bgdo --no-models --no-mcis --no-configs --no-atomics")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
@@ -247,6 +261,47 @@ def mcis_timing(reps=3):
             "paper_context": "IPF with MCIS 22 s per scene on an RTX A6000 (with DBSCAN and hulls; not comparable)"}
 
 
+def summarize_adjoint_counters(csv_paths, n_particles=None) -> dict:
+    """Per-dispatch means of every counter in rocprofv3 --pmc runs of
+    `bench.py --adjoint-counters`, per adjoint kernel, and per particle
+    (the 64-candidate batch: 2,374,644 particles); FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch) are also scaled by the same counter's reading for the
+    run's 256 MiB copy."""
+    import csv
+    n = n_particles or 2_374_644
+    sums, cnts, copy = {}, {}, {}
+    for path in csv_paths:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                k, c, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+                if k == "__amd_rocclr_copyBuffer":
+                    copy[c] = max(copy.get(c, 0.0), v)
+                    continue
+                key = "k_adj_g2p" if "k_adj_g2p" in k else ("k_adj_p2g" if "k_adj_p2g" in k else None)
+                if key is None:
+                    continue
+                sums.setdefault(key, {}).setdefault(c, 0.0)
+                sums[key][c] += v
+                cnts.setdefault(key, {}).setdefault(c, 0)
+                cnts[key][c] += 1
+    out = {"particles": n}
+    for key in sums:
+        d = {}
+        for c in sums[key]:
+            mean = sums[key][c] / cnts[key][c]
+            d[c] = mean
+            if c.startswith("SQ_INSTS") or c in ("SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_WAIT_INST_ANY"):
+                d[c + "_per_particle"] = mean * 64.0 / n
+            if c in ("FETCH_SIZE", "WRITE_SIZE") and copy.get(c):
+                scale = 256 * 1024 * 1024 / (copy[c] * 1024.0)
+                d[c + "_bytes_scaled"] = mean * 1024.0 * scale
+                d[c + "_bytes_per_particle"] = mean * 1024.0 * scale / n
+        d["dispatches"] = max(cnts[key].values())
+        out[key] = d
+    out["copy_calibration_kib"] = copy
+    return out
+
+
 def summarize_batched_trace(trace_csv: str) -> str:
     """One batched evaluation from a rocprofv3 kernel trace of --batched-only:
     the dispatches between the last two full-size position-loss kernels (the
@@ -300,6 +355,22 @@ def summarize_counters(csv_paths, kernel="k_substep<1>", n_particles=2_000_000) 
     return out
 
 
+def atomic_probe():
+    """Rates of the atomic operations the fused kernel is built on, measured
+    on this device in this run (libmpm_probes.so): LDS 64-bit adds with
+    lane-consecutive words and in the P2G scatter's node pattern, and global
+    FP32 adds to lane-distinct floats and to the 4 channels of a node."""
+    from paper_2602_01723_amd import probes as P
+    out = {}
+    for name, pat in (("lds_add_u64_consecutive", 0), ("lds_add_u64_p2g_pattern", 1)):
+        best = max(P.lds_add_u64(pat)["lane_ops_per_s"] for _ in range(3))
+        out[name] = best
+    for name, pat in (("global_add_f32_distinct", 0), ("global_add_f32_node_channels", 1)):
+        best = max(P.global_add_f32(pat)["lane_ops_per_s"] for _ in range(3))
+        out[name] = best
+    return {k: round(v / 1e12, 4) for k, v in out.items()} | {"unit": "T lane-ops/s"}
+
+
 def copy_probe(reps=20):
     """A plain 256 MiB device copy: the calibration point of the HBM counters,
     and (timed over reps copies of the same size) the bandwidth a plain copy
@@ -323,10 +394,11 @@ def copy_probe(reps=20):
     return 2 * 256 * 1024 * 1024 / t / 1e9
 
 
-def batched_setup(n_batch=64, steps=100, K=20):
+def batched_setup(n_batch=64, steps=100, K=20, tuning=None):
     """The candidate batch, its targets and one Evaluation of all candidates
     in one context, autotuned (the autotuner's trial calls: forward, one
-    checkpoint interval long, on the context's internal copies)."""
+    checkpoint interval long, on the context's internal copies) unless a
+    tuning is given."""
     from paper_2602_01723_amd import batch as BT
     from paper_2602_01723_amd import binding as B
     from paper_2602_01723_amd import scenes
@@ -334,28 +406,39 @@ def batched_setup(n_batch=64, steps=100, K=20):
     tl = BT.per_particle(sc.extras["target_log_E"], sc.batch_offsets)
     tn = BT.per_particle(sc.extras["target_nu"], sc.batch_offsets)
     xt = BT.target_positions(sc, steps, tl, tn)
-    ev = BT.Evaluation(sc, steps, K, xt)
-    tun = B.mpm_autotune(ev.ctx, ev.p, K)
-    tuning = {k: tun[k] for k in ("chunk", "sort_every", "workgroups", "tile_cap")}
+    ev = BT.Evaluation(sc, steps, K, xt, tuning=tuning)
+    if tuning is None:
+        tun = B.mpm_autotune(ev.ctx, ev.p, K)
+        tuning = {k: tun[k] for k in ("chunk", "sort_every", "workgroups", "tile_cap")}
     log(f"  batched launch tuning: {tuning}")
     return sc, xt, ev, tuning
 
 
-def batched_graph_only(n_batch=64, steps=100, K=20, reps=3):
-    """The batched forward + adjoint graph alone (for counter runs of the
-    adjoint kernels): capture, then `reps` replays."""
+# launch tuning of the batched evaluation for counter runs (the autotuner's
+# choice for it: 1536-particle items, 512 workgroups, a re-sort every 32
+# substeps), so the profiled run carries no autotuning trials
+BATCH_TUNING = {"chunk": 1536, "sort_every": 32, "workgroups": 512, "tile_cap": 1331}
+
+
+def adjoint_counter_run(n_batch=64, steps=100, K=20, reps=2):
+    """The batched forward + adjoint for counter runs of the adjoint kernels:
+    a 256 MiB copy (the counters' calibration), the candidates with
+    BATCH_TUNING, then `reps` evaluations issued eagerly on the evaluation's
+    stream with a device synchronisation before and after each (no graph,
+    no waits between streams)."""
     import torch
-    sc, _, ev, tuning = batched_setup(n_batch, steps, K)
-    ev.capture()
-    ev.run_graph()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    copy_probe(reps=2)
+    sc, _, ev, tuning = batched_setup(n_batch, steps, K, tuning=dict(BATCH_TUNING))
+    times = []
     for _ in range(reps):
-        ev.run_graph()
+        ev.reset()
         torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / reps
-    log(f"  batched: {t * 1e3:.1f} ms per evaluation of {n_batch} candidates")
-    return {"particles": sc.n, "substeps": steps, "batched_ms": t * 1e3, "tuning": tuning}
+        t0 = time.perf_counter()
+        ev._record(ev.stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    log(f"  eager evaluation: {min(times) * 1e3:.1f} ms for {n_batch} candidates")
+    return {"particles": sc.n, "substeps": steps, "eager_ms": min(times) * 1e3, "tuning": tuning}
 
 
 def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
@@ -379,6 +462,24 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
     t_batched = (time.perf_counter() - t0) / reps
     gl_b, _ = ev.gradients()
     log(f"  batched: {t_batched * 1e3:.1f} ms per evaluation of {n_batch} candidates")
+    # the adjoint kernels' durations: one eager evaluation with HIP events
+    # around each launch (a graph replay cannot record them)
+    from paper_2602_01723_amd import binding as B
+    B.mpm_profile(ev.ctx, True)
+    B.mpm_profile_read(ev.ctx)
+    ev.run_eager()
+    torch.cuda.synchronize()
+    prof = B.mpm_profile_read(ev.ctx)
+    B.mpm_profile(ev.ctx, False)
+    adj = {}
+    for cls, nbytes in (("adjoint_g2p", ADJ_G2P_BYTES), ("adjoint_p2g", ADJ_P2G_BYTES)):
+        ms, cnt = prof[cls]
+        if cnt:
+            avg = ms / cnt * 1e-3
+            adj[cls] = dict(avg_launch_us=round(avg * 1e6, 1), launches=cnt, bytes_per_particle=nbytes,
+                            achieved_gbs=round(nbytes * sc.n / avg / 1e9, 1),
+                            frac=round(nbytes * sc.n / avg / 1e9 / HBM_PEAK_GBS, 4))
+    fwd_bwd_gbs = FWD_BWD_BYTES * sc.n * steps / t_batched / 1e9
     plain = BT.plain_evaluations(sc, steps, K, xt, tuning=tuning)
     plain[0].run_eager()
     torch.cuda.synchronize()
@@ -402,8 +503,97 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
         "batched_grads_per_s": n_batch / t_batched, "plain_grads_per_s": n_batch / t_plain,
         "speedup": t_plain / t_batched, "batched_ms": t_batched * 1e3, "plain_ms": t_plain * 1e3,
         "fwd_bwd_particle_substeps_per_s": sc.n * steps / t_batched,
+        "roofline_fwd_bwd": {"bound": "hbm", "bytes_per_particle_substep": FWD_BWD_BYTES,
+                             "achieved": round(fwd_bwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(fwd_bwd_gbs / HBM_PEAK_GBS, 4), "kernels": adj},
         "max_rel_diff_candidate_grad_logE": max(diffs), "median_rel_diff_candidate_grad_logE": float(np.median(diffs)),
     }
+
+
+def config_timings():
+    """The other workloads, each on a context of its own: the plain cube at
+    its stated count (20,480 particles, 32^3; 100 substeps through
+    mpm_step_n), the Gaussian-scene cloud (300,000 particles, 64^3; 1,000
+    substeps on the resident scene) and the differentiation workload
+    (200,000 particles, 64^3; 200 substeps taped every 20, the position-loss
+    cotangent and the backward: one gradient)."""
+    import numpy as np
+    import torch
+
+    from paper_2602_01723_amd import binding as B
+    from paper_2602_01723_amd import scenes
+    out = {}
+    sc = scenes.make_scene("cube_uniform")
+    ctx = B.init_from_scene(sc)
+    p = B.Particles.from_scene(sc)
+    B.mpm_step_n(ctx, p, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.mpm_step_n(ctx, p, 100)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["cube_20480"] = dict(particles=sc.n, substeps=100, seconds=round(t, 5), particle_substeps_per_s=sc.n * 100 / t,
+                             path="mpm_step_n(100)")
+    del ctx, p
+    sc = scenes.make_scene("gaussian_cloud")
+    ctx = B.init_from_scene(sc)
+    p = B.Particles.from_scene(sc)
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.mpm_advance(ctx, 1000)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["gaussian_cloud_300k"] = dict(particles=sc.n, substeps=1000, seconds=round(t, 4),
+                                      particle_substeps_per_s=sc.n * 1000 / t, path="mpm_load + mpm_advance(1000)")
+    del ctx, p
+    sc = scenes.make_scene("colliding_pair", E=(2e5, 5e4), nu=(0.25, 0.35))
+    steps, K, N = sc.n_substeps, sc.checkpoint_every, sc.n
+    ctx = B.init_from_scene(sc)
+    tgt = B.Particles.from_scene(sc)
+    B.mpm_step_n(ctx, tgt, steps)
+    x_target = tgt.x.clone()
+    logE = np.full(N, math.log(1e5), np.float32)
+    nu = np.full(N, 0.3, np.float32)
+    p = B.Particles.from_arrays(sc.x, sc.v, sc.C, sc.F, sc.mass, sc.vol0, logE, nu, sc.mat_id)
+    init = p.clone()
+    tape = torch.empty(B.mpm_tape_size(ctx, steps, K) // 4 + 64, device="cuda")
+    w = torch.full((N,), 1.0 / (3 * N), device="cuda")
+    g_x = torch.empty(3, N, device="cuda")
+    gl = torch.empty(N, device="cuda")
+    gn = torch.empty(N, device="cuda")
+
+    def grad():
+        for k in ("x", "v", "C", "F"):
+            getattr(p, k).copy_(getattr(init, k))
+        B.mpm_step_n(ctx, p, steps, tape=tape, checkpoint_every=K)
+        B.mpm_position_loss_grad(ctx, p.x, x_target, w, g_x)
+        B.mpm_backward(ctx, p, tape, steps, g_x=g_x, g_log_E=gl, g_nu=gn)
+
+    grad()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        grad()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    out["colliding_pair_200k"] = dict(particles=N, substeps=steps, checkpoint_every=K, seconds_per_gradient=round(t, 4),
+                                      grads_per_s=1.0 / t, fwd_bwd_particle_substeps_per_s=N * steps / t,
+                                      path="mpm_step_n with tape + mpm_position_loss_grad + mpm_backward")
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(sc, n_sub=2):
@@ -432,7 +622,8 @@ def cpu_baseline(sc, n_sub=2):
     dt = timed(sc, n_sub, cores)
     small = scenes.make_scene("large_scene", n_total=max(sc.n // 16, 1000))
     dt1 = timed(small, 1, 1)
-    return dict(value=sc.n * n_sub / dt, unit="particle-substeps/s", cores=cores, kind="oracle",
+    return dict(value=sc.n * n_sub / dt, unit="particle-substeps/s", cores=cores, kind="oracle", cpu=cpu_model(),
+                host_cpus=os.cpu_count(),
                 sample=f"{n_sub} substeps of the full {sc.n}-particle workload from its initial state "
                        f"({dt:.1f} s, float64 PyTorch CPU)",
                 one_core={"value": small.n / dt1, "cores": 1,
@@ -456,16 +647,22 @@ def main():
     ap.add_argument("--no-bgdo", action="store_true", help="skip the BGDO iteration timing")
     ap.add_argument("--no-models", action="store_true", help="skip the per-model fused-kernel timing")
     ap.add_argument("--no-mcis", action="store_true", help="skip the MCIS interior-fill timing")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the timings of the other workloads (cube, Gaussian cloud, differentiation)")
+    ap.add_argument("--no-atomics", action="store_true", help="skip the atomic-throughput probes")
     ap.add_argument("--no-step-n", action="store_true",
                     help="skip timing the same frames through mpm_step_n (caller-order I/O at every call)")
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched vs plain forward + adjoint and exit")
     ap.add_argument("--adjoint-counters", action="store_true",
-                    help="replay only the batched forward + adjoint graph (no plain leg) and exit: the run "
+                    help="run the batched forward + adjoint eagerly (no graph, no plain leg) and exit: the run "
                          "that counter passes over the adjoint kernels profile")
     ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_CSV",
                     help="per-dispatch counter means of the fused kernel from rocprofv3 --pmc runs, and exit")
+    ap.add_argument("--summarize-adjoint-counters", nargs="+", metavar="PMC_CSV",
+                    help="per-dispatch counter means of the adjoint kernels from rocprofv3 --pmc runs of "
+                         "--adjoint-counters, and exit (no GPU use)")
     ap.add_argument("--summarize-batched-trace", metavar="TRACE_CSV",
                     help="per-kernel time of one batched evaluation in a rocprofv3 trace, and exit (no GPU use)")
     ap.add_argument("--write-valu", metavar="P1_CSV",
@@ -475,6 +672,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_counters:
         print(json.dumps(summarize_counters(args.summarize_counters, n_particles=args.n_total), indent=1))
+        return
+    if args.summarize_adjoint_counters:
+        print(json.dumps(summarize_adjoint_counters(args.summarize_adjoint_counters), indent=1))
         return
     if args.summarize_batched_trace:
         print(summarize_batched_trace(args.summarize_batched_trace))
@@ -506,10 +706,14 @@ def main():
         print(json.dumps({"batched_fwd_bwd": batched_vs_plain()}), flush=True)
         return
     if args.adjoint_counters:
-        print(json.dumps({"batched_graph": batched_graph_only()}), flush=True)
+        print(json.dumps({"adjoint_counter_run": adjoint_counter_run()}), flush=True)
         return
     copy_gbs = copy_probe()
     log(f"  plain 256 MiB copy: {copy_gbs:.0f} GB/s (read + write)")
+    probes = None
+    if not args.no_atomics:
+        probes = atomic_probe()
+        log(f"  atomic probes: {probes}")
     log("generating workload ...")
     t = time.perf_counter()
     sc = scenes.make_scene("large_scene", n_total=args.n_total)
@@ -597,6 +801,18 @@ def main():
         roofline["valu_issue"] = dict(instructions_per_particle=ipp, achieved=issued / 1e12,
                                       peak=VALU_PEAK_LANE_INSTR / 1e12, unit="T lane-instructions/s",
                                       frac=issued / VALU_PEAK_LANE_INSTR)
+    # atomic throughput of the fused kernel: its LDS adds (108 per particle)
+    # over the launch, against the probes' rates on this device
+    if probes and fused_n:
+        lds_rate = LDS_ADDS_PER_PARTICLE * sc.n / fused_avg_s / 1e12
+        roofline["atomics"] = dict(
+            lds_add_u64_per_launch=LDS_ADDS_PER_PARTICLE * sc.n, lds_achieved=round(lds_rate, 4),
+            lds_peak_p2g_pattern=probes["lds_add_u64_p2g_pattern"],
+            lds_peak_consecutive=probes["lds_add_u64_consecutive"],
+            lds_frac_of_p2g_pattern=round(lds_rate / probes["lds_add_u64_p2g_pattern"], 4),
+            global_add_f32_peak_node_channels=probes["global_add_f32_node_channels"],
+            global_add_f32_peak_distinct=probes["global_add_f32_distinct"], unit="T lane-ops/s",
+            note="LDS adds averaged over the whole launch; the P2G scatter is about a third of it")
     breakdown = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]}
     log("  kernel time by class:", json.dumps(breakdown))
     log("  diagnostics:", diag)
@@ -626,6 +842,13 @@ def main():
         log("batched vs plain forward + adjoint ...")
         batched = batched_vs_plain()
         log(f"  {batched['batched_grads_per_s']:.2f} vs {batched['plain_grads_per_s']:.2f} candidate gradients/s")
+
+    configs = None
+    if not args.no_configs:
+        log("other workloads ...")
+        configs = config_timings()
+        log("  " + json.dumps(configs))
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -662,6 +885,7 @@ def main():
         "cpu_baseline": cpu,
         "step_n_caller_order": step_n,
         "batched_fwd_bwd": batched,
+        "other_workloads": configs,
         "bgdo": bgdo,
         "per_model_fused": models,
         "mcis": mcis,

@@ -357,7 +357,8 @@ int mpm_mcis_select_static(int32_t n_instances, const float* surface, const int6
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, by class: 0 fused G2P+P2G substep kernel, 1 P2G-only kernel,
  * 2 G2P-only kernel, 3 sort and permute, 4 grid clear, 5 gather from /
- * scatter to the caller's arrays.  enable = 0 stops recording. */
+ * scatter to the caller's arrays, 6 adjoint G2P kernel, 7 adjoint P2G
+ * kernel.  enable = 0 stops recording. */
 #define MPM_PROFILE_CLASSES 8
 int mpm_profile(mpm_ctx ctx, int32_t enable);
 

@@ -29,8 +29,8 @@ EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_workspace_size", "mpm_in
             "mpm_bgdo_apply", "mpm_mcis_workspace_size", "mpm_mcis_select", "mpm_mcis_select_static", "mpm_profile",
             "mpm_profile_read",
             "mpm_destroy")
-PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io", "unused",
-                   "other_fill")
+PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io",
+                   "adjoint_g2p", "adjoint_p2g")
 
 
 class MPMError(RuntimeError):

@@ -11,6 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfastmpm.so")
+PROBES = os.path.join(PKG, "libmpm_probes.so")
 
 ARCH = os.environ.get("FASTMPM_ARCH", "gfx950")
 
@@ -33,19 +34,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every HIP source of the library into libfastmpm.so; returns its path."""
-    src = os.path.join(CSRC, "fastmpm.hip")
-    tmp = LIB + ".tmp"
+def _compile(src: str, out: str, verbose: bool, extra=()) -> str:
+    tmp = out + ".tmp"
     cmd = [hipcc()] + HIPCC_FLAGS + list(extra) + ["-I", INCLUDE, "-I", CSRC, src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfastmpm.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every HIP source: the library (libfastmpm.so, whose path is
+    returned) and the measurement probes bench.py uses (libmpm_probes.so)."""
+    _compile(os.path.join(CSRC, "probes.hip"), PROBES, verbose)
+    return _compile(os.path.join(CSRC, "fastmpm.hip"), LIB, verbose, extra)
 
 
 if __name__ == "__main__":

@@ -1026,11 +1026,17 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
                                                    tl.gn, N);
         LAUNCH_CHECK(ctx, "k_adj_return_map");
       }
-      fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
+      {
+        ProfScope pa(ctx, s, 6);
+        fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
+      }
       LAUNCH_CHECK(ctx, "k_adj_g2p");
       rc = fill_u32(ctx, ctx->work_counter, 1, s);  // the item queue again, for k_adj_p2g
       if (rc) return rc;
-      fmpm::k_adj_p2g<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
+      {
+        ProfScope pa(ctx, s, 7);
+        fmpm::k_adj_p2g<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
+      }
       LAUNCH_CHECK(ctx, "k_adj_p2g");
     }
     // (5) back to caller order (slot j -> caller index pid[j]); the

@@ -101,6 +101,15 @@ __device__ __forceinline__ unsigned wave_sum_u(unsigned v) {
   return v;
 }
 
+// Raises the float maximum kept as bits in *slot (non-negative values
+// compare as unsigned integers).  The atomic is skipped when the value read
+// is already as large: one address taken by every wave would otherwise
+// serialise them.
+__device__ __forceinline__ void raise_max(unsigned* slot, float v) {
+  const unsigned b = __float_as_uint(v);
+  if (v > 0.0f && b > __atomic_load_n(slot, __ATOMIC_RELAXED)) atomicMax(slot, b);
+}
+
 // The CFL watch of one wave: adds its count of violations to diag[4] and
 // raises diag[5] (float bits, non-negative) to its largest |v|^2.
 __device__ __forceinline__ void cfl_flush(unsigned long long* diag, float v2max, unsigned count) {
@@ -108,7 +117,7 @@ __device__ __forceinline__ void cfl_flush(unsigned long long* diag, float v2max,
   const unsigned c = wave_sum_u(count);
   if ((threadIdx.x & 63) == 0) {
     if (c) atomicAdd(&diag[4], (unsigned long long)c);
-    if (m > 0.0f) atomicMax(reinterpret_cast<unsigned*>(&diag[5]), __float_as_uint(m));
+    raise_max(reinterpret_cast<unsigned*>(&diag[5]), m);
   }
 }
 
@@ -1213,8 +1222,7 @@ __global__ void k_params_planes(float4* prm, int* mat, int* pid, const float* ma
     c2 = (w > 0.0 && w < 3.0e38) ? (float)w : 0.0f;
   }
   c2 = wave_maxf(c2);
-  if (diag && (threadIdx.x & 63) == 0 && c2 > 0.0f)
-    atomicMax(reinterpret_cast<unsigned*>(&diag[6]), __float_as_uint(c2));
+  if (diag && (threadIdx.x & 63) == 0) raise_max(reinterpret_cast<unsigned*>(&diag[6]), c2);
 }
 
 __global__ void k_gather_misc(float4* prm_out, int* mat_out, int* pid_out, const float4* prm_in, const int* mat_in,
