@@ -28,6 +28,9 @@ What it computes, step by step, in float64 with plain PyTorch CPU ops:
   O10 MCIS interior filling: nearest-surface distance,        Sec. 4.1 (MCIS steps 1-5)
       Gaussian weight with floor, normalised probability,
       sampling without replacement by exponential keys
+  O11 candidate generation of the interior fill: uniform     Sec. 4.1 (candidate sampling in the
+      points in the box of each instance's hull, kept by the   hull's box, occupancy threshold)
+      six-ray parity occupancy of the hull mesh (NumPy)
 
 The adjoint is torch autograd through the same steps (``adjoint``), with
 SVD-free forms of the pieces whose SVD derivative is undefined at repeated
@@ -66,6 +69,7 @@ from __future__ import annotations
 import math
 from typing import Dict, List, Optional, Sequence
 
+import numpy as np
 import torch
 
 F64 = torch.float64
@@ -753,3 +757,136 @@ def mcis(cand, cand_off, surf, surf_off, u, n_sel, sigma=MCIS_SIGMA, eps=MCIS_EP
         sel.append(idx + c0)
         dist.append(d)
     return torch.cat(sel) if sel else torch.zeros(0, dtype=torch.int64), torch.cat(dist) if dist else None
+
+
+# ---------------------------------------------------------------------------
+# O11: instance-aware candidate generation (Sec. 4.1): candidates drawn
+# uniformly in the axis-aligned box B_k of each instance's convex hull H_k,
+# kept where the ray-cast occupancy of H_k exceeds a threshold (0.6)
+# ---------------------------------------------------------------------------
+#
+# The hull itself (Quickhull of the instance's points) is an input: a
+# triangle mesh per instance.  Readings (the paper names the steps only):
+#   * B_k = [min, max] of the hull's vertices per axis;
+#   * q = b_min + u (b_max - b_min), per axis, in float64 from the caller's
+#     uniform u in [0, 1], rounded to float32 (the particle precision);
+#   * occ(q; H_k) = the fraction of six rays from q, along +x, -x, +y, -y,
+#     +z and -z, that cross the mesh an odd number of times (the parity rule
+#     of ray casting); q is kept when occ > 0.6, i.e. on at least four rays;
+#   * the line through q along axis a crosses a triangle when q's projection
+#     (coordinates b, c: the next two axes cyclically) lies in the closed 2D
+#     box of the triangle's projection and the triangle's three 2D edge
+#     functions, with exact zeros resolved by simulation of simplicity
+#     (q moved by (e, e^2) in (b, c), e -> 0; Edelsbrunner & Muecke 1990),
+#     have one sign s.  The crossing lies at parameter t of the sign of
+#     s * (U A_a + V B_a + W C_a) (vertices relative to q, U, V, W the edge
+#     functions opposite A, B, C); t >= 0 counts for the + ray and t <= 0
+#     for the - ray.
+# Every edge function is evaluated as one product minus another, in float64
+# without contraction, so a shared edge gives its two triangles exactly
+# opposite values and a ray through it is counted once.
+# Invalid input (vertices outside [0, 1]^3 or not finite, triangle indices
+# outside the instance, u outside [0, 1]) raises ValueError.
+
+IPF_OCCUPANCY = 0.6
+
+
+def _ipf_sign_tie(e, p, q, b, c):
+    """Sign of the edge function e of the directed edge p -> q (float32
+    vertices, rows of [n, 3]), with zeros resolved by the perturbation of
+    the query point along (e, e^2) in the (b, c) plane: the first order term
+    is p_c - q_c, the second q_b - p_b."""
+    s = np.sign(e)
+    tie1 = np.sign(p[..., c].astype(np.float64) - q[..., c].astype(np.float64))
+    tie2 = np.sign(q[..., b].astype(np.float64) - p[..., b].astype(np.float64))
+    tie = np.where(tie1 != 0, tie1, tie2)
+    return np.where(s != 0, s, tie)
+
+
+def ipf_ray_votes(points, tri_vertices, chunk=64):
+    """For float32 query points [M, 3] and one instance's triangles as float32
+    vertex triples [T, 3, 3] (triangle, vertex, axis): the number of the six
+    axis rays from each point that cross the triangles an odd number of
+    times, [M] int.  Brute force over every triangle."""
+    P = np.asarray(points, np.float32)
+    TV = np.asarray(tri_vertices, np.float32)
+    M, T = P.shape[0], TV.shape[0]
+    votes = np.zeros(M, np.int64)
+    if T == 0 or M == 0:
+        return votes
+    v0, v1, v2 = TV[:, 0, :], TV[:, 1, :], TV[:, 2, :]
+    lo = TV.min(axis=1)
+    hi = TV.max(axis=1)
+    for s0 in range(0, M, chunk):
+        q = P[s0:s0 + chunk]
+        q64 = q.astype(np.float64)[:, None, :]
+        A = v0.astype(np.float64)[None] - q64  # [m, T, 3], vertices relative to q
+        Bv = v1.astype(np.float64)[None] - q64
+        Cv = v2.astype(np.float64)[None] - q64
+        for a in range(3):
+            b, c = (a + 1) % 3, (a + 2) % 3
+            in_box = ((q[:, None, b] >= lo[None, :, b]) & (q[:, None, b] <= hi[None, :, b]) &
+                      (q[:, None, c] >= lo[None, :, c]) & (q[:, None, c] <= hi[None, :, c]))
+            U = Bv[..., b] * Cv[..., c] - Bv[..., c] * Cv[..., b]
+            V = Cv[..., b] * A[..., c] - Cv[..., c] * A[..., b]
+            W = A[..., b] * Bv[..., c] - A[..., c] * Bv[..., b]
+            sU = _ipf_sign_tie(U, v1[None], v2[None], b, c)
+            sV = _ipf_sign_tie(V, v2[None], v0[None], b, c)
+            sW = _ipf_sign_tie(W, v0[None], v1[None], b, c)
+            hit = in_box & (sU != 0) & (sU == sV) & (sV == sW)
+            Tn = (U * A[..., a] + V * Bv[..., a]) + W * Cv[..., a]
+            st = sU * np.sign(Tn)
+            fwd = (hit & (st >= 0)).sum(axis=1)
+            bwd = (hit & (st <= 0)).sum(axis=1)
+            votes[s0:s0 + chunk] += (fwd % 2) + (bwd % 2)
+    return votes
+
+
+def ipf_box(hull_vertices):
+    """B_k: per-axis min and max of one instance's hull vertices [V, 3]."""
+    hv = np.asarray(hull_vertices, np.float32)
+    return hv.min(axis=0), hv.max(axis=0)
+
+
+def ipf_points(u, b_min, b_max):
+    """q = b_min + u (b_max - b_min) in float64, rounded to float32; u [R, 3]."""
+    lo = np.asarray(b_min, np.float32).astype(np.float64)
+    hi = np.asarray(b_max, np.float32).astype(np.float64)
+    return (lo + np.asarray(u, np.float64) * (hi - lo)).astype(np.float32)
+
+
+def ipf_candidates(hull_vertices, hull_vertex_offsets, hull_triangles, hull_triangle_offsets, u, raw_offsets,
+                   threshold=IPF_OCCUPANCY):
+    """All instances: hull_vertices [V, 3] float32, hull_triangles [T, 3]
+    vertex indices local to the instance, u [R, 3] uniforms; instance k owns
+    the rows [off[k], off[k+1]) of each.  Returns (kept candidates [M_in, 3]
+    float32, their raw indices [M_in] int64, ascending, the kept counts'
+    offsets [K+1] int64, the six-ray votes [R])."""
+    hv = np.asarray(hull_vertices, np.float32).reshape(-1, 3)
+    ht = np.asarray(hull_triangles, np.int64).reshape(-1, 3)
+    uu = np.asarray(u, np.float64).reshape(-1, 3)
+    K = len(raw_offsets) - 1
+    if not (np.all(np.isfinite(hv)) and np.all((hv >= 0) & (hv <= 1))):
+        raise ValueError("hull vertices must lie in [0, 1]^3")
+    if not np.all((uu >= 0) & (uu <= 1)):
+        raise ValueError("u must lie in [0, 1]")
+    votes = np.zeros(uu.shape[0], np.int64)
+    pts = np.zeros((uu.shape[0], 3), np.float32)
+    for k in range(K):
+        v0, v1 = int(hull_vertex_offsets[k]), int(hull_vertex_offsets[k + 1])
+        t0, t1 = int(hull_triangle_offsets[k]), int(hull_triangle_offsets[k + 1])
+        r0, r1 = int(raw_offsets[k]), int(raw_offsets[k + 1])
+        tri = ht[t0:t1]
+        if tri.size and (tri.min() < 0 or tri.max() >= v1 - v0):
+            raise ValueError(f"triangle index outside instance {k}")
+        if v1 == v0 or t1 == t0 or r1 == r0:
+            continue  # no hull: nothing is kept
+        lo, hi = ipf_box(hv[v0:v1])
+        q = ipf_points(uu[r0:r1], lo, hi)
+        pts[r0:r1] = q
+        votes[r0:r1] = ipf_ray_votes(q, hv[v0:v1][tri])
+    keep = votes / 6.0 > threshold
+    idx = np.nonzero(keep)[0].astype(np.int64)
+    counts = [int(keep[int(raw_offsets[k]):int(raw_offsets[k + 1])].sum()) for k in range(K)]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return pts[idx], idx, offs, votes

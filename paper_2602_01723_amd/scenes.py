@@ -450,3 +450,106 @@ def mcis_inputs(seed=7, n_shell=(2000, 3000, 1500), cand_per_shell=2.0, fill_fra
                 surface_offsets=np.array(so, np.int64), candidates=np.concatenate(cand).astype(np.float32),
                 candidate_offsets=np.array(co, np.int64), u=1.0 - rng.uniform(0.0, 1.0, M),
                 n_select=np.array(nsel, np.int64))
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the candidate generation (Sec. 4.1): per instance a closed
+# triangle mesh (the convex hull of its points) and raw uniforms
+# ---------------------------------------------------------------------------
+
+def _box_index(x, y, z):
+    return x + 2 * y + 4 * z
+
+
+def box_mesh(lo, hi, drop=()):
+    """Triangle mesh of the axis-aligned box [lo, hi]^3 (scalars or 3-vectors):
+    8 vertices (vertex x + 2y + 4z at the corner (x, y, z) in {lo, hi}), two
+    triangles per face split along the diagonal from the face's lowest
+    corner.  Faces named in ``drop`` ("-x", "+x", "-y", "+y", "-z", "+z") are
+    left out, which opens the mesh.  Returns (vertices [8, 3] float32,
+    triangles [T, 3] int32)."""
+    lo = np.broadcast_to(np.asarray(lo, np.float32), (3,))
+    hi = np.broadcast_to(np.asarray(hi, np.float32), (3,))
+    v = np.array([[(lo, hi)[(i >> a) & 1][a] for a in range(3)] for i in range(8)], np.float32)
+    quads = {}
+    for s, name in ((0, "-"), (1, "+")):
+        quads[name + "x"] = [_box_index(s, 0, 0), _box_index(s, 1, 0), _box_index(s, 1, 1), _box_index(s, 0, 1)]
+        quads[name + "y"] = [_box_index(0, s, 0), _box_index(0, s, 1), _box_index(1, s, 1), _box_index(1, s, 0)]
+        quads[name + "z"] = [_box_index(0, 0, s), _box_index(1, 0, s), _box_index(1, 1, s), _box_index(0, 1, s)]
+    tris = []
+    for name in ("-x", "+x", "-y", "+y", "-z", "+z"):
+        if name in drop:
+            continue
+        q = quads[name]
+        tris += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    return v, np.array(tris, np.int32).reshape(-1, 3)
+
+
+def merge_meshes(*meshes):
+    """One mesh of several (vertices, triangles) pairs (indices shifted)."""
+    vs, ts, n = [], [], 0
+    for v, t in meshes:
+        vs.append(np.asarray(v, np.float32))
+        ts.append(np.asarray(t, np.int64) + n)
+        n += len(v)
+    return np.concatenate(vs), np.concatenate(ts).astype(np.int32)
+
+
+def octahedron_mesh(centre, r):
+    """The octahedron with vertices centre +- r along each axis (8 triangles)."""
+    c = np.asarray(centre, np.float32)
+    v = np.array([c + s * r * e for e in np.eye(3, dtype=np.float32) for s in (-1, 1)], np.float32)
+    tris = [(ix, iy, iz) for ix in (0, 1) for iy in (2, 3) for iz in (4, 5)]
+    return v, np.array(tris, np.int32)
+
+
+def ellipsoid_hull(rng, n_shell, r_range=(0.06, 0.16)):
+    """Points on a random ellipsoid shell in the unit cube (float32) and
+    their convex hull's triangles (Quickhull via SciPy's Qhull, run on the
+    float32 values).  Returns (points [n, 3] float32, triangles [T, 3] int32,
+    hull volume)."""
+    from scipy.spatial import ConvexHull
+    axes = rng.uniform(r_range[0], r_range[1], 3)
+    rot = haar_rotation(rng)
+    half = np.sqrt(((rot * axes[None, :]) ** 2).sum(1))
+    centre = rng.uniform(half + 0.01, 1.0 - half - 0.01)
+    d = rng.standard_normal((n_shell, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts = (centre + (d * axes) @ rot.T).astype(np.float32)
+    hull = ConvexHull(pts.astype(np.float64))
+    return pts, hull.simplices.astype(np.int32), float(hull.volume)
+
+
+def ipf_inputs(seed=8, n_shell=(1500, 2500, 1000), raw_per_point=4.0, meshes=(), raw_per_mesh=2000,
+               r_range=(0.06, 0.16)):
+    """Inputs of the candidate generation for ellipsoid instances (shell
+    points and their hull) followed by the given extra meshes (each a
+    (vertices, triangles) pair, one instance each).  Instance k gets
+    raw_per_point x its points (ellipsoids) or raw_per_mesh (extra meshes)
+    raw candidates with three uniforms each.  Returns a dict of NumPy arrays:
+    hull_vertices [V, 3] float32, hull_vertex_offsets [K+1], hull_triangles
+    [T, 3] int32 (local to the instance), hull_triangle_offsets [K+1], u
+    [R, 3] float64 in [0, 1), raw_offsets [K+1], surface / surface_offsets
+    (the instance's points, for the selection that follows) and
+    hull_volume [K] (NaN for the extra meshes)."""
+    rng = np.random.default_rng(seed)
+    vs, ts, raws, vols = [], [], [], []
+    for ns in n_shell:
+        p, t, vol = ellipsoid_hull(rng, ns, r_range)
+        vs.append(p)
+        ts.append(t)
+        raws.append(int(raw_per_point * ns))
+        vols.append(vol)
+    for v, t in meshes:
+        vs.append(np.asarray(v, np.float32).reshape(-1, 3))
+        ts.append(np.asarray(t, np.int32).reshape(-1, 3))
+        raws.append(int(raw_per_mesh))
+        vols.append(math.nan)
+    off = lambda sizes: np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    vo = off([len(v) for v in vs])
+    R = int(sum(raws))
+    return dict(hull_vertices=np.concatenate(vs).astype(np.float32), hull_vertex_offsets=vo,
+                hull_triangles=np.concatenate(ts).astype(np.int32), hull_triangle_offsets=off([len(t) for t in ts]),
+                u=rng.uniform(0.0, 1.0, (R, 3)), raw_offsets=off(raws),
+                surface=np.concatenate(vs).astype(np.float32), surface_offsets=vo.copy(),
+                hull_volume=np.array(vols, np.float64))
