@@ -93,7 +93,7 @@ VALU_FILE = os.path.join(ROOT, "profiles", "fused_substep_large_scene_valu.json"
 VALU_COMMAND = ("cd /tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
                 "SQ_INSTS_LDS SQ_WAIT_INST_ANY SQ_INSTS_SALU --kernel-include-regex k_substep -f csv -d <out>/pmc_p1 "
                 "-o p1 -- python3 <repo>/bench.py --steps 1 --warmup 1 --substeps-per-step 10 --no-autotune "
-                "--no-step-n --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis --no-configs --no-atomics")
+                "--no-step-n --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis --no-ipf --no-configs --no-atomics")
 
 
 def write_valu(p1_csv, n_particles=2_000_000):
@@ -124,7 +124,7 @@ def measured_valu(n_particles):
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
                "--steps 1 --warmup 1 --substeps-per-step 10 --no-autotune --no-step-n --no-cpu-baseline --no-batched "
-               "--no-bgdo --no-models --no-mcis --no-configs --no-atomics")
+               "--no-bgdo --no-models --no-mcis --no-ipf --no-configs --no-atomics")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
@@ -259,6 +259,66 @@ def mcis_timing(reps=3):
             "oracle": {"candidates_per_s": c_n / t_cpu, "cores": torch.get_num_threads(),
                        "sample": f"{c_n} candidates against {s_n} surface points (brute force, {t_cpu:.1f} s)"},
             "paper_context": "IPF with MCIS 22 s per scene on an RTX A6000 (with DBSCAN and hulls; not comparable)"}
+
+
+def ipf_timing(reps=3):
+    """Candidate generation of the interior fill (Sec. 4.1) and the whole
+    fill on the GPU at the scale of the 2M workload: 12 ellipsoid instances
+    with 1M hull points (their Qhull meshes), 16 raw candidates per point
+    (16M), kept by the six-ray occupancy, then MCIS selects 1/8 of the kept
+    ones.  Wall times (both calls synchronise), best of `reps` after a
+    warm-up; the oracle on a bounded sample beside it."""
+    import numpy as np
+    import torch
+
+    from oracle import mpm_oracle as O
+    from paper_2602_01723_amd import binding as B
+    from paper_2602_01723_amd import scenes
+    rng = np.random.default_rng(11)
+    ns = np.exp(rng.uniform(math.log(2e4), math.log(2e5), 12))
+    ns = np.floor(ns * (1_000_000 / ns.sum())).astype(np.int64)
+    ns[0] += 1_000_000 - ns.sum()
+    t0 = time.perf_counter()
+    d = scenes.ipf_inputs(seed=13, n_shell=tuple(int(v) for v in ns), raw_per_point=16.0, r_range=(0.05, 0.12))
+    t_setup = time.perf_counter() - t0
+    planes = lambda a, dt: torch.as_tensor(np.ascontiguousarray(np.asarray(a, dt).reshape(-1, 3).T)).cuda()
+    hv, ht, u = planes(d["hull_vertices"], np.float32), planes(d["hull_triangles"], np.int32), planes(d["u"], np.float64)
+    surf = planes(d["surface"], np.float32)
+    args = (hv, d["hull_vertex_offsets"], ht, d["hull_triangle_offsets"], u, d["raw_offsets"])
+    cand, offs, _ = B.mpm_ipf_candidates(*args)
+    M = int(offs[-1])
+    u_sel = torch.rand(M, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    u_sel = 1.0 - u_sel
+    n_sel = [int(v) // 8 for v in np.diff(offs)]
+    B.mpm_mcis_select(surf, d["surface_offsets"], cand, offs, u_sel, n_sel)
+    best_ipf = best_fill = math.inf
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cand, offs, _ = B.mpm_ipf_candidates(*args)
+        t1 = time.perf_counter()
+        B.mpm_mcis_select(surf, d["surface_offsets"], cand, offs, u_sel, n_sel)
+        t2 = time.perf_counter()
+        best_ipf, best_fill = min(best_ipf, t1 - t0), min(best_fill, t2 - t0)
+    R = int(d["raw_offsets"][-1])
+    T = int(d["hull_triangle_offsets"][-1])
+    # oracle: 200 raw candidates of instance 0 against its whole hull
+    v0, v1 = d["hull_vertex_offsets"][:2]
+    t0_, t1_ = d["hull_triangle_offsets"][:2]
+    lo, hi = O.ipf_box(d["hull_vertices"][v0:v1])
+    q = O.ipf_points(d["u"][:200], lo, hi)
+    tri = d["hull_vertices"][v0:v1][d["hull_triangles"][t0_:t1_]]
+    t0 = time.perf_counter()
+    O.ipf_ray_votes(q, tri)
+    t_cpu = time.perf_counter() - t0
+    return {"workload": f"12 ellipsoid instances, 1,000,000 hull points ({T} Qhull triangles), {R} raw "
+                        f"candidates, {M} kept (occupancy > 0.6), {sum(n_sel)} drawn by MCIS",
+            "ipf_seconds": best_ipf, "raw_candidates_per_s": R / best_ipf,
+            "fill_seconds": best_fill, "kept": M,
+            "host_setup_seconds": round(t_setup, 2),
+            "oracle": {"raw_candidates_per_s": 200 / t_cpu, "cores": torch.get_num_threads(),
+                       "sample": f"200 raw candidates against instance 0's {t1_ - t0_} triangles "
+                                 f"(brute force, {t_cpu:.1f} s)"}}
 
 
 def summarize_adjoint_counters(csv_paths, n_particles=None) -> dict:
@@ -653,6 +713,8 @@ def main():
     ap.add_argument("--no-step-n", action="store_true",
                     help="skip timing the same frames through mpm_step_n (caller-order I/O at every call)")
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
+    ap.add_argument("--no-ipf", action="store_true", help="skip the candidate-generation timing")
+    ap.add_argument("--ipf-only", action="store_true", help="time only the candidate generation and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched vs plain forward + adjoint and exit")
     ap.add_argument("--adjoint-counters", action="store_true",
@@ -701,6 +763,9 @@ def main():
     torch.cuda.set_device(0)
     if args.mcis_only:
         print(json.dumps({"mcis": mcis_timing()}), flush=True)
+        return
+    if args.ipf_only:
+        print(json.dumps({"ipf": ipf_timing()}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched_fwd_bwd": batched_vs_plain()}), flush=True)
@@ -837,6 +902,13 @@ def main():
         mcis = mcis_timing()
         log(f"  {mcis['seconds'] * 1e3:.1f} ms for 8M candidates")
         torch.cuda.empty_cache()
+    ipf = None
+    if not args.no_ipf:
+        log("candidate generation + interior fill ...")
+        ipf = ipf_timing()
+        log(f"  {ipf['ipf_seconds'] * 1e3:.1f} ms for {ipf['raw_candidates_per_s'] * ipf['ipf_seconds']:.0f} raw "
+            f"candidates, fill {ipf['fill_seconds'] * 1e3:.1f} ms")
+        torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
         log("batched vs plain forward + adjoint ...")
@@ -889,6 +961,7 @@ def main():
         "bgdo": bgdo,
         "per_model_fused": models,
         "mcis": mcis,
+        "ipf": ipf,
         "device_memory_gb": round((free0 - free1) / 1e9, 3),
         "paper_context": {
             "figure": "about 1 minute and 7 GB per scene for the whole pipeline (IPF 22 s, BGDO forward "

@@ -306,6 +306,49 @@ int mpm_bgdo_accumulate(mpm_ctx ctx, const mpm_particles* key, const float* F_ne
 /* BGDO update: log_E[p] -= g_total[p] / n_keys (n_keys >= 1). */
 int mpm_bgdo_apply(mpm_ctx ctx, float* log_E, const float* g_total, int32_t n_keys, void* stream);
 
+/* Candidate generation of the interior fill (Sec. 4.1, the candidate points
+ * of each instance drawn uniformly in the axis-aligned box of its convex hull
+ * and kept where the hull's ray-cast occupancy exceeds a threshold, 0.6 in
+ * the paper).  Context-free.  n_instances = K instances; instance k owns
+ *   hull vertices   hull_vertices[3][V]     columns [hull_vertex_offsets[k], .. [k+1])
+ *   hull triangles  hull_triangles[3][T]    int32 vertex indices local to the
+ *                                           instance's vertex range, columns
+ *                                           [hull_triangle_offsets[k], .. [k+1])
+ *   raw candidates  u[3][R] (float64)       columns [raw_offsets[k], .. [k+1])
+ * (hull_vertices, hull_triangles, u, candidates_out, source_out: device; the
+ * three offset arrays and candidate_offsets_out: host, int64, K+1 entries,
+ * offsets starting at 0).  The mesh is the caller's hull of the instance's
+ * points (the paper: Quickhull); its vertices must lie in [0, 1]^3.  For
+ * raw candidate j of instance k:
+ *   B_k = per-axis [b_min, b_max] over the vertices the triangles use
+ *   q_j = b_min + u_j (b_max - b_min), in float64, rounded to float32
+ *   occ = the fraction of the six rays from q_j along +x, -x, +y, -y, +z, -z
+ *         that cross the mesh an odd number of times (crossings tested in
+ *         float64 without contraction, exact zeros of the 2D edge functions
+ *         resolved by simulation of simplicity, so a ray through a shared
+ *         edge or vertex crosses exactly one triangle of a closed mesh);
+ * and q_j is kept when occ > occupancy_threshold (in [0, 1]).  An instance
+ * without triangles keeps nothing.  The kept candidates are written in raw
+ * order, instance by instance, to candidates_out as [3][M_in] planes of
+ * stride M_in = candidate_offsets_out[K] (room for 3 R floats), with
+ * candidate_offsets_out[k] the first kept candidate of instance k: the
+ * layout and offsets mpm_mcis_select takes.  source_out (optional, may be
+ * NULL; room for R entries) receives each kept candidate's raw index j.
+ * workspace: device memory of the size mpm_ipf_workspace_size gives,
+ * overwritten.  Runs on `stream` and synchronises it before returning.
+ * MPM_EINVAL for bad sizes or offsets, a threshold outside [0, 1], a
+ * missing workspace or output, or (found on the device) triangle indices
+ * outside their instance, vertices outside [0, 1]^3 or u outside [0, 1];
+ * MPM_EDEVICE for a HIP failure.  Limits: K <= 2^20, T <= 2^27,
+ * V, R < 2^31. */
+int mpm_ipf_workspace_size(int32_t n_instances, int64_t n_hull_vertices, int64_t n_hull_triangles, int64_t n_raw,
+                           size_t* bytes);
+int mpm_ipf_candidates(int32_t n_instances, const float* hull_vertices, const int64_t* hull_vertex_offsets,
+                       const int32_t* hull_triangles, const int64_t* hull_triangle_offsets, const double* u,
+                       const int64_t* raw_offsets, double occupancy_threshold, void* workspace,
+                       size_t workspace_bytes, float* candidates_out, int64_t* source_out,
+                       int64_t* candidate_offsets_out, void* stream);
+
 /* Interior filling by instance-aware Monte Carlo importance sampling (Sec. 4.1,
  * MCIS steps 1-5).  Context-free.  n_instances = K instances; instance k owns
  *   surface points     surface[3][S]    columns [surface_offsets[k], surface_offsets[k+1])

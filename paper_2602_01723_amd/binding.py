@@ -26,7 +26,7 @@ EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_workspace_size", "mpm_in
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
             "mpm_set_tuning", "mpm_get_tuning", "mpm_autotune", "mpm_graph_begin", "mpm_graph_end",
             "mpm_graph_launch", "mpm_graph_destroy", "mpm_position_loss_grad", "mpm_bgdo_accumulate",
-            "mpm_bgdo_apply", "mpm_mcis_workspace_size", "mpm_mcis_select", "mpm_mcis_select_static", "mpm_profile",
+            "mpm_bgdo_apply", "mpm_ipf_workspace_size", "mpm_ipf_candidates", "mpm_mcis_workspace_size", "mpm_mcis_select", "mpm_mcis_select_static", "mpm_profile",
             "mpm_profile_read",
             "mpm_destroy")
 PROFILE_CLASSES = ("fused_substep", "p2g_only", "g2p_only", "sort_permute", "grid_clear", "caller_io",
@@ -113,6 +113,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_graph_launch": (ctypes.c_int, [vp, vp]),
         "mpm_bgdo_accumulate": (ctypes.c_int, [vp, ctypes.POINTER(mpm_particles), vp, ctypes.c_float, vp, vp, vp, vp]),
         "mpm_bgdo_apply": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+        "mpm_ipf_workspace_size": (ctypes.c_int, [i32, i64, i64, i64, ctypes.POINTER(sz)]),
+        "mpm_ipf_candidates": (ctypes.c_int, [i32, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64), vp,
+                                              ctypes.POINTER(i64), ctypes.c_double, vp, sz, vp, vp,
+                                              ctypes.POINTER(i64), vp]),
         "mpm_mcis_workspace_size": (ctypes.c_int, [i32, i64, i64, ctypes.c_double, ctypes.c_double,
                                                    ctypes.POINTER(sz)]),
         "mpm_mcis_select": (ctypes.c_int, [i32, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64), vp,
@@ -419,6 +423,40 @@ def mpm_bgdo_accumulate(ctx: Context, key: "Particles", F_next, delta_target, g_
 def mpm_bgdo_apply(ctx: Context, log_E, g_total, n_keys, stream=None):
     rc = load().mpm_bgdo_apply(ctx.handle, _ptr(log_E), _ptr(g_total), int(n_keys), _stream(stream))
     _check(ctx, rc, "mpm_bgdo_apply")
+
+
+def mpm_ipf_candidates(hull_vertices, hull_vertex_offsets, hull_triangles, hull_triangle_offsets, u, raw_offsets,
+                       threshold=0.6, want_source=False, stream=None):
+    """Candidate generation of the interior fill (see include/fastmpm.h).
+    hull_vertices [3, V] float32, hull_triangles [3, T] int32 and u [3, R]
+    float64 device tensors; offsets as integer sequences.  Returns (kept
+    candidates [3, M_in] float32 device tensor, their offsets as a list of
+    K+1 ints, and their raw indices [M_in] int64 or None)."""
+    import torch
+    lib = load()
+    K = len(raw_offsets) - 1
+    hvo = (ctypes.c_int64 * (K + 1))(*[int(v) for v in hull_vertex_offsets])
+    hto = (ctypes.c_int64 * (K + 1))(*[int(v) for v in hull_triangle_offsets])
+    ro = (ctypes.c_int64 * (K + 1))(*[int(v) for v in raw_offsets])
+    R = int(ro[K])
+    nbytes = ctypes.c_size_t()
+    rc = lib.mpm_ipf_workspace_size(K, int(hvo[K]), int(hto[K]), R, ctypes.byref(nbytes))
+    if rc:
+        _check(None, rc, "mpm_ipf_workspace_size")
+    dev = u.device if hasattr(u, "device") else "cuda"
+    ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(max(3 * R, 1), dtype=torch.float32, device=dev)
+    src = torch.empty(max(R, 1), dtype=torch.int64, device=dev) if want_source else None
+    co = (ctypes.c_int64 * (K + 1))()
+    rc = lib.mpm_ipf_candidates(K, _ptr(hull_vertices) if int(hvo[K]) else None, hvo,
+                                _ptr(hull_triangles) if int(hto[K]) else None, hto, _ptr(u) if R else None, ro,
+                                float(threshold), _ptr(ws), int(nbytes.value), _ptr(out), _ptr(src), co,
+                                _stream(stream))
+    if rc:
+        _check(None, rc, "mpm_ipf_candidates")
+    offs = [int(v) for v in co]
+    m = offs[K]
+    return out[:3 * m].view(3, m), offs, (src[:m] if src is not None else None)
 
 
 def mpm_mcis_select(surface, surface_offsets, candidates, candidate_offsets, u, n_select, sigma=0.02, eps=1e-6,

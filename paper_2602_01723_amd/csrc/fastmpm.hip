@@ -21,6 +21,7 @@
 #include "mpm_adjoint.hpp"
 #include "mpm_kernels.hpp"
 #include "mcis_kernels.hpp"
+#include "ipf_kernels.hpp"
 
 using fmpm::kBlock;
 
@@ -1582,6 +1583,201 @@ int mpm_mcis_select(int32_t n_instances, const float* surface, const int64_t* su
   if (!workspace || workspace_bytes < L.total) return MPM_EINVAL;
   return mcis_run(K, surface, surface_offsets, candidates, candidate_offsets, u, sigma, eps, L, workspace,
                   out_off.data(), prefix.data(), rank.data(), out_index, d_out, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Candidate generation for the interior fill (context-free; the caller
+// supplies the workspace)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct IpfLayout {
+  int64_t cells = 0, refs = 0;  // capacities
+  size_t ro = 0, hv_off = 0, ht_off = 0, box = 0, grid = 0, tri = 0, count = 0, cursor = 0, refs_at = 0,
+         per_grid = 0, bsum = 0, flag = 0, offsets = 0, bad = 0, total = 0;
+};
+
+constexpr int kIpfMaxSide = 1024;  // cells per side of a triangle grid
+
+// Cells per side of instance grids with T_k triangles: the smallest g with
+// 2 g^2 >= T_k (at most kIpfMaxSide), so g^2 <= T_k + 2.
+int ipf_side(int64_t tk) {
+  int64_t g = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt(0.5 * (double)tk)));
+  while (g > 1 && 2 * (g - 1) * (g - 1) >= tk) --g;
+  while (2 * g * g < tk) ++g;
+  return (int)std::min<int64_t>(g, kIpfMaxSide);
+}
+
+// References a grid may hold before its side is halved.
+int64_t ipf_ref_budget(int64_t tk) { return 8 * tk + 64; }
+
+int ipf_layout(int32_t K, int64_t V, int64_t T, int64_t R, IpfLayout& L) {
+  if (K < 1 || K > (1 << 20) || V < 0 || T < 0 || R < 0 || V >= ((int64_t)1 << 31) || T > ((int64_t)1 << 27) ||
+      R >= ((int64_t)1 << 31))
+    return MPM_EINVAL;
+  L.cells = 3 * (T + 2 * (int64_t)K);        // sum over grids of g^2 <= T_k + 2
+  L.refs = 24 * T + 192 * (int64_t)K;        // sum over grids of the budget
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const int64_t nb = (std::max(L.cells, R) + 1 + fmpm::kScanTile - 1) / fmpm::kScanTile;
+  L.ro = take(8 * (size_t)(K + 1));
+  L.hv_off = take(8 * (size_t)(K + 1));
+  L.ht_off = take(8 * (size_t)(K + 1));
+  L.box = take(4 * 6 * (size_t)K);
+  L.grid = take(sizeof(fmpm::IpfGrid) * 3 * (size_t)K);
+  L.tri = take(sizeof(fmpm::IpfTri) * (size_t)std::max<int64_t>(T, 1));
+  L.count = take(4 * (size_t)(L.cells + 1));
+  L.cursor = take(4 * (size_t)L.cells);
+  L.refs_at = take(4 * (size_t)L.refs);
+  L.per_grid = take(8 * 3 * (size_t)K);
+  L.bsum = take(4 * (size_t)std::max<int64_t>(nb, 1));
+  L.flag = take(4 * (size_t)(R + 1));
+  L.offsets = take(4 * (size_t)(K + 1));
+  L.bad = take(8);
+  L.total = off;
+  return MPM_OK;
+}
+
+bool ipf_offsets_ok(const int64_t* off, int K, int64_t total) {
+  if (off[0] != 0 || off[K] != total) return false;
+  for (int k = 0; k < K; ++k)
+    if (off[k + 1] < off[k]) return false;
+  return true;
+}
+
+// u32 fill on the device (the kernels' counters and flags start at zero)
+int ipf_fill(void* p, int64_t count, uint32_t v, hipStream_t s) {
+  if (count <= 0) return MPM_OK;
+  const int64_t n4 = std::max<int64_t>(count >> 2, 4);
+  fmpm::k_fill_u32<<<blocks_for(n4, 256), 256, 0, s>>>((uint32_t*)p, v, count, nullptr);
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EDEVICE;
+}
+
+}  // namespace
+
+int mpm_ipf_workspace_size(int32_t n_instances, int64_t n_hull_vertices, int64_t n_hull_triangles, int64_t n_raw,
+                           size_t* bytes) {
+  if (!bytes) return MPM_EINVAL;
+  IpfLayout L;
+  const int rc = ipf_layout(n_instances, n_hull_vertices, n_hull_triangles, n_raw, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return MPM_OK;
+}
+
+int mpm_ipf_candidates(int32_t n_instances, const float* hull_vertices, const int64_t* hull_vertex_offsets,
+                       const int32_t* hull_triangles, const int64_t* hull_triangle_offsets, const double* u,
+                       const int64_t* raw_offsets, double occupancy_threshold, void* workspace,
+                       size_t workspace_bytes, float* candidates_out, int64_t* source_out,
+                       int64_t* candidate_offsets_out, void* stream) {
+  const int K = n_instances;
+  if (K < 1 || !hull_vertex_offsets || !hull_triangle_offsets || !raw_offsets || !candidate_offsets_out)
+    return MPM_EINVAL;
+  const int64_t V = hull_vertex_offsets[K], T = hull_triangle_offsets[K], R = raw_offsets[K];
+  IpfLayout L;
+  int rc = ipf_layout(K, V, T, R, L);
+  if (rc) return rc;
+  if (!ipf_offsets_ok(hull_vertex_offsets, K, V) || !ipf_offsets_ok(hull_triangle_offsets, K, T) ||
+      !ipf_offsets_ok(raw_offsets, K, R))
+    return MPM_EINVAL;
+  if (!(occupancy_threshold >= 0.0 && occupancy_threshold <= 1.0)) return MPM_EINVAL;
+  for (int k = 0; k <= K; ++k) candidate_offsets_out[k] = 0;
+  if (R == 0 || T == 0) return MPM_OK;  // no candidates, or no hull: nothing is kept
+  if (!hull_vertices || !hull_triangles || !u || !candidates_out) return MPM_EINVAL;
+  if (!workspace || workspace_bytes < L.total) return MPM_EINVAL;
+  const hipStream_t s = (hipStream_t)stream;
+  char* w = static_cast<char*>(workspace);
+  auto at = [&](size_t o) { return static_cast<void*>(w + o); };
+  int64_t* d_ro = (int64_t*)at(L.ro);
+  int64_t* d_hv_off = (int64_t*)at(L.hv_off);
+  int64_t* d_ht_off = (int64_t*)at(L.ht_off);
+  uint32_t* d_box = (uint32_t*)at(L.box);
+  fmpm::IpfGrid* d_grid = (fmpm::IpfGrid*)at(L.grid);
+  fmpm::IpfTri* d_tri = (fmpm::IpfTri*)at(L.tri);
+  uint32_t* d_count = (uint32_t*)at(L.count);
+  uint32_t* d_cursor = (uint32_t*)at(L.cursor);
+  uint32_t* d_refs = (uint32_t*)at(L.refs_at);
+  unsigned long long* d_per_grid = (unsigned long long*)at(L.per_grid);
+  uint32_t* d_bsum = (uint32_t*)at(L.bsum);
+  uint32_t* d_flag = (uint32_t*)at(L.flag);
+  uint32_t* d_offsets = (uint32_t*)at(L.offsets);
+  unsigned long long* d_bad = (unsigned long long*)at(L.bad);
+
+  MCIS_TRY(hipMemcpyAsync(d_ro, raw_offsets, 8 * (size_t)(K + 1), hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_hv_off, hull_vertex_offsets, 8 * (size_t)(K + 1), hipMemcpyHostToDevice, s));
+  MCIS_TRY(hipMemcpyAsync(d_ht_off, hull_triangle_offsets, 8 * (size_t)(K + 1), hipMemcpyHostToDevice, s));
+  // boxes: min at +inf, max at 0 (as float bits)
+  fmpm::k_ipf_box_init<<<blocks_for(6 * (int64_t)K, 256), 256, 0, s>>>(d_box, K);
+  MCIS_TRY(hipGetLastError());
+  if ((rc = ipf_fill(d_bad, 2, 0u, s))) return rc;
+  fmpm::k_ipf_tris<<<blocks_for(T, 256), 256, 0, s>>>(hull_vertices, V, hull_triangles, T, d_hv_off, d_ht_off, K,
+                                                      d_tri, d_box, d_bad);
+  MCIS_TRY(hipGetLastError());
+  // triangle grids: halve the side of any grid whose references exceed its
+  // budget, until every grid fits (a side of 1 always does)
+  std::vector<int> side(3 * (size_t)K);
+  for (int k = 0; k < K; ++k)
+    side[3 * k] = side[3 * k + 1] = side[3 * k + 2] =
+        ipf_side(hull_triangle_offsets[k + 1] - hull_triangle_offsets[k]);
+  std::vector<fmpm::IpfGrid> grid(3 * (size_t)K);
+  std::vector<unsigned long long> per_grid(3 * (size_t)K);
+  int64_t cells = 0;
+  for (;;) {
+    cells = 0;
+    for (int i = 0; i < 3 * K; ++i) {
+      grid[i].g = side[i];
+      grid[i].base = (uint32_t)cells;
+      cells += (int64_t)side[i] * side[i];
+    }
+    MCIS_TRY(hipMemcpyAsync(d_grid, grid.data(), sizeof(fmpm::IpfGrid) * 3 * (size_t)K, hipMemcpyHostToDevice, s));
+    if ((rc = ipf_fill(d_count, cells + 1, 0u, s)) || (rc = ipf_fill(d_per_grid, 6 * (int64_t)K, 0u, s))) return rc;
+    fmpm::k_ipf_bin<false><<<blocks_for(3 * T, 256), 256, 0, s>>>(d_tri, T, d_ht_off, K, d_box, d_grid, d_count,
+                                                                   d_per_grid, nullptr, nullptr, nullptr);
+    MCIS_TRY(hipGetLastError());
+    MCIS_TRY(hipMemcpyAsync(per_grid.data(), d_per_grid, 8 * 3 * (size_t)K, hipMemcpyDeviceToHost, s));
+    MCIS_TRY(hipStreamSynchronize(s));
+    bool fits = true;
+    for (int i = 0; i < 3 * K; ++i) {
+      const int64_t tk = hull_triangle_offsets[i / 3 + 1] - hull_triangle_offsets[i / 3];
+      if ((int64_t)per_grid[i] > ipf_ref_budget(tk) && side[i] > 1) {
+        side[i] = std::max(1, side[i] / 2);
+        fits = false;
+      }
+    }
+    if (fits) break;
+  }
+  if ((rc = mcis_scan(d_count, d_bsum, cells + 1, s))) return rc;
+  if ((rc = ipf_fill(d_cursor, cells, 0u, s))) return rc;
+  fmpm::k_ipf_bin<true><<<blocks_for(3 * T, 256), 256, 0, s>>>(d_tri, T, d_ht_off, K, d_box, d_grid, nullptr,
+                                                                nullptr, d_count, d_cursor, d_refs);
+  MCIS_TRY(hipGetLastError());
+  // occupancy of every raw candidate, then the kept ones in raw order
+  if ((rc = ipf_fill(d_flag + R, 1, 0u, s))) return rc;
+  fmpm::k_ipf_occupancy<<<blocks_for(R, 256), 256, 0, s>>>(u, R, d_ro, K, d_box, d_grid, d_count, d_refs, d_tri,
+                                                           occupancy_threshold, d_flag, d_bad);
+  MCIS_TRY(hipGetLastError());
+  if ((rc = mcis_scan(d_flag, d_bsum, R + 1, s))) return rc;
+  fmpm::k_ipf_offsets<<<blocks_for(K + 1, 64), 64, 0, s>>>(d_flag, d_ro, K, d_offsets);
+  MCIS_TRY(hipGetLastError());
+  std::vector<uint32_t> offs(K + 1);
+  unsigned long long bad = 0;
+  MCIS_TRY(hipMemcpyAsync(offs.data(), d_offsets, 4 * (size_t)(K + 1), hipMemcpyDeviceToHost, s));
+  MCIS_TRY(hipMemcpyAsync(&bad, d_bad, 8, hipMemcpyDeviceToHost, s));
+  MCIS_TRY(hipStreamSynchronize(s));
+  if (bad) return MPM_EINVAL;
+  const int64_t M_in = offs[K];
+  if (M_in > 0) {
+    fmpm::k_ipf_write<<<blocks_for(R, 256), 256, 0, s>>>(u, R, d_ro, K, d_box, d_flag, M_in, candidates_out,
+                                                         source_out);
+    MCIS_TRY(hipGetLastError());
+    MCIS_TRY(hipStreamSynchronize(s));
+  }
+  for (int k = 0; k <= K; ++k) candidate_offsets_out[k] = offs[k];
+  return MPM_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -119,3 +119,36 @@ def test_null_arguments(lib):
     assert lib.mpm_destroy(None) == B.MPM_EINVAL
     assert lib.mpm_get_diagnostics(None, None) == B.MPM_EINVAL
     assert lib.mpm_last_error(None) == b"NULL context"
+
+
+def test_ipf_workspace_size_and_host_checks(lib):
+    """Candidate generation: sizes and offsets are checked on the host;
+    no raw candidates or no triangles return at once with zero offsets."""
+    out = ctypes.c_size_t()
+    assert lib.mpm_ipf_workspace_size(2, 100, 200, 1000, ctypes.byref(out)) == B.MPM_OK and out.value > 0
+    small = out.value
+    assert lib.mpm_ipf_workspace_size(2, 100, 2000, 100000, ctypes.byref(out)) == B.MPM_OK
+    assert out.value > small + 100000 * 4 + 1800 * (48 + 24 * 4)
+    for args in ((0, 1, 1, 1), (2, -1, 1, 1), (2, 1, 1 << 28, 1), (2, 1, 1, 1 << 31)):
+        assert lib.mpm_ipf_workspace_size(*args, ctypes.byref(out)) == B.MPM_EINVAL
+    assert lib.mpm_ipf_workspace_size(1, 1, 1, 1, None) == B.MPM_EINVAL
+    I64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    co = (ctypes.c_int64 * 3)(7, 7, 7)
+    # no raw candidates: OK, offsets zero, nothing touched
+    assert lib.mpm_ipf_candidates(2, None, I64(0, 3, 6), None, I64(0, 1, 2), None, I64(0, 0, 0), 0.6, None, 0,
+                                  None, None, co, None) == B.MPM_OK
+    assert list(co) == [0, 0, 0]
+    # no triangles
+    co = (ctypes.c_int64 * 3)(7, 7, 7)
+    assert lib.mpm_ipf_candidates(2, None, I64(0, 3, 6), None, I64(0, 0, 0), None, I64(0, 5, 9), 0.6, None, 0,
+                                  None, None, co, None) == B.MPM_OK
+    assert list(co) == [0, 0, 0]
+    # bad offsets, threshold, missing buffers
+    bad = [(I64(1, 3, 6), I64(0, 1, 2), I64(0, 5, 9), 0.6), (I64(0, 3, 2), I64(0, 1, 2), I64(0, 5, 9), 0.6),
+           (I64(0, 3, 6), I64(0, 2, 1), I64(0, 5, 9), 0.6), (I64(0, 3, 6), I64(0, 1, 2), I64(0, 5, 9), 1.5),
+           (I64(0, 3, 6), I64(0, 1, 2), I64(0, 5, 9), float("nan")), (I64(0, 3, 6), I64(0, 1, 2), I64(0, 5, 9), 0.6)]
+    for hv, ht, ro, thr in bad:
+        assert lib.mpm_ipf_candidates(2, None, hv, None, ht, None, ro, thr, None, 0, None, None, co, None) == \
+            B.MPM_EINVAL
+    assert lib.mpm_ipf_candidates(2, None, I64(0, 3, 6), None, I64(0, 1, 2), None, I64(0, 5, 9), 0.6, None, 0,
+                                  None, None, None, None) == B.MPM_EINVAL
