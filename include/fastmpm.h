@@ -339,8 +339,8 @@ int mpm_bgdo_apply(mpm_ctx ctx, float* log_E, const float* g_total, int32_t n_ke
  * MPM_EINVAL for bad sizes or offsets, a threshold outside [0, 1], a
  * missing workspace or output, or (found on the device) triangle indices
  * outside their instance, vertices outside [0, 1]^3 or u outside [0, 1];
- * MPM_EDEVICE for a HIP failure.  Limits: K <= 2^20, T <= 2^27,
- * V, R < 2^31. */
+ * MPM_EDEVICE for a HIP failure.  Limits: K <= 2^20, T <= 2^27, V < 2^31,
+ * R < 2^30. */
 int mpm_ipf_workspace_size(int32_t n_instances, int64_t n_hull_vertices, int64_t n_hull_triangles, int64_t n_raw,
                            size_t* bytes);
 int mpm_ipf_candidates(int32_t n_instances, const float* hull_vertices, const int64_t* hull_vertex_offsets,

@@ -843,7 +843,8 @@ def ipf_ray_votes(points, tri_vertices, chunk=64):
 
 
 def ipf_box(hull_vertices):
-    """B_k: per-axis min and max of one instance's hull vertices [V, 3]."""
+    """B_k: per-axis min and max of the hull's vertices [V, 3] (the ones its
+    triangles use)."""
     hv = np.asarray(hull_vertices, np.float32)
     return hv.min(axis=0), hv.max(axis=0)
 
@@ -881,7 +882,7 @@ def ipf_candidates(hull_vertices, hull_vertex_offsets, hull_triangles, hull_tria
             raise ValueError(f"triangle index outside instance {k}")
         if v1 == v0 or t1 == t0 or r1 == r0:
             continue  # no hull: nothing is kept
-        lo, hi = ipf_box(hv[v0:v1])
+        lo, hi = ipf_box(hv[v0:v1][np.unique(tri)])  # the hull's box: the vertices its triangles use
         q = ipf_points(uu[r0:r1], lo, hi)
         pts[r0:r1] = q
         votes[r0:r1] = ipf_ray_votes(q, hv[v0:v1][tri])

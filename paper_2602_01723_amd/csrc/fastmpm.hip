@@ -1594,7 +1594,8 @@ namespace {
 struct IpfLayout {
   int64_t cells = 0, refs = 0;  // capacities
   size_t ro = 0, hv_off = 0, ht_off = 0, box = 0, grid = 0, tri = 0, count = 0, cursor = 0, refs_at = 0,
-         per_grid = 0, bsum = 0, flag = 0, offsets = 0, bad = 0, total = 0;
+         per_grid = 0, bsum = 0, qbuf = 0, ccount = 0, ccursor = 0, order = 0, par = 0, flag = 0, offsets = 0,
+         bad = 0, total = 0;
 };
 
 constexpr int kIpfMaxSide = 1024;  // cells per side of a triangle grid
@@ -1613,7 +1614,7 @@ int64_t ipf_ref_budget(int64_t tk) { return 8 * tk + 64; }
 
 int ipf_layout(int32_t K, int64_t V, int64_t T, int64_t R, IpfLayout& L) {
   if (K < 1 || K > (1 << 20) || V < 0 || T < 0 || R < 0 || V >= ((int64_t)1 << 31) || T > ((int64_t)1 << 27) ||
-      R >= ((int64_t)1 << 31))
+      R >= ((int64_t)1 << 30))
     return MPM_EINVAL;
   L.cells = 3 * (T + 2 * (int64_t)K);        // sum over grids of g^2 <= T_k + 2
   L.refs = 24 * T + 192 * (int64_t)K;        // sum over grids of the budget
@@ -1635,6 +1636,11 @@ int ipf_layout(int32_t K, int64_t V, int64_t T, int64_t R, IpfLayout& L) {
   L.refs_at = take(4 * (size_t)L.refs);
   L.per_grid = take(8 * 3 * (size_t)K);
   L.bsum = take(4 * (size_t)std::max<int64_t>(nb, 1));
+  L.qbuf = take(16 * (size_t)std::max<int64_t>(R, 1));
+  L.ccount = take(4 * (size_t)(L.cells + 1));
+  L.ccursor = take(4 * (size_t)L.cells);
+  L.order = take(4 * 3 * (size_t)std::max<int64_t>(R, 1));
+  L.par = take(3 * (size_t)std::max<int64_t>(R, 1));
   L.flag = take(4 * (size_t)(R + 1));
   L.offsets = take(4 * (size_t)(K + 1));
   L.bad = take(8);
@@ -1703,6 +1709,11 @@ int mpm_ipf_candidates(int32_t n_instances, const float* hull_vertices, const in
   uint32_t* d_refs = (uint32_t*)at(L.refs_at);
   unsigned long long* d_per_grid = (unsigned long long*)at(L.per_grid);
   uint32_t* d_bsum = (uint32_t*)at(L.bsum);
+  float4* d_qbuf = (float4*)at(L.qbuf);
+  uint32_t* d_ccount = (uint32_t*)at(L.ccount);
+  uint32_t* d_ccursor = (uint32_t*)at(L.ccursor);
+  uint32_t* d_order = (uint32_t*)at(L.order);
+  uint8_t* d_par = (uint8_t*)at(L.par);
   uint32_t* d_flag = (uint32_t*)at(L.flag);
   uint32_t* d_offsets = (uint32_t*)at(L.offsets);
   unsigned long long* d_bad = (unsigned long long*)at(L.bad);
@@ -1735,7 +1746,7 @@ int mpm_ipf_candidates(int32_t n_instances, const float* hull_vertices, const in
     }
     MCIS_TRY(hipMemcpyAsync(d_grid, grid.data(), sizeof(fmpm::IpfGrid) * 3 * (size_t)K, hipMemcpyHostToDevice, s));
     if ((rc = ipf_fill(d_count, cells + 1, 0u, s)) || (rc = ipf_fill(d_per_grid, 6 * (int64_t)K, 0u, s))) return rc;
-    fmpm::k_ipf_bin<false><<<blocks_for(3 * T, 256), 256, 0, s>>>(d_tri, T, d_ht_off, K, d_box, d_grid, d_count,
+    fmpm::k_ipf_bin<false><<<blocks_for(T, 256), 256, 0, s>>>(d_tri, T, d_ht_off, K, d_box, d_grid, d_count,
                                                                    d_per_grid, nullptr, nullptr, nullptr);
     MCIS_TRY(hipGetLastError());
     MCIS_TRY(hipMemcpyAsync(per_grid.data(), d_per_grid, 8 * 3 * (size_t)K, hipMemcpyDeviceToHost, s));
@@ -1752,13 +1763,22 @@ int mpm_ipf_candidates(int32_t n_instances, const float* hull_vertices, const in
   }
   if ((rc = mcis_scan(d_count, d_bsum, cells + 1, s))) return rc;
   if ((rc = ipf_fill(d_cursor, cells, 0u, s))) return rc;
-  fmpm::k_ipf_bin<true><<<blocks_for(3 * T, 256), 256, 0, s>>>(d_tri, T, d_ht_off, K, d_box, d_grid, nullptr,
+  fmpm::k_ipf_bin<true><<<blocks_for(T, 256), 256, 0, s>>>(d_tri, T, d_ht_off, K, d_box, d_grid, nullptr,
                                                                 nullptr, d_count, d_cursor, d_refs);
   MCIS_TRY(hipGetLastError());
-  // occupancy of every raw candidate, then the kept ones in raw order
+  // raw candidates into column order per axis, ray parities column by
+  // column, then the occupancy of every raw candidate
+  if ((rc = ipf_fill(d_ccount, cells + 1, 0u, s)) || (rc = ipf_fill(d_ccursor, cells, 0u, s))) return rc;
+  fmpm::k_ipf_points<<<blocks_for(R, 256), 256, 0, s>>>(u, R, d_ro, K, d_box, d_grid, d_qbuf, d_ccount, d_bad);
+  MCIS_TRY(hipGetLastError());
+  if ((rc = mcis_scan(d_ccount, d_bsum, cells + 1, s))) return rc;
+  fmpm::k_ipf_columns<<<blocks_for(R, 256), 256, 0, s>>>(d_qbuf, R, d_box, d_grid, d_ccount, d_ccursor, d_order);
+  MCIS_TRY(hipGetLastError());
+  fmpm::k_ipf_rays<<<blocks_for(3 * R, 256), 256, 0, s>>>(d_qbuf, R, d_box, d_grid, d_count, d_refs, d_tri,
+                                                          d_order, d_ccount + cells, d_par);
+  MCIS_TRY(hipGetLastError());
   if ((rc = ipf_fill(d_flag + R, 1, 0u, s))) return rc;
-  fmpm::k_ipf_occupancy<<<blocks_for(R, 256), 256, 0, s>>>(u, R, d_ro, K, d_box, d_grid, d_count, d_refs, d_tri,
-                                                           occupancy_threshold, d_flag, d_bad);
+  fmpm::k_ipf_flags<<<blocks_for(R, 256), 256, 0, s>>>(d_qbuf, R, d_par, occupancy_threshold, d_flag);
   MCIS_TRY(hipGetLastError());
   if ((rc = mcis_scan(d_flag, d_bsum, R + 1, s))) return rc;
   fmpm::k_ipf_offsets<<<blocks_for(K + 1, 64), 64, 0, s>>>(d_flag, d_ro, K, d_offsets);
@@ -1771,8 +1791,7 @@ int mpm_ipf_candidates(int32_t n_instances, const float* hull_vertices, const in
   if (bad) return MPM_EINVAL;
   const int64_t M_in = offs[K];
   if (M_in > 0) {
-    fmpm::k_ipf_write<<<blocks_for(R, 256), 256, 0, s>>>(u, R, d_ro, K, d_box, d_flag, M_in, candidates_out,
-                                                         source_out);
+    fmpm::k_ipf_write<<<blocks_for(R, 256), 256, 0, s>>>(d_qbuf, R, d_flag, M_in, candidates_out, source_out);
     MCIS_TRY(hipGetLastError());
     MCIS_TRY(hipStreamSynchronize(s));
   }

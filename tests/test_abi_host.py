@@ -129,7 +129,7 @@ def test_ipf_workspace_size_and_host_checks(lib):
     small = out.value
     assert lib.mpm_ipf_workspace_size(2, 100, 2000, 100000, ctypes.byref(out)) == B.MPM_OK
     assert out.value > small + 100000 * 4 + 1800 * (48 + 24 * 4)
-    for args in ((0, 1, 1, 1), (2, -1, 1, 1), (2, 1, 1 << 28, 1), (2, 1, 1, 1 << 31)):
+    for args in ((0, 1, 1, 1), (2, -1, 1, 1), (2, 1, 1 << 28, 1), (2, 1, 1, 1 << 30)):
         assert lib.mpm_ipf_workspace_size(*args, ctypes.byref(out)) == B.MPM_EINVAL
     assert lib.mpm_ipf_workspace_size(1, 1, 1, 1, None) == B.MPM_EINVAL
     I64 = lambda *v: (ctypes.c_int64 * len(v))(*v)

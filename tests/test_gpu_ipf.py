@@ -49,12 +49,15 @@ def grid_uniforms(n):
 
 
 def mixed_inputs(seed=8):
-    """Ellipsoid hulls, then a hollow box, two open boxes, an octahedron and
-    an instance without triangles; the box and octahedron instances take
-    grid uniforms (ties), the rest random ones."""
+    """Ellipsoid hulls, then a hollow box, two open boxes (one with an extra
+    vertex that no triangle uses, which must not widen its box), an
+    octahedron and an instance without triangles; the box and octahedron
+    instances take grid uniforms (ties), the rest random ones."""
     hollow = scenes.merge_meshes(scenes.box_mesh(0.25, 0.75), scenes.box_mesh(0.375, 0.625))
-    meshes = [hollow, scenes.box_mesh(0.25, 0.75, drop=("+z",)),
-              scenes.box_mesh(0.25, 0.75, drop=("+x", "+y", "+z")), scenes.octahedron_mesh((0.5, 0.5, 0.5), 0.25),
+    open_z = scenes.box_mesh(0.25, 0.75, drop=("+z",))
+    open_z = (np.concatenate([open_z[0], [[0.05, 0.9, 0.5]]]).astype(np.float32), open_z[1])
+    meshes = [hollow, open_z, scenes.box_mesh(0.25, 0.75, drop=("+x", "+y", "+z")),
+              scenes.octahedron_mesh((0.5, 0.5, 0.5), 0.25),
               (np.array([[0.5, 0.5, 0.5]], np.float32), np.zeros((0, 3), np.int32))]
     d = scenes.ipf_inputs(seed=seed, n_shell=(600, 1000, 400), raw_per_point=4.0, meshes=meshes, raw_per_mesh=729)
     # grid uniforms for the four dyadic meshes (their raw slots hold 729 = 9^3 each)

@@ -219,3 +219,14 @@ def test_threshold_is_strict():
     u = rng.uniform(0.05, 0.95, (100, 3))
     _, _, offs, vt = O.ipf_candidates(v, [0, 8], t, [0, len(t)], u, [0, 100], threshold=0.5)
     assert np.all(vt == 3) and list(offs) == [0, 0]
+
+
+def test_box_ignores_vertices_no_triangle_uses():
+    """B_k is the box of the hull H_k: a vertex that no triangle uses (a point
+    inside the hull, or a stray one) does not widen it."""
+    v, t = scenes.box_mesh(0.3, 0.7)
+    v2 = np.concatenate([v, [[0.05, 0.95, 0.5]]]).astype(np.float32)
+    u = np.random.default_rng(9).uniform(0, 1, (200, 3))
+    a = O.ipf_candidates(v, [0, 8], t, [0, 12], u, [0, 200])
+    b = O.ipf_candidates(v2, [0, 9], t, [0, 12], u, [0, 200])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and len(a[1]) == 200
