@@ -93,7 +93,7 @@ VALU_FILE = os.path.join(ROOT, "profiles", "fused_substep_large_scene_valu.json"
 VALU_COMMAND = ("cd /tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
                 "SQ_INSTS_LDS SQ_WAIT_INST_ANY SQ_INSTS_SALU --kernel-include-regex k_substep -f csv -d <out>/pmc_p1 "
                 "-o p1 -- python3 <repo>/bench.py --steps 1 --warmup 1 --substeps-per-step 10 --no-autotune "
-                "--no-step-n --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis --no-ipf --no-configs --no-atomics")
+                "--no-step-n --no-cpu-baseline --no-batched --no-bgdo --no-models --no-mcis --no-ipf --no-det --no-configs --no-atomics")
 
 
 def write_valu(p1_csv, n_particles=2_000_000):
@@ -124,7 +124,7 @@ def measured_valu(n_particles):
 
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
                "--steps 1 --warmup 1 --substeps-per-step 10 --no-autotune --no-step-n --no-cpu-baseline --no-batched "
-               "--no-bgdo --no-models --no-mcis --no-ipf --no-configs --no-atomics")
+               "--no-bgdo --no-models --no-mcis --no-ipf --no-det --no-configs --no-atomics")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) -> dict:
@@ -185,6 +185,42 @@ def bgdo_timing(sc, frames=25, substeps_per_frame=20):
             "seconds": dt, "substeps": frames * substeps_per_frame,
             "mean_log_E_update": float(upd.mean()),
             "paper_context": "39 s BGDO forward per scene on an RTX A6000 (different scenes, not comparable)"}
+
+
+def deterministic_timing(sc, substeps=20, reps=3):
+    """Cost of MPM_FLAG_DETERMINISTIC on the workload: resident substeps
+    (mpm_advance) with and without the flag, wall time per substep
+    (device-synchronised, best of reps), and whether two deterministic runs
+    from the same state agree bit for bit."""
+    import numpy as np
+    import torch
+
+    from paper_2602_01723_amd import binding as B
+    out = {}
+    finals = []
+    for det in (False, True):
+        best = float("inf")
+        for r in range(reps):
+            ctx = B.init_from_scene(sc, deterministic=det)
+            p = B.Particles.from_scene(sc)
+            B.mpm_load(ctx, p)
+            B.mpm_advance(ctx, 1)  # primes the grid
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.mpm_advance(ctx, substeps)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+            if det and r < 2:
+                B.mpm_store(ctx, p)
+                torch.cuda.synchronize()
+                finals.append(p.x.cpu().numpy().view(np.uint32).copy())
+            del ctx, p
+            torch.cuda.empty_cache()
+        out["deterministic" if det else "default"] = {"ms_per_substep": best / substeps * 1e3}
+    out["slowdown"] = out["deterministic"]["ms_per_substep"] / out["default"]["ms_per_substep"]
+    out["repeat_bitwise_equal"] = bool(len(finals) == 2 and np.array_equal(finals[0], finals[1]))
+    out["workload"] = f"same scene, mpm_advance({substeps}) after one primed substep, best of {reps}"
+    return out
 
 
 MODEL_VARIANTS = (("fixed_corotated", 0, 0), ("hencky", 1, 0), ("neo_hookean", 2, 0), ("stvk", 3, 0),
@@ -714,6 +750,8 @@ def main():
                     help="skip timing the same frames through mpm_step_n (caller-order I/O at every call)")
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
     ap.add_argument("--no-ipf", action="store_true", help="skip the candidate-generation timing")
+    ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode timing")
+    ap.add_argument("--det-only", action="store_true", help="time only the deterministic mode and exit")
     ap.add_argument("--ipf-only", action="store_true", help="time only the candidate generation and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched vs plain forward + adjoint and exit")
@@ -772,6 +810,11 @@ def main():
         return
     if args.adjoint_counters:
         print(json.dumps({"adjoint_counter_run": adjoint_counter_run()}), flush=True)
+        return
+    if args.det_only:
+        print(json.dumps({"deterministic": deterministic_timing(scenes.make_scene("large_scene",
+                                                                                 n_total=args.n_total))}),
+              flush=True)
         return
     copy_gbs = copy_probe()
     log(f"  plain 256 MiB copy: {copy_gbs:.0f} GB/s (read + write)")
@@ -902,6 +945,13 @@ def main():
         mcis = mcis_timing()
         log(f"  {mcis['seconds'] * 1e3:.1f} ms for 8M candidates")
         torch.cuda.empty_cache()
+    det = None
+    if not args.no_det:
+        log("deterministic mode ...")
+        det = deterministic_timing(sc)
+        log(f"  {det['deterministic']['ms_per_substep']:.3f} vs {det['default']['ms_per_substep']:.3f} ms per "
+            f"substep, repeat bitwise equal: {det['repeat_bitwise_equal']}")
+        torch.cuda.empty_cache()
     ipf = None
     if not args.no_ipf:
         log("candidate generation + interior fill ...")
@@ -962,6 +1012,7 @@ def main():
         "per_model_fused": models,
         "mcis": mcis,
         "ipf": ipf,
+        "deterministic": det,
         "device_memory_gb": round((free0 - free1) / 1e9, 3),
         "paper_context": {
             "figure": "about 1 minute and 7 GB per scene for the whole pipeline (IPF 22 s, BGDO forward "

@@ -110,8 +110,23 @@ typedef struct {
   float dt;              /* substep, s (> 0) */
   float gravity[3];      /* acceleration, m/s^2, added to grid velocity as dt * g */
   int32_t sort_every;    /* re-sort particles by cell every this many substeps (0 = library default) */
-  uint32_t flags;        /* reserved, must be 0 */
+  uint32_t flags;        /* 0 or MPM_FLAG_DETERMINISTIC */
 } mpm_config;
+
+/* Deterministic forward: the particle state after any sequence of substep
+ * calls is a function of the inputs alone, bit for bit (the same on every
+ * run, whatever the order of the GPU's atomic operations), and a scene's
+ * result in a batched context equals its result alone.  The P2G of each
+ * substep then runs twice: a measuring launch finds each scene's largest
+ * contribution bound B_b, and the accumulating launch adds every
+ * contribution, rounded to one fixed-point scale per scene (a power of two
+ * set by B_b and the scene's particle count), as 64-bit integers, which sum
+ * exactly in any order; the particles of each cell are ordered by index at
+ * every sort.  Costs a second P2G-side launch per substep and 32 B per grid
+ * node of workspace.  The backward's adjoint scatter stays in floating
+ * point and is not covered.  A cell of more than 4096 particles keeps the
+ * order of the atomics (counted in mpm_diag.order_fallbacks). */
+#define MPM_FLAG_DETERMINISTIC 1u
 
 typedef struct {
   float* x;              /* [3][N] in/out */
@@ -137,6 +152,8 @@ typedef struct {
   double max_wave_cfl;    /* largest c dt / dx of the particles handed in since mpm_init, with
                              c^2 = (lam + 2 mu) V0 / m the squared P-wave speed (the explicit
                              update is unstable once this is well above 1) */
+  int64_t order_fallbacks; /* deterministic mode: sorts of a cell holding more than 4096
+                              particles, which keep the atomics' order (0 otherwise) */
 } mpm_diag;
 
 /* Status code as text (static storage). */

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libfastmpm.so")
 
 MPM_ABI_VERSION = 1
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MPM_FLAG_DETERMINISTIC = 1
 EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_workspace_size", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_load",
             "mpm_advance", "mpm_store", "mpm_export_frame", "mpm_tape_size",
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
@@ -65,7 +66,7 @@ class mpm_tuning(ctypes.Structure):
 class mpm_diag(ctypes.Structure):
     _fields_ = [("nonfinite", ctypes.c_int64), ("out_of_grid", ctypes.c_int64), ("tile_overflow", ctypes.c_int64),
                 ("tile_escapes", ctypes.c_int64), ("substeps", ctypes.c_int64), ("cfl_violations", ctypes.c_int64),
-                ("max_cfl", ctypes.c_double), ("max_wave_cfl", ctypes.c_double)]
+                ("max_cfl", ctypes.c_double), ("max_wave_cfl", ctypes.c_double), ("order_fallbacks", ctypes.c_int64)]
 
 
 _lib = None
@@ -231,9 +232,11 @@ class Particles:
         return Particles(**{k: getattr(self, k).clone() for k in self.__dataclass_fields__})
 
 
-def make_config(grid_res, dt, n_batch=1, gravity=(0.0, -9.8, 0.0), bound=3, sort_every=0) -> mpm_config:
+def make_config(grid_res, dt, n_batch=1, gravity=(0.0, -9.8, 0.0), bound=3, sort_every=0,
+                deterministic=False) -> mpm_config:
     return mpm_config(MPM_ABI_VERSION, int(grid_res), int(bound), int(n_batch), float(dt),
-                      (ctypes.c_float * 3)(*[float(g) for g in gravity]), int(sort_every), 0)
+                      (ctypes.c_float * 3)(*[float(g) for g in gravity]), int(sort_every),
+                      MPM_FLAG_DETERMINISTIC if deterministic else 0)
 
 
 def mpm_workspace_size(cfg: mpm_config, n_particles: int) -> int:
@@ -244,13 +247,14 @@ def mpm_workspace_size(cfg: mpm_config, n_particles: int) -> int:
 
 
 def mpm_init(grid_res, dt, materials: Sequence[dict], n_particles, batch_offsets=None, gravity=(0.0, -9.8, 0.0),
-             bound=3, sort_every=0) -> Context:
+             bound=3, sort_every=0, deterministic=False) -> Context:
     """Create a context; its device workspace is a torch uint8 tensor on the
-    current device, held by the returned Context."""
+    current device, held by the returned Context.  deterministic sets
+    MPM_FLAG_DETERMINISTIC."""
     import torch
     lib = load()
     n_batch = 1 if batch_offsets is None else len(batch_offsets) - 1
-    cfg = make_config(grid_res, dt, n_batch, gravity, bound, sort_every)
+    cfg = make_config(grid_res, dt, n_batch, gravity, bound, sort_every, deterministic)
     mats = (mpm_material * len(materials))(*[mpm_material(int(m["elastic"]), int(m["plastic"]),
                                                           float(m.get("yield_stress", 0.0)),
                                                           float(m.get("friction_deg", 0.0))) for m in materials])
@@ -266,9 +270,9 @@ def mpm_init(grid_res, dt, materials: Sequence[dict], n_particles, batch_offsets
     return Context(h, int(n_particles), n_batch, int(grid_res), ws)
 
 
-def init_from_scene(sc, sort_every=0) -> Context:
+def init_from_scene(sc, sort_every=0, deterministic=False) -> Context:
     return mpm_init(sc.grid_res, sc.dt, sc.materials, sc.n,
-                    None if sc.n_batch == 1 else sc.batch_offsets, sc.gravity, sc.bound, sort_every)
+                    None if sc.n_batch == 1 else sc.batch_offsets, sc.gravity, sc.bound, sort_every, deterministic)
 
 
 def mpm_substep(ctx: Context, p: Particles, stream=None):
@@ -345,7 +349,7 @@ def mpm_get_diagnostics(ctx: Context) -> dict:
     rc = load().mpm_get_diagnostics(ctx.handle, ctypes.byref(d))
     out = dict(nonfinite=d.nonfinite, out_of_grid=d.out_of_grid, tile_overflow=d.tile_overflow,
                tile_escapes=d.tile_escapes, substeps=d.substeps, cfl_violations=d.cfl_violations,
-               max_cfl=d.max_cfl, max_wave_cfl=d.max_wave_cfl, status=rc)
+               max_cfl=d.max_cfl, max_wave_cfl=d.max_wave_cfl, order_fallbacks=d.order_fallbacks, status=rc)
     if rc not in (MPM_OK, MPM_EUNSTABLE):
         _check(ctx, rc, "mpm_get_diagnostics")
     return out

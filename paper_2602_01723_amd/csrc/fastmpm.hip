@@ -27,7 +27,8 @@ using fmpm::kBlock;
 
 // device counters: 0 non-finite, 1 out of grid, 2 tile overflow, 3 tile
 // escapes, 4 CFL violations, 5 max (|v'| dt / dx)^2 and 6 max (c dt / dx)^2
-// (float bits in the low word), 7 unused
+// (float bits in the low word), 7 cells left in atomic order by the
+// deterministic sort (more than fmpm::kStableMax particles)
 constexpr int kDiagSlots = 8;
 
 struct mpm_context {
@@ -67,6 +68,13 @@ struct mpm_context {
   const int* pdest_cur = nullptr;  // destinations of the prepared permutation
   unsigned long long* diag = nullptr;
   fmpm::Material* d_mats = nullptr;
+  // deterministic mode (MPM_FLAG_DETERMINISTIC): per-scene bounds and range
+  // factors, the 64-bit fixed-point grid, the second permutation buffer
+  bool det = false;
+  unsigned* fxb = nullptr;
+  double* fxk = nullptr;
+  unsigned long long* gfx = nullptr;
+  int* perm2 = nullptr;
   size_t workspace_bytes = 0;  // of the caller's workspace, which holds every device buffer above
 
   // kernel timing (mpm_profile): event pairs recorded around launches
@@ -200,6 +208,12 @@ int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
   LAUNCH_CHECK(c, "k_scan_apply");
   fmpm::k_place<<<blocks_for(c->N, 256), 256, 0, s>>>(c->keys, c->slots, c->count, c->perm, c->N);
   LAUNCH_CHECK(c, "k_place");
+  if (c->det) {  // each cell's particles by source index
+    fmpm::k_stable_rank<<<blocks_for(c->N, 256), 256, 0, s>>>(c->perm, c->keys, c->count, c->bins, c->N, c->perm2,
+                                                              c->diag + 7);
+    LAUNCH_CHECK(c, "k_stable_rank");
+    std::swap(c->perm, c->perm2);
+  }
   // chunk table of the new order
   const unsigned gb = blocks_for(c->nblocks, 256);
   fmpm::k_block_chunk_count<<<gb, 256, 0, s>>>(c->count, c->nblocks, c->N, c->item, c->nchk);
@@ -442,6 +456,39 @@ int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
   return rc ? rc : perm_apply(c, state_planes(in, out, N), s);
 }
 
+// One substep kernel with arguments a.  In deterministic mode a launch
+// that scatters (P2G) is a measuring launch, the accumulating launch and
+// the conversion of the fixed-point grid into a.grid_out.
+template <int MODE>
+int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s) {
+  if (MODE == fmpm::kG2P || !c->det) {
+    fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);  // persistent: items from the queue
+    LAUNCH_CHECK(c, "k_substep");
+    return MPM_OK;
+  }
+  if constexpr (MODE != fmpm::kG2P) {
+    int rc = fill_u32(c, c->fxb, 2 * (int64_t)c->B, s);
+    if (rc) return rc;
+    fmpm::SubstepArgs m = a;  // reads the state, writes nothing but the bounds
+    m.grid_clear = nullptr;
+    m.clear_nodes = 0;
+    m.box_out = nullptr;
+    m.write_vc = 0;
+    m.fxb = c->fxb;
+    fmpm::k_substep<MODE, fmpm::kDetMeasure><<<c->grid_blocks, kBlock, 0, s>>>(m);
+    LAUNCH_CHECK(c, "k_substep measure");
+    a.fxb = c->fxb;
+    a.fxk = c->fxk;
+    a.gfx = c->gfx;
+    fmpm::k_substep<MODE, fmpm::kDetAccumulate><<<c->grid_blocks, kBlock, 0, s>>>(a);
+    LAUNCH_CHECK(c, "k_substep accumulate");
+    fmpm::k_fx_grid<<<blocks_for(c->nodes, 256), 256, 0, s>>>(c->gfx, a.grid_out, c->nodes,
+                                                             (int64_t)c->n * c->n * c->n, c->fxb, c->fxk);
+    LAUNCH_CHECK(c, "k_fx_grid");
+  }
+  return MPM_OK;
+}
+
 template <int MODE>
 int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hipStream_t s,
                    float4* gclear = nullptr, const int* box_in = nullptr, int* box_out = nullptr) {
@@ -454,9 +501,7 @@ int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hip
   a.box_in = box_in;
   a.box_out = box_out;
   ProfScope ps(c, s, MODE == fmpm::kFused ? 0 : (MODE == fmpm::kP2G ? 1 : 2));
-  fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);  // persistent: items from the queue
-  LAUNCH_CHECK(c, "k_substep");
-  return MPM_OK;
+  return launch_args<MODE>(c, a, s);
 }
 
 int check_particles(mpm_ctx ctx, const mpm_particles* p) {
@@ -469,7 +514,8 @@ int check_particles(mpm_ctx ctx, const mpm_particles* p) {
 
 // Sizes derived from the configuration (shared by mpm_workspace_size and mpm_init).
 struct Geometry {
-  int n = 0, nb = 0;
+  bool det = false;
+  int n = 0, nb = 0, B = 1;
   int64_t N = 0, nodes = 0, bins = 0, n_bsum = 0, nblocks = 0, max_chunks = 0, chunk_cap = 0;
 };
 
@@ -485,7 +531,7 @@ int check_config(const mpm_config* cfg, int64_t n_particles, const int64_t* batc
   if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt)) return MPM_EINVAL;
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(cfg->gravity[k])) return MPM_EINVAL;
-  if (cfg->sort_every < 0 || cfg->flags != 0) return MPM_EINVAL;
+  if (cfg->sort_every < 0 || (cfg->flags & ~(uint32_t)MPM_FLAG_DETERMINISTIC) != 0) return MPM_EINVAL;
   if (n_particles < 0 || n_particles > (int64_t)0x7fffff00) return MPM_EINVAL;
   if (off) {
     if (batch_offsets) {
@@ -498,6 +544,8 @@ int check_config(const mpm_config* cfg, int64_t n_particles, const int64_t* batc
     for (int b = 0; b < cfg->n_batch; ++b)
       if ((*off)[b + 1] < (*off)[b]) return MPM_EINVAL;
   }
+  g->det = (cfg->flags & MPM_FLAG_DETERMINISTIC) != 0;
+  g->B = cfg->n_batch;
   g->n = cfg->grid_res;
   g->nb = (g->n + 3) / 4;
   g->N = n_particles;
@@ -552,6 +600,12 @@ size_t carve(mpm_ctx c, const Geometry& g, char* base) {
   take(c->nchk, g.nblocks);
   take(c->work_counter, 1);
   take(c->d_mats, fmpm::kMaxMaterials);
+  if (g.det) {
+    take(c->gfx, 4 * g.nodes);
+    take(c->fxb, 2 * (int64_t)g.B);
+    take(c->fxk, g.B);
+    take(c->perm2, N);
+  }
   const PermGeom pg = perm_geom(N);
   take(c->pdest, N);
   if (pg.bucketed) {
@@ -627,6 +681,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   c->bins = g.bins;
   c->n_bsum = g.n_bsum;
   if (cfg->sort_every > 0) c->sort_every = cfg->sort_every;
+  c->det = g.det;
 
   std::vector<int> cs, cb;
   for (int b = 0; b < c->B; ++b)
@@ -654,6 +709,12 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemset(c->grid[0], 0, (size_t)c->nodes * sizeof(float4));
+  if (e == hipSuccess && c->det) {  // range factors K_b = max(2^15, N_b / 2^9); the fixed-point grid at zero
+    std::vector<double> k(c->B);
+    for (int b = 0; b < c->B; ++b) k[b] = std::max(32768.0, (double)(off[b + 1] - off[b]) / 512.0);
+    e = hipMemcpy(c->fxk, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->gfx, 0, (size_t)c->nodes * 4 * sizeof(unsigned long long));
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete c;
@@ -956,8 +1017,8 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::SubstepArgs a = args_for(0, 0);
       a.grid_out = gslot(0);
       a.box_out = bslot(0);
-      fmpm::k_substep<fmpm::kP2G><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
-      LAUNCH_CHECK(ctx, "recompute P2G");
+      rc = launch_args<fmpm::kP2G>(ctx, a, s);
+      if (rc) return rc;
     }
     for (int j = 0; j + 1 < L; ++j) {
       rc = fill_u32(ctx, gslot(j + 1), 4 * ctx->nodes, s, -1, ctx->work_counter);
@@ -968,8 +1029,8 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       a.box_in = bslot(j);
       a.box_out = bslot(j + 1);
       a.write_vc = 1;
-      fmpm::k_substep<fmpm::kFused><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
-      LAUNCH_CHECK(ctx, "recompute substep");
+      rc = launch_args<fmpm::kFused>(ctx, a, s);
+      if (rc) return rc;
     }
     // with return maps: the state after the segment's last substep as well
     // (slot L), whose C forms that substep's F_trial
@@ -978,8 +1039,8 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       fmpm::SubstepArgs a = args_for(L - 1, L);
       a.grid_in = gslot(L - 1);
       a.box_in = bslot(L - 1);
-      fmpm::k_substep<fmpm::kG2P><<<ctx->grid_blocks, kBlock, 0, s>>>(a);
-      LAUNCH_CHECK(ctx, "recompute G2P");
+      rc = launch_args<fmpm::kG2P>(ctx, a, s);
+      if (rc) return rc;
     }
     // (3) adjoint of the segment's final state, in sorted order, through
     // the permutation (1) prepared (caller index -> slot; the recompute
@@ -1100,6 +1161,7 @@ int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out) {
   std::memcpy(&c2, &b6, 4);
   out->max_cfl = std::sqrt((double)v2) * scale;
   out->max_wave_cfl = std::sqrt((double)c2) * scale;
+  out->order_fallbacks = (int64_t)h[7];
   return (h[0] || h[1] || h[4]) ? MPM_EUNSTABLE : MPM_OK;
 }
 

@@ -78,7 +78,25 @@ struct SubstepArgs {
   // CFL watch: G2P velocities with |v'|^2 above cfl_v2 (|v'| dt / dx > 1/2)
   // are counted in diag[4]; the largest |v'|^2 goes to diag[5]
   float cfl_v2;
+  // deterministic mode (k_substep<MODE, kDetMeasure / kDetAccumulate>):
+  // fxb[2 b + 0 / 1] = per-scene largest P2G contribution bound (momentum,
+  // mass; float bits) raised by the measuring launch, fxk[b] the scene's
+  // range factor, gfx the 64-bit fixed-point grid [node][4] the
+  // accumulating launch adds into
+  unsigned* fxb;
+  const double* fxk;
+  unsigned long long* gfx;
 };
+
+// Deterministic mode.  The P2G of a substep runs twice: a measuring launch
+// computes every particle's contribution bound and keeps each scene's
+// largest, B_b; the accumulating launch then uses one fixed-point scale per
+// scene and channel, s_b = fx_scale(K_b B_b), for every contribution, in
+// the LDS tiles and in a 64-bit integer grid, so each node's sum is exact
+// and independent of the order of the additions and of how the particles
+// are grouped into items.  K_b = max(2^15, N_b / 2^9) keeps a tile node sum
+// of up to 8192 particles below 2^47 and a grid node sum below 2^58.
+constexpr int kDetOff = 0, kDetMeasure = 1, kDetAccumulate = 2;
 
 // --------------------------------------------------------------------------
 // small helpers
@@ -324,8 +342,9 @@ __device__ __forceinline__ void block_minmax(const int* lo, const int* hi, int* 
     }
 }
 
-template <int MODE>
+template <int MODE, int DET = kDetOff>
 __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
+  constexpr bool kMeasure = DET == kDetMeasure, kAccum = DET == kDetAccumulate;
   __shared__ unsigned long long ptile[4 * kTileCapMax];  // P2G fixed-point accumulators: mv.x, mv.y, mv.z, m
   __shared__ float gtile[3 * kTileCapMax];               // G2P node velocities
   __shared__ int red[8 * (kBlock / 64)];
@@ -403,8 +422,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     const int SX = py * pz + kPadX;
     const int PT = empty ? 0 : (px - 1) * SX + (py - 1) * pz + pz;
     const bool lds_g = (MODE != kP2G) && !empty && GT <= cap;
-    const bool lds_p = (MODE != kG2P) && !empty && PT <= cap;
-    if (threadIdx.x == 0 && !empty && (((MODE != kP2G) && !lds_g) || ((MODE != kG2P) && !lds_p)))
+    const bool lds_p = !kMeasure && (MODE != kG2P) && !empty && PT <= cap;
+    if (!kMeasure && threadIdx.x == 0 && !empty && (((MODE != kP2G) && !lds_g) || ((MODE != kG2P) && !lds_p)))
       atomicAdd(&a.diag[2], 1ull);
 
     // 2. tiles
@@ -441,9 +460,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     // scatters to global memory instead.
     double s_mom = 1.0, s_mass = 1.0;
     float lim_mom = 0.0f, lim_mass = 0.0f;
+    const int scene = a.chunk_batch[item];
+    if (kAccum) {  // the scene's scales from the measured bounds
+      lim_mom = __uint_as_float(a.fxb[2 * scene]);
+      lim_mass = __uint_as_float(a.fxb[2 * scene + 1]);
+      s_mom = fx_scale(a.fxk[scene] * (double)lim_mom);
+      s_mass = fx_scale(a.fxk[scene] * (double)lim_mass);
+    }
     for (int sub = start; sub < end; sub += kBlock) {
       const int i = sub + (int)threadIdx.x;
-      const bool scale_pass = (MODE != kG2P) && lds_p && sub == start;
+      const bool scale_pass = !kAccum && (MODE != kG2P) && lds_p && sub == start;
       if (i >= end && !scale_pass) break;  // the scale pass needs every thread at its barrier
       // P2G contribution of this thread's particle: w (q + Ad o) for node offset o
       bool scat = false;
@@ -481,7 +507,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
           for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
           ok = in_grid;
           if (in_grid) b0p = b0[0] | (b0[1] << 10) | (b0[2] << 20);
-          if (!in_grid) {
+          if (!in_grid && !kMeasure) {
             atomicAdd(&a.diag[1], 1ull);
             if (a.xo != a.x) {  // skipped: carry the state over unchanged
 #pragma unroll
@@ -575,8 +601,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
               xp[k] = xp[k] + a.dt * vs[k];
             }
             const float v2 = vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2];
-            v2max = fmaxf(v2max, v2);
-            cfl_count += (v2 > a.cfl_v2) ? 1u : 0u;
+            if (!kMeasure) {
+              v2max = fmaxf(v2max, v2);
+              cfl_count += (v2 > a.cfl_v2) ? 1u : 0u;
+            }
             // F_trial = (I + dt C') F, in double
             double Ftr[9];
 #pragma unroll
@@ -599,14 +627,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) fin &= isfinite(xp[k]);
             if (!fin) {
-              atomicAdd(&a.diag[0], 1ull);
+              if (!kMeasure) atomicAdd(&a.diag[0], 1ull);
               ok = false;
             }
+            if (!kMeasure) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) a.xo[k * N + i] = xp[k];
+              for (int k = 0; k < 3; ++k) a.xo[k * N + i] = xp[k];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = Ff[k];
-            if (MODE == kG2P || a.write_vc) {
+              for (int k = 0; k < 9; ++k) a.Fo[k * N + i] = Ff[k];
+            }
+            if (!kMeasure && (MODE == kG2P || a.write_vc)) {
 #pragma unroll
               for (int k = 0; k < 3; ++k) a.vo[k * N + i] = vp[k];
 #pragma unroll
@@ -620,7 +650,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
           bool in_grid = true;
 #pragma unroll
           for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
-          if (MODE == kP2G && !in_grid) atomicAdd(&a.diag[1], 1ull);
+          if (MODE == kP2G && !in_grid && !kMeasure) atomicAdd(&a.diag[1], 1ull);
           // a particle that changed cell may widen the item's next box
           if (MODE == kFused && a.box_out && in_grid && (b1[0] | (b1[1] << 10) | (b1[2] << 20)) != b0p) {
 #pragma unroll
@@ -652,7 +682,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
             for (int k = 0; k < 9; ++k) fin &= isfinite(Ad[k]);
             if (fin) {
               scat = true;
-            } else {  // never let a bad particle reach the grid
+            } else if (!kMeasure) {  // never let a bad particle reach the grid
               atomicAdd(&a.diag[0], 1ull);
             }
           }
@@ -671,6 +701,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       }
       // a bound that overflows float32 keeps its particle out of the tile and out of the scale
       const bool fx_ok = bnd_mom <= 3.0e38f && bnd_mass <= 3.0e38f;
+      if (kMeasure) {  // the scene's largest bounds; nothing is scattered
+        if (scat && fx_ok) {
+          raise_max(&a.fxb[2 * scene], bnd_mom);
+          raise_max(&a.fxb[2 * scene + 1], bnd_mass);
+        }
+        continue;
+      }
       if (scale_pass) {
         float m2[2] = {wave_maxf(fx_ok ? bnd_mom : 0.0f), wave_maxf(fx_ok ? bnd_mass : 0.0f)};
         if ((threadIdx.x & 63) == 0) {
@@ -747,11 +784,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
           const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
           const float wgt = sel3(w[0], ox) * sel3(w[1], oy) * sel3(w[2], oz);
           const int ix = b1[0] + ox, iy = b1[1] + oy, iz = b1[2] + oz;
-          float* gp = (float*)&a.grid_out[gbase + ((int64_t)ix * n + iy) * n + iz];
+          const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
+          if (kAccum) {  // the scene's fixed point, added exactly
+            unsigned long long* gq = a.gfx + 4 * node;
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            atomicAdd(gp + c, wgt * (q[c] + Ad[3 * c] * (float)ox + Ad[3 * c + 1] * (float)oy + Ad[3 * c + 2] * (float)oz));
-          atomicAdd(gp + 3, wgt * mass);
+            for (int c = 0; c < 3; ++c)
+              atomicAdd(gq + c, (unsigned long long)fx_value(fx_bits(
+                                    wgt * (q[c] + Ad[3 * c] * (float)ox + Ad[3 * c + 1] * (float)oy +
+                                           Ad[3 * c + 2] * (float)oz), s_mom)));
+            atomicAdd(gq + 3, (unsigned long long)fx_value(fx_bits(wgt * mass, s_mass)));
+          } else {
+            float* gp = (float*)&a.grid_out[node];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              atomicAdd(gp + c, wgt * (q[c] + Ad[3 * c] * (float)ox + Ad[3 * c + 1] * (float)oy + Ad[3 * c + 2] * (float)oz));
+            atomicAdd(gp + 3, wgt * mass);
+          }
         }
       }
     }
@@ -768,15 +816,24 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
         const int ti = t / SX, tr = t - ti * SX;
         const int tj = tr / pz, tk = tr - tj * pz;
         if (tj >= py) continue;  // padding
-        float* gp = (float*)&a.grid_out[gbase + ((int64_t)(plo[0] + ti) * n + (plo[1] + tj)) * n + (plo[2] + tk)];
-        atomicAdd(gp + 0, (float)((double)fx_value(ptile[t]) * is_mom));
-        atomicAdd(gp + 1, (float)((double)fx_value(ptile[kTileCapMax + t]) * is_mom));
-        atomicAdd(gp + 2, (float)((double)fx_value(ptile[2 * kTileCapMax + t]) * is_mom));
-        atomicAdd(gp + 3, (float)((double)im * is_mass));
+        const int64_t node = gbase + ((int64_t)(plo[0] + ti) * n + (plo[1] + tj)) * n + (plo[2] + tk);
+        if (kAccum) {  // integer sums at the scene's scale: exact, in any order
+          unsigned long long* gq = a.gfx + 4 * node;
+          atomicAdd(gq + 0, (unsigned long long)fx_value(ptile[t]));
+          atomicAdd(gq + 1, (unsigned long long)fx_value(ptile[kTileCapMax + t]));
+          atomicAdd(gq + 2, (unsigned long long)fx_value(ptile[2 * kTileCapMax + t]));
+          atomicAdd(gq + 3, (unsigned long long)im);
+        } else {
+          float* gp = (float*)&a.grid_out[node];
+          atomicAdd(gp + 0, (float)((double)fx_value(ptile[t]) * is_mom));
+          atomicAdd(gp + 1, (float)((double)fx_value(ptile[kTileCapMax + t]) * is_mom));
+          atomicAdd(gp + 2, (float)((double)fx_value(ptile[2 * kTileCapMax + t]) * is_mom));
+          atomicAdd(gp + 3, (float)((double)im * is_mass));
+        }
       }
     }
   }
-  if (MODE != kP2G) cfl_flush(a.diag, v2max, cfl_count);
+  if (MODE != kP2G && !kMeasure) cfl_flush(a.diag, v2max, cfl_count);
   // the queue is drained: the last workgroup out resets the counters
   if (a.done_counter && threadIdx.x == 0) {
     __threadfence();
@@ -798,6 +855,46 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n, int* counter) {
   if (i < n4) reinterpret_cast<uint4*>(p)[i] = make_uint4(v, v, v, v);
   const int64_t t = (n4 << 2) + i;
   if (i < (n & 3)) p[t] = v;
+}
+
+// Deterministic mode: the 64-bit fixed-point grid [node][4] -> grid (mv,
+// m) as float4 at each scene's scales (the same fx_scale of the same
+// bounds as the accumulating launch), and the fixed-point grid zeroed for
+// the next accumulation.  per_scene = n^3.
+__global__ void k_fx_grid(unsigned long long* gfx, float4* grid, int64_t nodes, int64_t per_scene,
+                          const unsigned* fxb, const double* fxk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nodes) return;
+  const int b = (int)(t / per_scene);
+  const double is_mom = 1.0 / fx_scale(fxk[b] * (double)__uint_as_float(fxb[2 * b]));
+  const double is_mass = 1.0 / fx_scale(fxk[b] * (double)__uint_as_float(fxb[2 * b + 1]));
+  unsigned long long* g = gfx + 4 * t;
+  grid[t] = make_float4((float)((double)(long long)g[0] * is_mom), (float)((double)(long long)g[1] * is_mom),
+                        (float)((double)(long long)g[2] * is_mom), (float)((double)(long long)g[3] * is_mass));
+  g[0] = g[1] = g[2] = g[3] = 0ull;
+}
+
+// Deterministic mode: order the particles of each cell by source index
+// (the counting sort's slots come from atomics, in no fixed order).
+// perm: sorted slot -> source index; start: exclusive scan of the cell
+// counts.  A cell of more than kStableMax particles keeps its order and is
+// counted in *fallbacks.
+constexpr int kStableMax = 4096;
+__global__ void k_stable_rank(const int* perm, const uint32_t* keys, const uint32_t* start, int64_t bins, int64_t N,
+                              int* perm_out, unsigned long long* fallbacks) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int me = perm[j];
+  const uint32_t key = keys[me];
+  const int64_t s0 = start[key], s1 = (int64_t)key + 1 < bins ? (int64_t)start[key + 1] : N;
+  if (s1 - s0 > kStableMax) {
+    perm_out[j] = me;
+    if (j == s0) atomicAdd(fallbacks, 1ull);
+    return;
+  }
+  int64_t r = 0;
+  for (int64_t q = s0; q < s1; ++q) r += perm[q] < me;
+  perm_out[s0 + r] = me;
 }
 
 // key = scene * bins_per_scene + block(4^3 cells, linear) * 64 + morton(cell in block)

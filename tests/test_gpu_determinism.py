@@ -1,0 +1,171 @@
+"""Deterministic mode (MPM_FLAG_DETERMINISTIC) through the C ABI.
+
+With the flag the forward state is a function of the inputs alone: the P2G
+sums are 64-bit integers at one fixed-point scale per scene (exact in any
+order of the atomics) and each cell's particles are ordered by index at
+every sort.  Checked bit for bit: repeated runs, a resident run split into
+calls against one call (re-sorts in between), a batched context against
+each scene alone, and the mpm_step_n path against itself under a different
+particle order of the caller.  The mode keeps the substep's parity with the
+oracle, and its state stays within rounding of the default mode."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mpm_oracle as O
+from paper_2602_01723_amd import binding as B
+from paper_2602_01723_amd import scenes
+from tests.parity import TOL_SUBSTEP, compare_substep, parity_failures, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def state_bits(p):
+    return [a.view(np.uint32) for a in p.state_numpy()]
+
+
+def assert_same_bits(a, b, what):
+    for k, (x, y) in enumerate(zip(a, b)):
+        diff = int(np.count_nonzero(x != y))
+        assert diff == 0, f"{what}: field {'xvCF'[k]} differs in {diff} entries"
+
+
+def pair_scene(n=40_000):
+    """Two ellipsoids colliding at +-1 m/s (contact, particles crossing
+    item boxes), 48^3 grid, with a von Mises half so a return map runs."""
+    sc = scenes.make_scene("colliding_pair", n_total=n, grid_res=48)
+    sc.materials = [dict(sc.materials[0]), scenes._material(scenes.ELASTIC_HENCKY, scenes.PLASTIC_VON_MISES, 2e3)]
+    sc.mat_id = np.where(np.arange(sc.n) < sc.n // 2, 0, 1).astype(np.int32)
+    return sc
+
+
+def run_step_n(sc, n_steps, det=True, order=None, sort_every=6, tile_cap=0):
+    order = np.arange(sc.n) if order is None else order
+    print(f"determinism: step_n N={sc.n} steps={n_steps} det={det} tile_cap={tile_cap}", flush=True)
+    ctx = B.init_from_scene(sc, sort_every=sort_every, deterministic=det)
+    if tile_cap:
+        B.mpm_set_tuning(ctx, tile_cap=tile_cap)
+    p = B.Particles.from_arrays(sc.x[order], sc.v[order], sc.C[order], sc.F[order], sc.mass[order],
+                                sc.vol0[order], sc.log_E[order], sc.nu[order], sc.mat_id[order])
+    B.mpm_step_n(ctx, p, n_steps)
+    torch.cuda.synchronize()
+    d = B.mpm_get_diagnostics(ctx)
+    assert d["nonfinite"] == 0 and d["out_of_grid"] == 0 and d["order_fallbacks"] == 0, d
+    return p, d
+
+
+@pytest.mark.parametrize("tile_cap", [0, 64])
+def test_repeated_runs_are_bitwise_equal(tile_cap):
+    """Two runs from the same input; with tile_cap = 64 nearly every item
+    exceeds its LDS tiles, so G2P reads and P2G adds node by node in global
+    memory (the 64-bit fixed-point grid directly)."""
+    sc = pair_scene()
+    a, da = run_step_n(sc, 40, tile_cap=tile_cap)
+    b, _ = run_step_n(sc, 40, tile_cap=tile_cap)
+    if tile_cap:
+        assert da["tile_overflow"] > 0
+    assert_same_bits(state_bits(a), state_bits(b), "two runs")
+
+
+def test_caller_order_does_not_change_the_bits():
+    """The caller's particle order changes the atomics' order and the
+    counting sort's slots; the deterministic sort orders each cell by index,
+    and the state in caller order must come out the same."""
+    sc = pair_scene(30_000)
+    order = np.random.default_rng(5).permutation(sc.n)
+    a, _ = run_step_n(sc, 30)
+    b, _ = run_step_n(sc, 30, order=order)
+    inv = np.argsort(order)
+    bs = [x[inv] for x in state_bits(b)]
+    # the within-cell order follows the caller index, which the permutation
+    # changes, so the grouping of particles into items differs: the P2G sums
+    # are exact either way, and every per-particle path must agree bitwise
+    assert_same_bits(state_bits(a), bs, "caller order")
+
+
+def test_resident_calls_split_equal_one_call():
+    """mpm_advance(12) + mpm_advance(8) against mpm_advance(20), re-sorting
+    every 6 substeps across the call boundary."""
+    sc = pair_scene(30_000)
+    outs = []
+    for splits in ((12, 8), (20,)):
+        ctx = B.init_from_scene(sc, sort_every=6, deterministic=True)
+        p = B.Particles.from_scene(sc)
+        B.mpm_load(ctx, p)
+        for n in splits:
+            B.mpm_advance(ctx, n)
+        B.mpm_store(ctx, p)
+        torch.cuda.synchronize()
+        outs.append(state_bits(p))
+    assert_same_bits(outs[0], outs[1], "split resident run")
+
+
+def test_batched_context_equals_each_scene_alone():
+    """Three candidate scenes of different sizes in one context against
+    each in a context of its own, through mpm_step_n and through the
+    resident path."""
+    sc = scenes.make_scene("candidate_batch", n_batch=3, grid_res=32, n_min=3000, n_max=9000)
+    off = sc.batch_offsets
+    batched, _ = run_step_n(sc, 25)
+    got = state_bits(batched)
+    for b in range(3):
+        alone, _ = run_step_n(sc.subset(b), 25)
+        assert_same_bits([g[off[b]:off[b + 1]] for g in got], state_bits(alone), f"scene {b}, step_n")
+    ctx = B.init_from_scene(sc, sort_every=6, deterministic=True)
+    p = B.Particles.from_scene(sc)
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 25)
+    B.mpm_store(ctx, p)
+    torch.cuda.synchronize()
+    res = state_bits(p)
+    for b in range(3):
+        sub = sc.subset(b)
+        c1 = B.init_from_scene(sub, sort_every=6, deterministic=True)
+        q = B.Particles.from_scene(sub)
+        B.mpm_load(c1, q)
+        B.mpm_advance(c1, 25)
+        B.mpm_store(c1, q)
+        torch.cuda.synchronize()
+        assert_same_bits([r[off[b]:off[b + 1]] for r in res], state_bits(q), f"scene {b}, resident")
+
+
+def test_deterministic_substep_matches_the_oracle():
+    """One substep in deterministic mode against the oracle, to the same
+    element-wise bar as the default mode."""
+    sc = pair_scene(8_000)
+    p, _ = run_step_n(sc, 1)
+    errs, _ = compare_substep((sc.x, sc.v, sc.C, sc.F), p.state_numpy(), None, O.Params.from_scene(sc), sc.mass)
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert not parity_failures(errs, TOL_SUBSTEP), errs
+
+
+def test_deterministic_state_is_close_to_the_default_mode():
+    sc = pair_scene(30_000)
+    a, _ = run_step_n(sc, 30, det=True)
+    b, _ = run_step_n(sc, 30, det=False)
+    xa, xb = a.state_numpy()[0], b.state_numpy()[0]
+    da, db = xa - sc.x, xb - sc.x
+    e = rel_err(da, db, 1e-30)
+    print("displacement rel diff det vs default", e, flush=True)
+    assert e <= 1e-4
+
+
+def test_deterministic_backward_runs_and_matches_the_default_mode():
+    """The taped forward and mpm_backward in deterministic mode (the
+    recompute uses the deterministic launches): the parameter gradients
+    agree with the default mode's within the rounding of the forward."""
+    sc = pair_scene(8_000)
+    grads = []
+    for det in (True, False):
+        ctx = B.init_from_scene(sc, sort_every=6, deterministic=det)
+        p = B.Particles.from_scene(sc)
+        tape = torch.empty(B.mpm_tape_size(ctx, 12, 4) // 4 + 64, dtype=torch.float32, device="cuda")
+        B.mpm_step_n(ctx, p, 12, tape=tape, checkpoint_every=4)
+        gl, gn = torch.empty(sc.n, device="cuda"), torch.empty(sc.n, device="cuda")
+        B.mpm_backward(ctx, p, tape, 12, g_x=torch.ones_like(p.x), g_log_E=gl, g_nu=gn)
+        torch.cuda.synchronize()
+        grads.append((gl.cpu().numpy(), gn.cpu().numpy()))
+    for a, b in zip(*grads):
+        e = rel_err(a, b, 1e-30)
+        print("gradient rel diff", e, flush=True)
+        assert e <= 1e-3
