@@ -454,13 +454,15 @@ def summarize_counters(csv_paths, kernel="k_substep<1, 0>", n_particles=2_000_00
 def atomic_probe():
     """Rates of the atomic operations the fused kernel is built on, measured
     on this device in this run (libmpm_probes.so): LDS 64-bit adds with
-    lane-consecutive words and in the P2G scatter's node pattern, and global
-    FP32 adds to lane-distinct floats and to the 4 channels of a node."""
+    lane-consecutive words and in the P2G scatter's node pattern (and the
+    32-bit integer and FP32 alternatives), and global FP32 adds to
+    lane-distinct floats and to the 4 channels of a node."""
     from paper_2602_01723_amd import probes as P
     out = {}
-    for name, pat in (("lds_add_u64_consecutive", 0), ("lds_add_u64_p2g_pattern", 1)):
-        best = max(P.lds_add_u64(pat)["lane_ops_per_s"] for _ in range(3))
-        out[name] = best
+    for word in ("u64", "u32", "f32"):
+        for name, pat in ((f"lds_add_{word}_consecutive", 0), (f"lds_add_{word}_p2g_pattern", 1)):
+            best = max(P.lds_add(pat, word)["lane_ops_per_s"] for _ in range(3))
+            out[name] = best
     for name, pat in (("global_add_f32_distinct", 0), ("global_add_f32_node_channels", 1)):
         best = max(P.global_add_f32(pat)["lane_ops_per_s"] for _ in range(3))
         out[name] = best

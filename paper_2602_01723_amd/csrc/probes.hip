@@ -11,6 +11,8 @@
 //     addresses and in the flush pattern (the 4 channels of a node).
 // Each probe runs two workgroups of 256 threads per CU (the substep kernel's
 // occupancy) and returns the elapsed time and the lane operations done.
+// The LDS probe also runs with 32-bit integer and FP32 words (ds_add_u32,
+// ds_add_f32), the alternatives to the 64-bit tile words.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -25,11 +27,14 @@ __device__ __forceinline__ int rot3(int s, int k) {
   return r >= 3 ? r - 3 : r;
 }
 
-// pattern 0: lane-consecutive 64-bit words; pattern 1: the P2G scatter's
-// node order.  Every address stays inside the 4 x 1331-word tile.
-__global__ __launch_bounds__(kThreads, 2) void k_lds_add_u64(int pattern, int reps, unsigned long long* sink) {
-  __shared__ unsigned long long tile[4 * kTile];
-  for (int t = threadIdx.x; t < 4 * kTile; t += kThreads) tile[t] = 0ull;
+// pattern 0: lane-consecutive words; pattern 1: the P2G scatter's node
+// order.  Every address stays inside the 4 x 1331-word tile.  T is the
+// word: unsigned long long (ds_add_u64), unsigned (ds_add_u32) or float
+// (ds_add_f32).
+template <typename T>
+__global__ __launch_bounds__(kThreads, 2) void k_lds_add(int pattern, int reps, T* sink) {
+  __shared__ T tile[4 * kTile];
+  for (int t = threadIdx.x; t < 4 * kTile; t += kThreads) tile[t] = (T)0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // P2G geometry: box of 6^3 base cells -> 8^3 nodes, x stride 8*8+3
@@ -39,7 +44,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_lds_add_u64(int pattern, int re
   const int a1 = cx * SX + cy * pz + cz;  // base node of the cell's stencil (< 3*67+3*8+3+... < 1331)
   const int g = lane % 27;
   const int gs[3] = {g / 9, (g / 3) % 3, g % 3};
-  const unsigned long long v = 0x4338000000000001ull + (unsigned long long)threadIdx.x;
+  const T v = (T)(1 + (threadIdx.x & 7));
   for (int it = 0; it < reps; ++it) {
 #pragma unroll
     for (int kx = 0; kx < 3; ++kx)
@@ -87,28 +92,40 @@ int device_cus(int* cus) {
   return 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-// LDS 64-bit adds: pattern 0 (lane-consecutive) or 1 (P2G tile pattern);
-// reps rounds of 108 adds per thread.  *ms = kernel time, *lane_ops = adds.
-int probe_lds_add_u64(int pattern, int reps, void* sink, float* ms, double* lane_ops) {
+template <typename T>
+int lds_probe(int pattern, int reps, void* sink, float* ms, double* lane_ops) {
   if ((pattern != 0 && pattern != 1) || reps < 1 || !sink || !ms || !lane_ops) return -1;
   int cus = 0;
   if (device_cus(&cus)) return -3;
   const int blocks = 2 * cus;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -3;
-  k_lds_add_u64<<<blocks, kThreads>>>(pattern, 1, (unsigned long long*)sink);  // warm-up
+  k_lds_add<T><<<blocks, kThreads>>>(pattern, 1, (T*)sink);  // warm-up
   hipEventRecord(e0, nullptr);
-  k_lds_add_u64<<<blocks, kThreads>>>(pattern, reps, (unsigned long long*)sink);
+  k_lds_add<T><<<blocks, kThreads>>>(pattern, reps, (T*)sink);
   hipEventRecord(e1, nullptr);
   const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(ms, e0, e1) == hipSuccess;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *lane_ops = (double)blocks * kThreads * reps * 108.0;
   return ok && hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace
+
+extern "C" {
+
+// LDS adds: pattern 0 (lane-consecutive) or 1 (P2G tile pattern); reps
+// rounds of 108 adds per thread.  *ms = kernel time, *lane_ops = adds.
+// sink: device memory of at least 2 x (number of CUs) 64-bit words.
+int probe_lds_add_u64(int pattern, int reps, void* sink, float* ms, double* lane_ops) {
+  return lds_probe<unsigned long long>(pattern, reps, sink, ms, lane_ops);
+}
+int probe_lds_add_u32(int pattern, int reps, void* sink, float* ms, double* lane_ops) {
+  return lds_probe<unsigned>(pattern, reps, sink, ms, lane_ops);
+}
+int probe_lds_add_f32(int pattern, int reps, void* sink, float* ms, double* lane_ops) {
+  return lds_probe<float>(pattern, reps, sink, ms, lane_ops);
 }
 
 // Global FP32 adds into grid (device, `floats` floats, multiple of 4):

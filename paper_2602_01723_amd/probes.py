@@ -25,8 +25,10 @@ def load(path: str = PROBES_PATH):
             torch.cuda.init()
         lib = ctypes.CDLL(path)
         fp, dp = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
-        lib.probe_lds_add_u64.restype = ctypes.c_int
-        lib.probe_lds_add_u64.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, fp, dp]
+        for word in ("u64", "u32", "f32"):
+            fn = getattr(lib, f"probe_lds_add_{word}")
+            fn.restype = ctypes.c_int
+            fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, fp, dp]
         lib.probe_global_add_f32.restype = ctypes.c_int
         lib.probe_global_add_f32.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_int64, fp, dp]
@@ -34,16 +36,22 @@ def load(path: str = PROBES_PATH):
     return _lib
 
 
-def lds_add_u64(pattern: int, reps: int = 200) -> dict:
-    """Rate of ds_add_u64 (lane operations per second): pattern 0 lane-
-    consecutive words, 1 the P2G scatter's node order."""
+def lds_add(pattern: int, word: str = "u64", reps: int = 200) -> dict:
+    """Rate of LDS atomic adds (lane operations per second) of one word type
+    ("u64": ds_add_u64, "u32": ds_add_u32, "f32": ds_add_f32): pattern 0
+    lane-consecutive words, 1 the P2G scatter's node order."""
     import torch
     sink = torch.empty(4096, dtype=torch.int64, device="cuda")
     ms, ops = ctypes.c_float(), ctypes.c_double()
-    rc = load().probe_lds_add_u64(int(pattern), int(reps), sink.data_ptr(), ctypes.byref(ms), ctypes.byref(ops))
+    fn = getattr(load(), f"probe_lds_add_{word}")
+    rc = fn(int(pattern), int(reps), sink.data_ptr(), ctypes.byref(ms), ctypes.byref(ops))
     if rc:
-        raise RuntimeError(f"probe_lds_add_u64 failed ({rc})")
+        raise RuntimeError(f"probe_lds_add_{word} failed ({rc})")
     return dict(lane_ops_per_s=ops.value / (ms.value * 1e-3), ms=ms.value, lane_ops=ops.value)
+
+
+def lds_add_u64(pattern: int, reps: int = 200) -> dict:
+    return lds_add(pattern, "u64", reps)
 
 
 def global_add_f32(pattern: int, reps: int = 8, mib: int = 256) -> dict:
