@@ -122,7 +122,9 @@ typedef struct {
  * contribution, rounded to one fixed-point scale per scene (a power of two
  * set by B_b and the scene's particle count), as 64-bit integers, which sum
  * exactly in any order; the particles of each cell are ordered by index at
- * every sort.  Costs a second P2G-side launch per substep and 32 B per grid
+ * every sort; and the stress of a substep is taken from F as stored in
+ * float32, so a run split at any call boundary (mpm_step_n, mpm_advance,
+ * mpm_store / mpm_load) equals the run in one piece.  Costs a second P2G-side launch per substep and 32 B per grid
  * node of workspace.  The backward's adjoint scatter stays in floating
  * point and is not covered.  A cell of more than 4096 particles keeps the
  * order of the atomics (counted in mpm_diag.order_fallbacks). */

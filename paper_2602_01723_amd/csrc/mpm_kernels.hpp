@@ -345,6 +345,10 @@ __device__ __forceinline__ void block_minmax(const int* lo, const int* hi, int* 
 template <int MODE, int DET = kDetOff>
 __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   constexpr bool kMeasure = DET == kDetMeasure, kAccum = DET == kDetAccumulate;
+  // deterministic modes take the stress of the stored (float32) F, as a
+  // P2G-only launch from stored state does, so that a run split at any call
+  // boundary equals the run in one piece
+  constexpr bool kStressFromStored = (DET != kDetOff) && (MODE == kFused);
   __shared__ unsigned long long ptile[4 * kTileCapMax];  // P2G fixed-point accumulators: mv.x, mv.y, mv.z, m
   __shared__ float gtile[3 * kTileCapMax];               // G2P node velocities
   __shared__ int red[8 * (kBlock / 64)];
@@ -616,7 +620,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
                 for (int k = 0; k < 3; ++k) acc += (double)a.dt * (double)Cp[3 * r + k] * Fd[3 * k + c];
                 Ftr[3 * r + c] = acc;
               }
-            update_and_stress(mat, mu, lam, Ftr, true, MODE == kFused, Fd, tau);
+            update_and_stress(mat, mu, lam, Ftr, true, MODE == kFused && !kStressFromStored, Fd, tau);
             float Ff[9];
             bool fin = true;
 #pragma unroll
@@ -662,10 +666,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
           if (ok && in_grid) {
             // A = m C - 4/dx^2 dt V0 tau, folded with dx for the node offsets
             mass = prm.x;
-            if (MODE == kP2G) {
+            if (MODE == kP2G || kStressFromStored) {
               double Fs[9];
 #pragma unroll
-              for (int k = 0; k < 9; ++k) Fs[k] = Fd[k];
+              for (int k = 0; k < 9; ++k) Fs[k] = kStressFromStored ? (double)(float)Fd[k] : Fd[k];
               update_and_stress(mat, mu, lam, Fs, false, true, Fd, tau);
             }
             const float ks = 4.0f * inv_dx * inv_dx * a.dt * prm.y;

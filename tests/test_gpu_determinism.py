@@ -2,11 +2,11 @@
 
 With the flag the forward state is a function of the inputs alone: the P2G
 sums are 64-bit integers at one fixed-point scale per scene (exact in any
-order of the atomics) and each cell's particles are ordered by index at
-every sort.  Checked bit for bit: repeated runs, a resident run split into
-calls against one call (re-sorts in between), a batched context against
-each scene alone, and the mpm_step_n path against itself under a different
-particle order of the caller.  The mode keeps the substep's parity with the
+order of the atomics), each cell's particles are ordered by index at
+every sort, and the stress is taken from the stored float32 F.  Checked bit
+for bit: repeated runs, the caller's particle order permuted, resident and
+mpm_step_n runs split into calls against one call, a stored state loaded
+into a new context, and a batched context against each scene alone.  The mode keeps the substep's parity with the
 oracle, and its state stays within rounding of the default mode."""
 import numpy as np
 import pytest
@@ -98,6 +98,47 @@ def test_resident_calls_split_equal_one_call():
         torch.cuda.synchronize()
         outs.append(state_bits(p))
     assert_same_bits(outs[0], outs[1], "split resident run")
+
+
+def test_step_n_calls_split_equal_one_call():
+    """mpm_step_n(12) then mpm_step_n(18) on the same arrays against one
+    mpm_step_n(30): the second call sorts the stored state afresh and starts
+    with a P2G-only launch from the stored float32 state, which in
+    deterministic mode is what the fused launch computes as well."""
+    sc = pair_scene(30_000)
+    a, _ = run_step_n(sc, 30)
+    ctx = B.init_from_scene(sc, sort_every=6, deterministic=True)
+    p = B.Particles.from_scene(sc)
+    B.mpm_step_n(ctx, p, 12)
+    B.mpm_step_n(ctx, p, 18)
+    torch.cuda.synchronize()
+    assert_same_bits(state_bits(a), state_bits(p), "mpm_step_n 12 + 18")
+
+
+def test_store_and_load_into_a_new_context_resume_bitwise():
+    """mpm_advance(10), mpm_store, a new context, mpm_load, mpm_advance(10)
+    against mpm_advance(20) in one context."""
+    sc = pair_scene(30_000)
+    outs = []
+    ctx = B.init_from_scene(sc, sort_every=6, deterministic=True)
+    p = B.Particles.from_scene(sc)
+    B.mpm_load(ctx, p)
+    B.mpm_advance(ctx, 20)
+    B.mpm_store(ctx, p)
+    torch.cuda.synchronize()
+    outs.append(state_bits(p))
+    q = B.Particles.from_scene(sc)
+    c1 = B.init_from_scene(sc, sort_every=6, deterministic=True)
+    B.mpm_load(c1, q)
+    B.mpm_advance(c1, 10)
+    B.mpm_store(c1, q)
+    c2 = B.init_from_scene(sc, sort_every=6, deterministic=True)
+    B.mpm_load(c2, q)
+    B.mpm_advance(c2, 10)
+    B.mpm_store(c2, q)
+    torch.cuda.synchronize()
+    outs.append(state_bits(q))
+    assert_same_bits(outs[0], outs[1], "store + load resume")
 
 
 def test_batched_context_equals_each_scene_alone():
