@@ -124,10 +124,13 @@ typedef struct {
  * exactly in any order; the particles of each cell are ordered by index at
  * every sort; and the stress of a substep is taken from F as stored in
  * float32, so a run split at any call boundary (mpm_step_n, mpm_advance,
- * mpm_store / mpm_load) equals the run in one piece.  Costs a second P2G-side launch per substep and 32 B per grid
- * node of workspace.  The backward's adjoint scatter stays in floating
- * point and is not covered.  A cell of more than 4096 particles keeps the
- * order of the atomics (counted in mpm_diag.order_fallbacks). */
+ * mpm_store / mpm_load) equals the run in one piece.  mpm_backward is
+ * deterministic too: its adjoint scatter into the grid adds at one
+ * fixed-point scale per scene, set by a bound of the contributions taken
+ * before the scatter.  Costs a second P2G-side launch per substep, a bound
+ * pass per reversed substep and 32 B per grid node of workspace.  A cell of
+ * more than 4096 particles keeps the order of the atomics (counted in
+ * mpm_diag.order_fallbacks). */
 #define MPM_FLAG_DETERMINISTIC 1u
 
 typedef struct {

@@ -30,13 +30,15 @@ def loss_weights(offsets) -> np.ndarray:
 class Evaluation:
     """Forward + loss + adjoint of one context (all scenes of `sc`)."""
 
-    def __init__(self, sc, steps: int, K: int, x_target, log_E=None, nu=None, tuning=None, stream=None):
+    def __init__(self, sc, steps: int, K: int, x_target, log_E=None, nu=None, tuning=None, stream=None,
+                 deterministic=False):
         import torch
         self.sc = sc
         self.steps = int(steps)
         self.K = int(K)
         offs = None if sc.n_batch == 1 else sc.batch_offsets
-        self.ctx = B.mpm_init(sc.grid_res, sc.dt, sc.materials, sc.n, offs, sc.gravity, sc.bound)
+        self.ctx = B.mpm_init(sc.grid_res, sc.dt, sc.materials, sc.n, offs, sc.gravity, sc.bound,
+                              deterministic=deterministic)
         if tuning:
             B.mpm_set_tuning(self.ctx, **tuning)
         self.p = B.Particles.from_arrays(sc.x, sc.v, sc.C, sc.F, sc.mass, sc.vol0,
@@ -103,11 +105,11 @@ class Evaluation:
         return self.g_log_E.cpu().numpy(), self.g_nu.cpu().numpy()
 
 
-def target_positions(sc, steps, log_E, nu) -> np.ndarray:
+def target_positions(sc, steps, log_E, nu, deterministic=False) -> np.ndarray:
     """Final positions of the scene advanced with other (hidden) parameters."""
     import torch
     offs = None if sc.n_batch == 1 else sc.batch_offsets
-    ctx = B.mpm_init(sc.grid_res, sc.dt, sc.materials, sc.n, offs, sc.gravity, sc.bound)
+    ctx = B.mpm_init(sc.grid_res, sc.dt, sc.materials, sc.n, offs, sc.gravity, sc.bound, deterministic=deterministic)
     p = B.Particles.from_arrays(sc.x, sc.v, sc.C, sc.F, sc.mass, sc.vol0, log_E, nu, sc.mat_id)
     B.mpm_step_n(ctx, p, steps)
     torch.cuda.synchronize()
@@ -121,7 +123,7 @@ def per_particle(values_per_scene, offsets) -> np.ndarray:
     return out
 
 
-def plain_evaluations(sc, steps, K, x_target, tuning=None) -> List[Evaluation]:
+def plain_evaluations(sc, steps, K, x_target, tuning=None, deterministic=False) -> List[Evaluation]:
     """One single-scene Evaluation per candidate of the batched scene `sc`,
     all on one shared stream (they run one after the other)."""
     import torch
@@ -130,5 +132,6 @@ def plain_evaluations(sc, steps, K, x_target, tuning=None) -> List[Evaluation]:
     for b in range(sc.n_batch):
         sub = sc.subset(b)
         lo, hi = int(sc.batch_offsets[b]), int(sc.batch_offsets[b + 1])
-        evs.append(Evaluation(sub, steps, K, np.asarray(x_target)[lo:hi], tuning=tuning, stream=stream))
+        evs.append(Evaluation(sub, steps, K, np.asarray(x_target)[lo:hi], tuning=tuning, stream=stream,
+                              deterministic=deterministic))
     return evs

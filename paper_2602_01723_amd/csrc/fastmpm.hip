@@ -1088,7 +1088,21 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
                                                    tl.gn, N);
         LAUNCH_CHECK(ctx, "k_adj_return_map");
       }
-      {
+      if (ctx->det) {  // exact sums of the grid-velocity adjoint at one scale per scene
+        ProfScope pa(ctx, s, 6);
+        rc = fill_u32(ctx, ctx->fxb, 2 * (int64_t)ctx->B, s);
+        if (rc) return rc;
+        b.fxb = ctx->fxb;
+        b.fxk = ctx->fxk;
+        b.gfx = ctx->gfx;
+        fmpm::k_adj_bound<<<(unsigned)std::max<int64_t>(ctx->max_chunks, 1), 256, 0, s>>>(b, items);
+        LAUNCH_CHECK(ctx, "k_adj_bound");
+        fmpm::k_adj_g2p<true><<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
+        LAUNCH_CHECK(ctx, "k_adj_g2p");
+        fmpm::k_fx_grid<<<blocks_for(ctx->nodes, 256), 256, 0, s>>>(ctx->gfx, tl.vhb, ctx->nodes,
+                                                                     (int64_t)ctx->n * ctx->n * ctx->n, ctx->fxb,
+                                                                     ctx->fxk);
+      } else {
         ProfScope pa(ctx, s, 6);
         fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
       }

@@ -62,6 +62,12 @@ struct AdjArgs {
   int bound;
   float dt;
   float g[3];
+  // deterministic mode (k_adj_g2p<true>): per-scene bound of the
+  // grid-velocity adjoint contributions (float bits, both slots of the
+  // scene), the scenes' range factors and the 64-bit fixed-point grid
+  unsigned* fxb;
+  const double* fxk;
+  unsigned long long* gfx;
 };
 
 __device__ __forceinline__ void bspline_dw(float f, float* dw) {
@@ -571,8 +577,48 @@ struct AdjItems {
   const int* box_in;      // per-item base-cell boxes of the state (NULL: a pass over x)
 };
 
+// Deterministic mode: each scene's bound of |w (vbt + D Cbt dpos)| over its
+// particles and their 27 nodes (w <= 0.75^3, |dpos| <= 1.5 dx per axis),
+// raised into both of the scene's slots of a.fxb.  One workgroup per item.
+__global__ __launch_bounds__(256) void k_adj_bound(AdjArgs a, AdjItems it) {
+  const int item = blockIdx.x;
+  if (item >= *it.n_items) return;
+  const int64_t N = a.N;
+  const float dx = 1.0f / (float)a.n, D = 4.0f * (float)a.n * (float)a.n;
+  const int scene = it.item_batch[item];
+  for (int i = it.item_start[item] + (int)threadIdx.x; i < it.item_start[item + 1]; i += blockDim.x) {
+    int b[3];
+    float f[3];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ok &= cell_of(a.x[k * N + i], a.n, b[k], f[k]);
+    if (!ok) continue;
+    float bnd = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      float row = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float t = a.aC[(3 * r + c) * N + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t += a.dt * a.aF[(3 * r + k) * N + i] * a.F[(3 * c + k) * N + i];
+        row += fabsf(t);
+      }
+      bnd = fmaxf(bnd, fabsf(a.av[r * N + i] + a.dt * a.ax[r * N + i]) + D * 1.5f * dx * row);
+    }
+    bnd *= 0.421875f;
+    if (bnd <= 3.0e38f) {  // NaN and overflow stay out of the scale
+      raise_max(&a.fxb[2 * scene], bnd);
+      raise_max(&a.fxb[2 * scene + 1], bnd);
+    }
+  }
+}
+
+template <bool DET = false>
 __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
   __shared__ double ptile[3 * kTileCapMax];
+  // deterministic mode: the same LDS as 64-bit fixed point at the scene's scale
+  unsigned long long* const pu = reinterpret_cast<unsigned long long*>(ptile);
   __shared__ float gtile[3 * kTileCapMax];
   __shared__ int red[8 * (kBlock / 64)];
   __shared__ int item_s;
@@ -595,6 +641,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
     if (item >= n_items) break;
     const int start = it.item_start[item], end = it.item_start[item + 1];
     const int64_t gbase = (int64_t)it.item_batch[item] * n * n * n;
+    double s_fx = 1.0;
+    if (DET) {
+      const int scene = it.item_batch[item];
+      s_fx = fx_scale(a.fxk[scene] * (double)__uint_as_float(a.fxb[2 * scene]));
+    }
     int box[6];
     if (it.box_in) {
 #pragma unroll
@@ -777,13 +828,25 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
             }
             if (lds) {
               const int t = a0 + ox * sz + oy * gz + oz;
+              if (DET) {
 #pragma unroll
-              for (int r = 0; r < 3; ++r) atomicAdd(&ptile[r * kTileCapMax + t], (double)gv[r]);
+                for (int r = 0; r < 3; ++r) atomicAdd(&pu[r * kTileCapMax + t], fx_bits(gv[r], s_fx));
+              } else {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) atomicAdd(&ptile[r * kTileCapMax + t], (double)gv[r]);
+              }
             } else {
               const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
-              float* gp = (float*)&a.vhb[gbase + ((int64_t)ix * n + iy) * n + iz];
+              const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
+              if (DET) {
 #pragma unroll
-              for (int r = 0; r < 3; ++r) atomicAdd(gp + r, gv[r]);
+                for (int r = 0; r < 3; ++r)
+                  atomicAdd(a.gfx + 4 * node + r, (unsigned long long)fx_value(fx_bits(gv[r], s_fx)));
+              } else {
+                float* gp = (float*)&a.vhb[node];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) atomicAdd(gp + r, gv[r]);
+              }
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -801,15 +864,25 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
     if (lds) {
       __syncthreads();
       for (int t = threadIdx.x; t < GT; t += kBlock) {
-        const double v0 = ptile[t], v1 = ptile[kTileCapMax + t], v2 = ptile[2 * kTileCapMax + t];
-        if (v0 == 0.0 && v1 == 0.0 && v2 == 0.0) continue;
         const int ti = t / sz, tr = t - ti * sz;
         const int tj = tr / gz, tk = tr - tj * gz;
         if (tj >= gy) continue;  // padding
-        float* gp = (float*)&a.vhb[gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk)];
-        atomicAdd(gp + 0, (float)v0);
-        atomicAdd(gp + 1, (float)v1);
-        atomicAdd(gp + 2, (float)v2);
+        const int64_t node = gbase + ((int64_t)(box[0] + ti) * n + (box[1] + tj)) * n + (box[2] + tk);
+        if (DET) {  // integer sums at the scene's scale: exact, in any order
+          const long long q0 = fx_value(pu[t]), q1 = fx_value(pu[kTileCapMax + t]),
+                          q2 = fx_value(pu[2 * kTileCapMax + t]);
+          if (q0 == 0 && q1 == 0 && q2 == 0) continue;
+          atomicAdd(a.gfx + 4 * node + 0, (unsigned long long)q0);
+          atomicAdd(a.gfx + 4 * node + 1, (unsigned long long)q1);
+          atomicAdd(a.gfx + 4 * node + 2, (unsigned long long)q2);
+        } else {
+          const double v0 = ptile[t], v1 = ptile[kTileCapMax + t], v2 = ptile[2 * kTileCapMax + t];
+          if (v0 == 0.0 && v1 == 0.0 && v2 == 0.0) continue;
+          float* gp = (float*)&a.vhb[node];
+          atomicAdd(gp + 0, (float)v0);
+          atomicAdd(gp + 1, (float)v1);
+          atomicAdd(gp + 2, (float)v2);
+        }
       }
     }
   }

@@ -13,6 +13,7 @@ import pytest
 import torch
 
 from oracle import mpm_oracle as O
+from paper_2602_01723_amd import batch as BT
 from paper_2602_01723_amd import binding as B
 from paper_2602_01723_amd import scenes
 from tests.parity import TOL_SUBSTEP, compare_substep, parity_failures, rel_err
@@ -210,3 +211,56 @@ def test_deterministic_backward_runs_and_matches_the_default_mode():
         e = rel_err(a, b, 1e-30)
         print("gradient rel diff", e, flush=True)
         assert e <= 1e-3
+
+
+def test_batched_graph_gradients_equal_plain_bitwise():
+    """The batched forward + loss + adjoint, captured into one hipGraph and
+    replayed, against its eager run and against each candidate evaluated
+    alone: with the deterministic adjoint scatter (exact fixed-point sums of
+    the grid-velocity adjoint per scene) every gradient agrees bit for bit."""
+    sc = scenes.make_scene("candidate_batch", n_batch=3, grid_res=32, n_min=3000, n_max=9000)
+    steps, K = 30, 10
+    tl = BT.per_particle(sc.extras["target_log_E"], sc.batch_offsets)
+    tn = BT.per_particle(sc.extras["target_nu"], sc.batch_offsets)
+    xt = BT.target_positions(sc, steps, tl, tn, deterministic=True)
+    ev = BT.Evaluation(sc, steps, K, xt, deterministic=True)
+    ev.run_eager()
+    torch.cuda.synchronize()
+    gl_e, gn_e = (g.copy() for g in ev.gradients())
+    assert np.all(np.isfinite(gl_e)) and np.abs(gl_e).max() > 0
+    ev.capture()
+    for rep in range(2):
+        ev.run_graph()
+        torch.cuda.synchronize()
+        gl, gn = ev.gradients()
+        assert np.array_equal(gl.view(np.uint32), gl_e.view(np.uint32)), f"replay {rep}: log E gradients differ"
+        assert np.array_equal(gn.view(np.uint32), gn_e.view(np.uint32)), f"replay {rep}: nu gradients differ"
+        _ = torch.ones(1000, device="cuda").sum().item()
+    off = sc.batch_offsets
+    for b, pe in enumerate(BT.plain_evaluations(sc, steps, K, xt, deterministic=True)):
+        pe.run_eager()
+        torch.cuda.synchronize()
+        g1, n1 = pe.gradients()
+        lo, hi = off[b], off[b + 1]
+        d1 = int(np.count_nonzero(g1.view(np.uint32) != gl_e[lo:hi].view(np.uint32)))
+        d2 = int(np.count_nonzero(n1.view(np.uint32) != gn_e[lo:hi].view(np.uint32)))
+        print(f"candidate {b}: {d1} log E and {d2} nu gradients differ", flush=True)
+        assert d1 == 0 and d2 == 0
+
+
+def test_deterministic_gradients_repeat_bitwise():
+    """Two taped runs and backwards from the same input, with a return map
+    in the scene: the parameter gradients agree bit for bit."""
+    sc = pair_scene(8_000)
+    outs = []
+    for _ in range(2):
+        ctx = B.init_from_scene(sc, sort_every=6, deterministic=True)
+        p = B.Particles.from_scene(sc)
+        tape = torch.empty(B.mpm_tape_size(ctx, 12, 4) // 4 + 64, dtype=torch.float32, device="cuda")
+        B.mpm_step_n(ctx, p, 12, tape=tape, checkpoint_every=4)
+        gl, gn = torch.empty(sc.n, device="cuda"), torch.empty(sc.n, device="cuda")
+        B.mpm_backward(ctx, p, tape, 12, g_x=torch.ones_like(p.x), g_log_E=gl, g_nu=gn)
+        torch.cuda.synchronize()
+        outs.append([gl.cpu().numpy().view(np.uint32), gn.cpu().numpy().view(np.uint32)])
+    for k, (a, b) in enumerate(zip(outs[0], outs[1])):
+        assert int(np.count_nonzero(a != b)) == 0, f"gradient {k} differs"
