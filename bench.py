@@ -223,6 +223,43 @@ def deterministic_timing(sc, substeps=20, reps=3):
     return out
 
 
+def deterministic_batched_timing(n_batch=64, steps=100, K=20, reps=2):
+    """Cost of MPM_FLAG_DETERMINISTIC on the batched forward + loss + adjoint
+    (the 64-candidate batch, fixed launch tuning, eager on one stream): wall
+    time per evaluation and the mean time per launch of each timed kernel
+    class, with and without the flag."""
+    import torch
+
+    from paper_2602_01723_amd import batch as BT
+    from paper_2602_01723_amd import binding as B
+    from paper_2602_01723_amd import scenes
+    sc = scenes.make_scene("candidate_batch", n_batch=n_batch, n_substeps=steps)
+    tl = BT.per_particle(sc.extras["target_log_E"], sc.batch_offsets)
+    tn = BT.per_particle(sc.extras["target_nu"], sc.batch_offsets)
+    xt = BT.target_positions(sc, steps, tl, tn)
+    out = {"workload": f"{n_batch} candidates, {sc.n} particles, {steps} substeps (checkpoints every {K}) + "
+                       f"position loss + backward, eager, mean of {reps}"}
+    for det in (False, True):
+        ev = BT.Evaluation(sc, steps, K, xt, tuning=BATCH_TUNING, deterministic=det)
+        ev.run_eager()
+        torch.cuda.synchronize()
+        B.mpm_profile(ev.ctx, True)
+        B.mpm_profile_read(ev.ctx)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ev.run_eager()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        prof = B.mpm_profile_read(ev.ctx)
+        out["deterministic" if det else "default"] = {
+            "ms_per_evaluation": wall * 1e3,
+            "us_per_launch": {k: round(v[0] / max(v[1], 1) * 1e3, 1) for k, v in prof.items() if v[1]}}
+        del ev
+        torch.cuda.empty_cache()
+    out["slowdown"] = out["deterministic"]["ms_per_evaluation"] / out["default"]["ms_per_evaluation"]
+    return out
+
+
 MODEL_VARIANTS = (("fixed_corotated", 0, 0), ("hencky", 1, 0), ("neo_hookean", 2, 0), ("stvk", 3, 0),
                   ("fluid_elastic", 4, 0), ("volume", 5, 0), ("hencky+von_mises", 1, 1),
                   ("hencky+drucker_prager", 1, 2), ("fixed_corotated+fluid", 0, 3), ("hencky+sigma", 1, 4))
@@ -753,7 +790,8 @@ def main():
     ap.add_argument("--mcis-only", action="store_true", help="time only the MCIS interior fill and exit")
     ap.add_argument("--no-ipf", action="store_true", help="skip the candidate-generation timing")
     ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode timing")
-    ap.add_argument("--det-only", action="store_true", help="time only the deterministic mode and exit")
+    ap.add_argument("--det-only", action="store_true",
+                    help="time only the deterministic mode (the 2M scene and the batched forward + adjoint) and exit")
     ap.add_argument("--ipf-only", action="store_true", help="time only the candidate generation and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched vs plain forward + adjoint and exit")
@@ -814,9 +852,9 @@ def main():
         print(json.dumps({"adjoint_counter_run": adjoint_counter_run()}), flush=True)
         return
     if args.det_only:
-        print(json.dumps({"deterministic": deterministic_timing(scenes.make_scene("large_scene",
-                                                                                 n_total=args.n_total))}),
-              flush=True)
+        det = deterministic_timing(scenes.make_scene("large_scene", n_total=args.n_total))
+        det["batched_fwd_bwd"] = deterministic_batched_timing()
+        print(json.dumps({"deterministic": det}), flush=True)
         return
     copy_gbs = copy_probe()
     log(f"  plain 256 MiB copy: {copy_gbs:.0f} GB/s (read + write)")

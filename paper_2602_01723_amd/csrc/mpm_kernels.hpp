@@ -864,18 +864,23 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n, int* counter) {
 // Deterministic mode: the 64-bit fixed-point grid [node][4] -> grid (mv,
 // m) as float4 at each scene's scales (the same fx_scale of the same
 // bounds as the accumulating launch), and the fixed-point grid zeroed for
-// the next accumulation.  per_scene = n^3.
+// the next accumulation.  per_scene = n^3.  The float grid is zero where
+// nothing was added (it was cleared before the launch), so untouched nodes
+// are only read.
 __global__ void k_fx_grid(unsigned long long* gfx, float4* grid, int64_t nodes, int64_t per_scene,
                           const unsigned* fxb, const double* fxk) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nodes) return;
+  ulonglong2* g = reinterpret_cast<ulonglong2*>(gfx + 4 * t);
+  const ulonglong2 a = g[0], c = g[1];
+  if ((a.x | a.y | c.x | c.y) == 0ull) return;
   const int b = (int)(t / per_scene);
   const double is_mom = 1.0 / fx_scale(fxk[b] * (double)__uint_as_float(fxb[2 * b]));
   const double is_mass = 1.0 / fx_scale(fxk[b] * (double)__uint_as_float(fxb[2 * b + 1]));
-  unsigned long long* g = gfx + 4 * t;
-  grid[t] = make_float4((float)((double)(long long)g[0] * is_mom), (float)((double)(long long)g[1] * is_mom),
-                        (float)((double)(long long)g[2] * is_mom), (float)((double)(long long)g[3] * is_mass));
-  g[0] = g[1] = g[2] = g[3] = 0ull;
+  grid[t] = make_float4((float)((double)(long long)a.x * is_mom), (float)((double)(long long)a.y * is_mom),
+                        (float)((double)(long long)c.x * is_mom), (float)((double)(long long)c.y * is_mass));
+  g[0] = make_ulonglong2(0ull, 0ull);
+  g[1] = make_ulonglong2(0ull, 0ull);
 }
 
 // Deterministic mode: order the particles of each cell by source index
