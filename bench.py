@@ -717,7 +717,41 @@ def config_timings():
     out["colliding_pair_200k"] = dict(particles=N, substeps=steps, checkpoint_every=K, seconds_per_gradient=round(t, 4),
                                       grads_per_s=1.0 / t, fwd_bwd_particle_substeps_per_s=N * steps / t,
                                       path="mpm_step_n with tape + mpm_position_loss_grad + mpm_backward")
+    del ctx, p, init, tape, tgt
+    torch.cuda.empty_cache()
+    out["large_domain_512"] = large_domain_timing()
     return out
+
+
+def large_domain_timing(substeps=20):
+    """A large, mostly empty domain: 2,000,000 particles in a cube of side
+    0.125 (about 9 per occupied cell) on a 512^3 grid (134 M nodes, 2.1 GB
+    per grid buffer), resident substeps with the block-sparse grid (the
+    default at this size) and with dense clearing forced."""
+    import torch
+
+    from paper_2602_01723_amd import binding as B
+    from paper_2602_01723_amd import scenes
+    sc = scenes.make_scene("cube_uniform", n=2_000_000, grid_res=512, side=0.125, centre=(0.5, 0.5, 0.5),
+                           dt=2e-5)
+    res = {"particles": sc.n, "grid_res": 512, "substeps": substeps,
+           "path": "mpm_load + mpm_advance(1) + timed mpm_advance(substeps)"}
+    for grid in ("auto", "dense"):
+        ctx = B.init_from_scene(sc, grid=grid)
+        p = B.Particles.from_scene(sc)
+        B.mpm_load(ctx, p)
+        B.mpm_advance(ctx, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.mpm_advance(ctx, substeps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res["sparse_grid" if grid == "auto" else "dense_grid"] = dict(
+            ms_per_substep=t / substeps * 1e3, particle_substeps_per_s=sc.n * substeps / t)
+        del ctx, p
+        torch.cuda.empty_cache()
+    res["speedup"] = res["dense_grid"]["ms_per_substep"] / res["sparse_grid"]["ms_per_substep"]
+    return res
 
 
 def cpu_model() -> str:

@@ -110,7 +110,7 @@ typedef struct {
   float dt;              /* substep, s (> 0) */
   float gravity[3];      /* acceleration, m/s^2, added to grid velocity as dt * g */
   int32_t sort_every;    /* re-sort particles by cell every this many substeps (0 = library default) */
-  uint32_t flags;        /* 0 or MPM_FLAG_DETERMINISTIC */
+  uint32_t flags;        /* 0 or MPM_FLAG_* below */
 } mpm_config;
 
 /* Deterministic forward: the particle state after any sequence of substep
@@ -132,6 +132,18 @@ typedef struct {
  * more than 4096 particles keeps the order of the atomics (counted in
  * mpm_diag.order_fallbacks). */
 #define MPM_FLAG_DETERMINISTIC 1u
+
+/* Block-sparse grid activity.  The three grid buffers the substeps rotate
+ * through carry one flag per 4^3-node block; a substep flags the blocks it
+ * adds mass to and, when it clears a buffer for the substep after next,
+ * zeroes only the flagged blocks.  The grid work then follows the occupied
+ * blocks rather than n^3 (the memory stays dense: n^3 float4 nodes per
+ * buffer).  The default (neither flag) takes it when the grid has more than
+ * 4 nodes per particle; MPM_FLAG_GRID_SPARSE asks for it, MPM_FLAG_GRID_DENSE
+ * for dense clearing.  Not with MPM_FLAG_DETERMINISTIC (which clears
+ * densely); the two sparse / dense flags together are invalid. */
+#define MPM_FLAG_GRID_SPARSE 2u
+#define MPM_FLAG_GRID_DENSE 4u
 
 typedef struct {
   float* x;              /* [3][N] in/out */

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_PKG, "libfastmpm.so")
 
 MPM_ABI_VERSION = 1
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE, MPM_ESTATE, MPM_EUNSTABLE, MPM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-MPM_FLAG_DETERMINISTIC = 1
+MPM_FLAG_DETERMINISTIC, MPM_FLAG_GRID_SPARSE, MPM_FLAG_GRID_DENSE = 1, 2, 4
+_GRID_FLAGS = {"auto": 0, "sparse": MPM_FLAG_GRID_SPARSE, "dense": MPM_FLAG_GRID_DENSE}
 EXPORTED = ("mpm_status_string", "mpm_last_error", "mpm_workspace_size", "mpm_init", "mpm_substep", "mpm_step_n", "mpm_load",
             "mpm_advance", "mpm_store", "mpm_export_frame", "mpm_tape_size",
             "mpm_backward", "mpm_grid_state", "mpm_export_covariance", "mpm_get_diagnostics",
@@ -233,10 +234,12 @@ class Particles:
 
 
 def make_config(grid_res, dt, n_batch=1, gravity=(0.0, -9.8, 0.0), bound=3, sort_every=0,
-                deterministic=False) -> mpm_config:
+                deterministic=False, grid="auto") -> mpm_config:
+    """grid: "auto", "sparse" or "dense" (block-sparse grid clearing, see
+    MPM_FLAG_GRID_SPARSE in include/fastmpm.h)."""
+    flags = (MPM_FLAG_DETERMINISTIC if deterministic else 0) | _GRID_FLAGS[grid]
     return mpm_config(MPM_ABI_VERSION, int(grid_res), int(bound), int(n_batch), float(dt),
-                      (ctypes.c_float * 3)(*[float(g) for g in gravity]), int(sort_every),
-                      MPM_FLAG_DETERMINISTIC if deterministic else 0)
+                      (ctypes.c_float * 3)(*[float(g) for g in gravity]), int(sort_every), flags)
 
 
 def mpm_workspace_size(cfg: mpm_config, n_particles: int) -> int:
@@ -247,14 +250,15 @@ def mpm_workspace_size(cfg: mpm_config, n_particles: int) -> int:
 
 
 def mpm_init(grid_res, dt, materials: Sequence[dict], n_particles, batch_offsets=None, gravity=(0.0, -9.8, 0.0),
-             bound=3, sort_every=0, deterministic=False) -> Context:
+             bound=3, sort_every=0, deterministic=False, grid="auto") -> Context:
     """Create a context; its device workspace is a torch uint8 tensor on the
     current device, held by the returned Context.  deterministic sets
-    MPM_FLAG_DETERMINISTIC."""
+    MPM_FLAG_DETERMINISTIC; grid chooses the grid clearing ("auto",
+    "sparse", "dense")."""
     import torch
     lib = load()
     n_batch = 1 if batch_offsets is None else len(batch_offsets) - 1
-    cfg = make_config(grid_res, dt, n_batch, gravity, bound, sort_every, deterministic)
+    cfg = make_config(grid_res, dt, n_batch, gravity, bound, sort_every, deterministic, grid)
     mats = (mpm_material * len(materials))(*[mpm_material(int(m["elastic"]), int(m["plastic"]),
                                                           float(m.get("yield_stress", 0.0)),
                                                           float(m.get("friction_deg", 0.0))) for m in materials])
@@ -270,9 +274,10 @@ def mpm_init(grid_res, dt, materials: Sequence[dict], n_particles, batch_offsets
     return Context(h, int(n_particles), n_batch, int(grid_res), ws)
 
 
-def init_from_scene(sc, sort_every=0, deterministic=False) -> Context:
+def init_from_scene(sc, sort_every=0, deterministic=False, grid="auto") -> Context:
     return mpm_init(sc.grid_res, sc.dt, sc.materials, sc.n,
-                    None if sc.n_batch == 1 else sc.batch_offsets, sc.gravity, sc.bound, sort_every, deterministic)
+                    None if sc.n_batch == 1 else sc.batch_offsets, sc.gravity, sc.bound, sort_every, deterministic,
+                    grid)
 
 
 def mpm_substep(ctx: Context, p: Particles, stream=None):

@@ -49,7 +49,10 @@ struct mpm_context {
   float *xs = nullptr, *vs = nullptr, *Cs = nullptr, *Fs = nullptr, *xs2 = nullptr, *Fs2 = nullptr;
   float4 *prm = nullptr, *prm2 = nullptr;
   int *mat = nullptr, *mat2 = nullptr, *pid = nullptr, *pid2 = nullptr, *perm = nullptr;
-  float4* grid[3] = {nullptr, nullptr, nullptr};  // rotation: read, write, cleared for the step after
+  // rotation: read, write, cleared for the step after; each buffer is
+  // followed by one flag per 4^3-node block (block-sparse clearing)
+  float4* grid[3] = {nullptr, nullptr, nullptr};
+  bool sparse = false;  // the rotation's launches flag blocks and clear only flagged ones
   unsigned* done_counter = nullptr;                // finished workgroups of the substep kernel
   int* item_box = nullptr;                         // [2][max_chunks][6]: per-item cell boxes, in turn
   int *chunk_start = nullptr, *chunk_batch = nullptr;            // by scene, fixed (cell keys)
@@ -190,6 +193,7 @@ fmpm::SubstepArgs make_args(mpm_ctx c) {
   a.done_counter = c->done_counter;
   const double vmax = 0.5 / ((double)c->cfg.dt * (double)c->n);  // |v| dt / dx = 1/2
   a.cfl_v2 = (float)(vmax * vmax);
+  a.n_scenes = c->B;
   return a;
 }
 
@@ -460,7 +464,15 @@ int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
 // that scatters (P2G) is a measuring launch, the accumulating launch and
 // the conversion of the fixed-point grid into a.grid_out.
 template <int MODE>
-int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s) {
+int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = false) {
+  if constexpr (MODE != fmpm::kG2P) {
+    if (rotation && c->sparse) {  // the rotation's buffers carry block flags
+      a.clear_nodes = c->nodes;
+      fmpm::k_substep<MODE, fmpm::kDetOff, true><<<c->grid_blocks, kBlock, 0, s>>>(a);
+      LAUNCH_CHECK(c, "k_substep");
+      return MPM_OK;
+    }
+  }
   if (MODE == fmpm::kG2P || !c->det) {
     fmpm::k_substep<MODE><<<c->grid_blocks, kBlock, 0, s>>>(a);  // persistent: items from the queue
     LAUNCH_CHECK(c, "k_substep");
@@ -501,7 +513,7 @@ int launch_substep(mpm_ctx c, const float4* gin, float4* gout, int write_vc, hip
   a.box_in = box_in;
   a.box_out = box_out;
   ProfScope ps(c, s, MODE == fmpm::kFused ? 0 : (MODE == fmpm::kP2G ? 1 : 2));
-  return launch_args<MODE>(c, a, s);
+  return launch_args<MODE>(c, a, s, true);
 }
 
 int check_particles(mpm_ctx ctx, const mpm_particles* p) {
@@ -514,7 +526,7 @@ int check_particles(mpm_ctx ctx, const mpm_particles* p) {
 
 // Sizes derived from the configuration (shared by mpm_workspace_size and mpm_init).
 struct Geometry {
-  bool det = false;
+  bool det = false, sparse = false;
   int n = 0, nb = 0, B = 1;
   int64_t N = 0, nodes = 0, bins = 0, n_bsum = 0, nblocks = 0, max_chunks = 0, chunk_cap = 0;
 };
@@ -531,7 +543,10 @@ int check_config(const mpm_config* cfg, int64_t n_particles, const int64_t* batc
   if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt)) return MPM_EINVAL;
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(cfg->gravity[k])) return MPM_EINVAL;
-  if (cfg->sort_every < 0 || (cfg->flags & ~(uint32_t)MPM_FLAG_DETERMINISTIC) != 0) return MPM_EINVAL;
+  const uint32_t known = MPM_FLAG_DETERMINISTIC | MPM_FLAG_GRID_SPARSE | MPM_FLAG_GRID_DENSE;
+  if (cfg->sort_every < 0 || (cfg->flags & ~known) != 0) return MPM_EINVAL;
+  if ((cfg->flags & MPM_FLAG_GRID_SPARSE) && (cfg->flags & (MPM_FLAG_GRID_DENSE | MPM_FLAG_DETERMINISTIC)))
+    return MPM_EINVAL;
   if (n_particles < 0 || n_particles > (int64_t)0x7fffff00) return MPM_EINVAL;
   if (off) {
     if (batch_offsets) {
@@ -554,6 +569,10 @@ int check_config(const mpm_config* cfg, int64_t n_particles, const int64_t* batc
   g->n_bsum = (g->bins + fmpm::kScanTile - 1) / fmpm::kScanTile;
   g->nodes = (int64_t)cfg->n_batch * g->n * g->n * g->n;
   g->nblocks = (int64_t)cfg->n_batch * g->nb * g->nb * g->nb;
+  // block-sparse clearing: asked for, or by default where the grid has
+  // more than 4 nodes per particle (the deterministic mode stays dense)
+  g->sparse = (cfg->flags & MPM_FLAG_GRID_SPARSE) ||
+              (!(cfg->flags & (MPM_FLAG_GRID_DENSE | MPM_FLAG_DETERMINISTIC)) && g->nodes > 4 * n_particles);
   g->max_chunks = (n_particles + 63) / 64 + std::min<int64_t>(n_particles, g->nblocks) + 1;  // items >= 64
   g->chunk_cap = (n_particles + kBlock - 1) / kBlock + cfg->n_batch;  // per-scene chunks of kBlock
   return MPM_OK;
@@ -586,7 +605,7 @@ size_t carve(mpm_ctx c, const Geometry& g, char* base) {
   take(c->perm, N);
   take(c->keys, N);
   take(c->slots, N);
-  for (int k = 0; k < 3; ++k) take(c->grid[k], g.nodes);
+  for (int k = 0; k < 3; ++k) take(c->grid[k], g.nodes + (g.nblocks + 3) / 4);  // nodes, then block flags
   take(c->done_counter, 1);
   take(c->item_box, 2 * 6 * (g.max_chunks + 1));
   take(c->count, g.bins);
@@ -682,6 +701,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   c->n_bsum = g.n_bsum;
   if (cfg->sort_every > 0) c->sort_every = cfg->sort_every;
   c->det = g.det;
+  c->sparse = g.sparse;
 
   std::vector<int> cs, cb;
   for (int b = 0; b < c->B; ++b)
@@ -708,7 +728,8 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     fmpm::k_iota<<<blocks_for(n_particles, 256), 256>>>(c->pid, n_particles);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipMemset(c->grid[0], 0, (size_t)c->nodes * sizeof(float4));
+  for (int k = 0; k < 3 && e == hipSuccess; ++k)  // empty grids, no block flagged
+    e = hipMemset(c->grid[k], 0, (size_t)(c->nodes + (g.nblocks + 3) / 4) * sizeof(float4));
   if (e == hipSuccess && c->det) {  // range factors K_b = max(2^15, N_b / 2^9); the fixed-point grid at zero
     std::vector<double> k(c->B);
     for (int b = 0; b < c->B; ++b) k[b] = std::max(32768.0, (double)(off[b + 1] - off[b]) / 512.0);

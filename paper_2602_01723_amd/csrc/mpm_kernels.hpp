@@ -64,7 +64,7 @@ struct SubstepArgs {
   int n_materials;
   const Material* mats;  // device table [n_materials]
   // a grid buffer this launch neither reads nor writes, zeroed for the
-  // launch after next (NULL: none), and its node count
+  // launch after next (NULL: none), and the node count of a grid buffer
   float4* grid_clear;
   int64_t clear_nodes;
   // workgroups finished; the last one resets it and the queue head, so the
@@ -78,6 +78,7 @@ struct SubstepArgs {
   // CFL watch: G2P velocities with |v'|^2 above cfl_v2 (|v'| dt / dx > 1/2)
   // are counted in diag[4]; the largest |v'|^2 goes to diag[5]
   float cfl_v2;
+  int n_scenes;  // scenes (grids) of the context
   // deterministic mode (k_substep<MODE, kDetMeasure / kDetAccumulate>):
   // fxb[2 b + 0 / 1] = per-scene largest P2G contribution bound (momentum,
   // mass; float bits) raised by the measuring launch, fxk[b] the scene's
@@ -342,7 +343,14 @@ __device__ __forceinline__ void block_minmax(const int* lo, const int* hi, int* 
     }
 }
 
-template <int MODE, int DET = kDetOff>
+// SPARSE: block-sparse activity of the rotation's grid buffers.  Each
+// buffer is followed in memory (at clear_nodes nodes) by one uint32 flag per
+// 4^3-node block, (n + 3) / 4 blocks per axis and scene.  The launch flags
+// every block it adds to in grid_out and zeroes only the flagged blocks of
+// grid_clear (resetting their flags), so its grid work follows the occupied
+// blocks instead of the whole n^3.  Flags only ever over-cover the blocks
+// that hold mass.
+template <int MODE, int DET = kDetOff, bool SPARSE = false>
 __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   constexpr bool kMeasure = DET == kDetMeasure, kAccum = DET == kDetAccumulate;
   // deterministic modes take the stress of the stored (float32) F, as a
@@ -362,7 +370,31 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   const int cap = a.tile_cap;
   const int n_items = *a.n_chunks;
 
-  if (a.grid_clear) {  // this workgroup's slice of the buffer to clear
+  const int nbn = (n + 3) >> 2;  // 4^3-node blocks per axis
+  unsigned* const flag_out =
+      (SPARSE && a.grid_out) ? reinterpret_cast<unsigned*>(a.grid_out + a.clear_nodes) : nullptr;
+  if (SPARSE && a.grid_clear) {
+    // this workgroup's slice of the block flags: a thread zeroes the 64
+    // nodes of a flagged block (rows of 4 nodes along z) and resets its flag
+    // (32-bit block arithmetic: block indices stay below 2^31)
+    unsigned* const fc = reinterpret_cast<unsigned*>(a.grid_clear + a.clear_nodes);
+    const int per_scene = nbn * nbn * nbn;
+    const int nflags = a.n_scenes * per_scene;
+    const int per = (nflags + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int c0 = (int)blockIdx.x * per, c1 = min(nflags, c0 + per);
+    for (int blk = c0 + (int)threadIdx.x; blk < c1; blk += kBlock) {
+      if (!fc[blk]) continue;
+      const int sc = blk / per_scene, rb = blk - sc * per_scene;
+      const int bx = rb / (nbn * nbn), by = (rb / nbn) % nbn, bz = rb % nbn;
+      for (int r = 0; r < 16; ++r) {
+        const int ix = 4 * bx + (r >> 2), iy = 4 * by + (r & 3);
+        if (ix >= n || iy >= n) continue;
+        float4* row = a.grid_clear + ((((int64_t)sc * n + ix) * n + iy) * n + 4 * bz);
+        for (int k = 0; k < 4 && 4 * bz + k < n; ++k) row[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      fc[blk] = 0u;
+    }
+  } else if (a.grid_clear) {  // this workgroup's slice of the buffer to clear
     const int64_t per = (a.clear_nodes + gridDim.x - 1) / gridDim.x;
     const int64_t c0 = (int64_t)blockIdx.x * per, c1 = min(a.clear_nodes, c0 + per);
     for (int64_t t = c0 + threadIdx.x; t < c1; t += kBlock) a.grid_clear[t] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -782,13 +814,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
         }
       } else {
         // outside the item's P2G tile or its fixed-point range (rare): FP32
-        // global atomics node by node, in a loop kept rolled (code size)
+        // global atomics node by node, in a loop kept rolled (code size);
+        // with SPARSE each node's block is flagged first
 #pragma unroll 1
         for (int o = 0; o < 27; ++o) {
           const int ox = o / 9, oy = (o / 3) % 3, oz = o % 3;
           const float wgt = sel3(w[0], ox) * sel3(w[1], oy) * sel3(w[2], oz);
           const int ix = b1[0] + ox, iy = b1[1] + oy, iz = b1[2] + oz;
           const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
+          if (SPARSE && flag_out)
+            flag_out[(int64_t)scene * nbn * nbn * nbn + ((int64_t)(ix >> 2) * nbn + (iy >> 2)) * nbn + (iz >> 2)] = 1u;
           if (kAccum) {  // the scene's fixed point, added exactly
             unsigned long long* gq = a.gfx + 4 * node;
 #pragma unroll
@@ -811,7 +846,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     __syncthreads();  // the tile and the next box are complete
     if (a.box_out && threadIdx.x < 6) a.box_out[6 * item + threadIdx.x] = nbox_s[threadIdx.x];
 
-    // 4. flush
+    // 4. flush (with SPARSE, after flagging the node blocks the tile covers)
+    if (SPARSE && lds_p && flag_out) {
+      const int bx0 = plo[0] >> 2, by0 = plo[1] >> 2, bz0 = plo[2] >> 2;
+      const int nx = ((phi[0] + 2) >> 2) - bx0 + 1, ny = ((phi[1] + 2) >> 2) - by0 + 1,
+                nz = ((phi[2] + 2) >> 2) - bz0 + 1;
+      const int64_t sbase = (int64_t)scene * nbn * nbn * nbn;
+      for (int t = threadIdx.x; t < nx * ny * nz; t += kBlock) {
+        const int bx = bx0 + t / (ny * nz), by = by0 + (t / nz) % ny, bz = bz0 + t % nz;
+        flag_out[sbase + ((int64_t)bx * nbn + by) * nbn + bz] = 1u;
+      }
+    }
     if (lds_p) {
       const double is_mom = 1.0 / s_mom, is_mass = 1.0 / s_mass;
       for (int t = threadIdx.x; t < PT; t += kBlock) {

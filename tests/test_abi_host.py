@@ -90,7 +90,7 @@ def test_workspace_checks_before_any_device_work(lib):
 
 @pytest.mark.parametrize("kw", [dict(abi_version=2), dict(grid_res=4), dict(grid_res=4096), dict(bound=-1),
                                 dict(bound=15), dict(n_batch=0), dict(dt=0.0), dict(dt=float("nan")),
-                                dict(flags=1), dict(sort_every=-1)])
+                                dict(flags=8), dict(flags=2 | 4), dict(flags=2 | 1), dict(sort_every=-1)])
 def test_invalid_config_rejected_on_host(lib, kw):
     rc, h = _init(lib, _cfg(**kw))
     assert rc == B.MPM_EINVAL and not h.value
