@@ -59,6 +59,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# The default-mode fused kernel's name in rocprofv3 records (the template
+# arguments: fused mode, no deterministic variant, dense grid clearing).
+FUSED_KERNEL = "k_substep<1, 0, false>"
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -100,7 +105,7 @@ def write_valu(p1_csv, n_particles=2_000_000):
     """Summarise the p1 instruction-mix pass (SQ_INSTS_VALU) of the fused
     kernel into VALU_FILE, stamped with the kernel source hash."""
     c = summarize_counters([p1_csv], n_particles=n_particles)
-    out = {"kernel": "k_substep<1, 0>", "particles": n_particles, "dispatches": c["dispatches"],
+    out = {"kernel": FUSED_KERNEL, "particles": n_particles, "dispatches": c["dispatches"],
            "valu_instructions_per_particle": c["valu_instructions_per_particle"],
            "kernel_source_hash": kernel_source_hash(),
            "command": VALU_COMMAND}
@@ -143,7 +148,7 @@ def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) 
                 v = float(r["Counter_Value"])
                 if r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
                     copy = max(copy, v)
-                elif "k_substep<1, 0>" in r["Kernel_Name"]:
+                elif FUSED_KERNEL in r["Kernel_Name"]:
                     fused.append(v)
         if not fused or copy <= 0:
             raise SystemExit(f"{path}: no {counter} rows for the copy and the fused kernel")
@@ -151,7 +156,7 @@ def write_traffic(fetch_csv: str, write_csv: str, n_particles: int = 2_000_000) 
 
     cf, ff, nf = read(fetch_csv, "FETCH_SIZE")
     cw, fw, nw = read(write_csv, "WRITE_SIZE")
-    t = {"kernel": "k_substep<1, 0> (fused G2P + return map + stress + P2G)",
+    t = {"kernel": FUSED_KERNEL + " (fused G2P + return map + stress + P2G)",
          "workload": "large_scene, 2,000,000 particles, 128^3", "particles": n_particles,
          "kernel_source_hash": kernel_source_hash(), "fused_fetch_kib": ff, "fused_write_kib": fw,
          "dispatches": min(nf, nw), "copy_bytes": 256 * 1024 * 1024, "copy_fetch_kib": cf, "copy_write_kib": cw,
@@ -462,7 +467,7 @@ def summarize_batched_trace(trace_csv: str) -> str:
     return "\n".join(out)
 
 
-def summarize_counters(csv_paths, kernel="k_substep<1, 0>", n_particles=2_000_000) -> dict:
+def summarize_counters(csv_paths, kernel=FUSED_KERNEL, n_particles=2_000_000) -> dict:
     """Per-dispatch means of rocprofv3 --pmc counters for `kernel`, with a few
     derived figures (wave-level instructions per particle, LDS bank-conflict
     cycles per LDS instruction cycle, share of wave time issuing VALU)."""
