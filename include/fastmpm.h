@@ -120,8 +120,9 @@ typedef struct {
  * substep then runs twice: a measuring launch finds each scene's largest
  * contribution bound B_b, and the accumulating launch adds every
  * contribution, rounded to one fixed-point scale per scene (a power of two
- * set by B_b and the scene's particle count), as 64-bit integers, which sum
- * exactly in any order; the particles of each cell are ordered by index at
+ * set by B_b, the scene's largest work item and its particle count), as
+ * 64-bit integers, which sum exactly in any order; the particles of each
+ * cell are ordered by index at
  * every sort; and the stress of a substep is taken from F as stored in
  * float32, so a run split at any call boundary (mpm_step_n, mpm_advance,
  * mpm_store / mpm_load) equals the run in one piece.  mpm_backward is

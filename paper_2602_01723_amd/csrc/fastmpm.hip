@@ -479,7 +479,7 @@ int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = f
     return MPM_OK;
   }
   if constexpr (MODE != fmpm::kG2P) {
-    int rc = fill_u32(c, c->fxb, 2 * (int64_t)c->B, s);
+    int rc = fill_u32(c, c->fxb, 4 * (int64_t)c->B, s);
     if (rc) return rc;
     fmpm::SubstepArgs m = a;  // reads the state, writes nothing but the bounds
     m.grid_clear = nullptr;
@@ -621,7 +621,7 @@ size_t carve(mpm_ctx c, const Geometry& g, char* base) {
   take(c->d_mats, fmpm::kMaxMaterials);
   if (g.det) {
     take(c->gfx, 4 * g.nodes);
-    take(c->fxb, 2 * (int64_t)g.B);
+    take(c->fxb, 4 * (int64_t)g.B);
     take(c->fxk, g.B);
     take(c->perm2, N);
   }
@@ -730,9 +730,9 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   }
   for (int k = 0; k < 3 && e == hipSuccess; ++k)  // empty grids, no block flagged
     e = hipMemset(c->grid[k], 0, (size_t)(c->nodes + (g.nblocks + 3) / 4) * sizeof(float4));
-  if (e == hipSuccess && c->det) {  // range factors K_b = max(2^15, N_b / 2^9); the fixed-point grid at zero
+  if (e == hipSuccess && c->det) {  // N_b / 2^13 (the range factor's floor); the fixed-point grid at zero
     std::vector<double> k(c->B);
-    for (int b = 0; b < c->B; ++b) k[b] = std::max(32768.0, (double)(off[b + 1] - off[b]) / 512.0);
+    for (int b = 0; b < c->B; ++b) k[b] = (double)(off[b + 1] - off[b]) / 8192.0;
     e = hipMemcpy(c->fxk, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->gfx, 0, (size_t)c->nodes * 4 * sizeof(unsigned long long));
   }
@@ -1111,7 +1111,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       }
       if (ctx->det) {  // exact sums of the grid-velocity adjoint at one scale per scene
         ProfScope pa(ctx, s, 6);
-        rc = fill_u32(ctx, ctx->fxb, 2 * (int64_t)ctx->B, s);
+        rc = fill_u32(ctx, ctx->fxb, 4 * (int64_t)ctx->B, s);
         if (rc) return rc;
         b.fxb = ctx->fxb;
         b.fxk = ctx->fxk;

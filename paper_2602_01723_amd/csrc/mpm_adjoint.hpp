@@ -579,13 +579,15 @@ struct AdjItems {
 
 // Deterministic mode: each scene's bound of |w (vbt + D Cbt dpos)| over its
 // particles and their 27 nodes (w <= 0.75^3, |dpos| <= 1.5 dx per axis),
-// raised into both of the scene's slots of a.fxb.  One workgroup per item.
+// raised into both of the scene's bound slots of a.fxb, and the scene's
+// largest item into its item slot.  One workgroup per item.
 __global__ __launch_bounds__(256) void k_adj_bound(AdjArgs a, AdjItems it) {
   const int item = blockIdx.x;
   if (item >= *it.n_items) return;
   const int64_t N = a.N;
   const float dx = 1.0f / (float)a.n, D = 4.0f * (float)a.n * (float)a.n;
   const int scene = it.item_batch[item];
+  if (threadIdx.x == 0) atomicMax(&a.fxb[4 * scene + 2], (unsigned)(it.item_start[item + 1] - it.item_start[item]));
   for (int i = it.item_start[item] + (int)threadIdx.x; i < it.item_start[item + 1]; i += blockDim.x) {
     int b[3];
     float f[3];
@@ -608,8 +610,8 @@ __global__ __launch_bounds__(256) void k_adj_bound(AdjArgs a, AdjItems it) {
     }
     bnd *= 0.421875f;
     if (bnd <= 3.0e38f) {  // NaN and overflow stay out of the scale
-      raise_max(&a.fxb[2 * scene], bnd);
-      raise_max(&a.fxb[2 * scene + 1], bnd);
+      raise_max(&a.fxb[4 * scene], bnd);
+      raise_max(&a.fxb[4 * scene + 1], bnd);
     }
   }
 }
@@ -644,7 +646,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
     double s_fx = 1.0;
     if (DET) {
       const int scene = it.item_batch[item];
-      s_fx = fx_scale(a.fxk[scene] * (double)__uint_as_float(a.fxb[2 * scene]));
+      s_fx = fx_scale(fx_range(a.fxb, a.fxk, scene) * (double)__uint_as_float(a.fxb[4 * scene]));
     }
     int box[6];
     if (it.box_in) {

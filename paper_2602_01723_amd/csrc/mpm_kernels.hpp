@@ -80,10 +80,11 @@ struct SubstepArgs {
   float cfl_v2;
   int n_scenes;  // scenes (grids) of the context
   // deterministic mode (k_substep<MODE, kDetMeasure / kDetAccumulate>):
-  // fxb[2 b + 0 / 1] = per-scene largest P2G contribution bound (momentum,
-  // mass; float bits) raised by the measuring launch, fxk[b] the scene's
-  // range factor, gfx the 64-bit fixed-point grid [node][4] the
-  // accumulating launch adds into
+  // fxb[4 b + 0 / 1] = per-scene largest P2G contribution bound (momentum,
+  // mass; float bits) and fxb[4 b + 2] the particle count of the scene's
+  // largest work item, raised by the measuring launch; fxk[b] = N_b / 2^13;
+  // gfx the 64-bit fixed-point grid [node][4] the accumulating launch adds
+  // into
   unsigned* fxb;
   const double* fxk;
   unsigned long long* gfx;
@@ -95,9 +96,17 @@ struct SubstepArgs {
 // scene and channel, s_b = fx_scale(K_b B_b), for every contribution, in
 // the LDS tiles and in a 64-bit integer grid, so each node's sum is exact
 // and independent of the order of the additions and of how the particles
-// are grouped into items.  K_b = max(2^15, N_b / 2^9) keeps a tile node sum
-// of up to 8192 particles below 2^47 and a grid node sum below 2^58.
+// are grouped into items.  K_b = max(the largest item's particle count,
+// N_b / 2^13) keeps a tile node sum (at most one contribution per particle
+// of the item, each below 2^49 / K_b) below 2^49 and a grid node sum below
+// 2^62.  Items, and so K_b, are the same whether a scene runs alone or in a
+// batch.
 constexpr int kDetOff = 0, kDetMeasure = 1, kDetAccumulate = 2;
+
+// K_b of scene b (deterministic mode)
+__device__ __forceinline__ double fx_range(const unsigned* fxb, const double* fxk, int b) {
+  return fmax((double)fxb[4 * b + 2], fxk[b]);
+}
 
 // --------------------------------------------------------------------------
 // small helpers
@@ -497,11 +506,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     double s_mom = 1.0, s_mass = 1.0;
     float lim_mom = 0.0f, lim_mass = 0.0f;
     const int scene = a.chunk_batch[item];
+    if (kMeasure && threadIdx.x == 0) atomicMax(&a.fxb[4 * scene + 2], (unsigned)(end - start));
     if (kAccum) {  // the scene's scales from the measured bounds
-      lim_mom = __uint_as_float(a.fxb[2 * scene]);
-      lim_mass = __uint_as_float(a.fxb[2 * scene + 1]);
-      s_mom = fx_scale(a.fxk[scene] * (double)lim_mom);
-      s_mass = fx_scale(a.fxk[scene] * (double)lim_mass);
+      lim_mom = __uint_as_float(a.fxb[4 * scene]);
+      lim_mass = __uint_as_float(a.fxb[4 * scene + 1]);
+      const double K = fx_range(a.fxb, a.fxk, scene);
+      s_mom = fx_scale(K * (double)lim_mom);
+      s_mass = fx_scale(K * (double)lim_mass);
     }
     for (int sub = start; sub < end; sub += kBlock) {
       const int i = sub + (int)threadIdx.x;
@@ -739,8 +750,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       const bool fx_ok = bnd_mom <= 3.0e38f && bnd_mass <= 3.0e38f;
       if (kMeasure) {  // the scene's largest bounds; nothing is scattered
         if (scat && fx_ok) {
-          raise_max(&a.fxb[2 * scene], bnd_mom);
-          raise_max(&a.fxb[2 * scene + 1], bnd_mass);
+          raise_max(&a.fxb[4 * scene], bnd_mom);
+          raise_max(&a.fxb[4 * scene + 1], bnd_mass);
         }
         continue;
       }
@@ -920,8 +931,9 @@ __global__ void k_fx_grid(unsigned long long* gfx, float4* grid, int64_t nodes, 
   const ulonglong2 a = g[0], c = g[1];
   if ((a.x | a.y | c.x | c.y) == 0ull) return;
   const int b = (int)(t / per_scene);
-  const double is_mom = 1.0 / fx_scale(fxk[b] * (double)__uint_as_float(fxb[2 * b]));
-  const double is_mass = 1.0 / fx_scale(fxk[b] * (double)__uint_as_float(fxb[2 * b + 1]));
+  const double K = fx_range(fxb, fxk, b);
+  const double is_mom = 1.0 / fx_scale(K * (double)__uint_as_float(fxb[4 * b]));
+  const double is_mass = 1.0 / fx_scale(K * (double)__uint_as_float(fxb[4 * b + 1]));
   grid[t] = make_float4((float)((double)(long long)a.x * is_mom), (float)((double)(long long)a.y * is_mom),
                         (float)((double)(long long)c.x * is_mom), (float)((double)(long long)c.y * is_mass));
   g[0] = make_ulonglong2(0ull, 0ull);

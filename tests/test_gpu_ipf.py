@@ -209,3 +209,12 @@ def test_no_raw_candidates_or_no_triangles():
     d = scenes.ipf_inputs(seed=17, n_shell=(), meshes=[(box[0], np.zeros((0, 3), np.int32))], raw_per_mesh=100)
     cand, offs, src = run_gpu(d)
     assert list(offs) == [0, 0]
+
+
+def test_many_small_instances_bit_exact():
+    """300 instances of 40 hull points each (grids of a few cells, waves
+    spanning instances in the box reduction and the binning)."""
+    d = scenes.ipf_inputs(seed=18, n_shell=(40,) * 300, raw_per_point=5.0, r_range=(0.01, 0.04))
+    ref = run_oracle(d)
+    assert np.all(np.diff(ref[2]) > 0)
+    assert_bit_exact(run_gpu(d), ref)

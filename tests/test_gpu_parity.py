@@ -48,9 +48,10 @@ def random_scene(seed, N, n=32, dt=1e-4, mats=MATS_MIXED, spread=0.35, fdev=0.08
     return dict(x=x, v=v, C=C, F=F, mass=mass, vol0=vol0, log_E=log_E, nu=nu, mat_id=mat, mats=mats, n=n, dt=dt)
 
 
-def run_case(d, warm=0, sort_every=0, tile_cap=0, offsets=None):
+def run_case(d, warm=0, sort_every=0, tile_cap=0, offsets=None, grid="auto", deterministic=False):
     N = len(d["mass"])
-    ctx = B.mpm_init(d["n"], d["dt"], d["mats"], N, offsets, sort_every=sort_every)
+    ctx = B.mpm_init(d["n"], d["dt"], d["mats"], N, offsets, sort_every=sort_every, grid=grid,
+                     deterministic=deterministic)
     if tile_cap:
         B.mpm_set_tuning(ctx, tile_cap=tile_cap)
     p = B.Particles.from_arrays(d["x"], d["v"], d["C"], d["F"], d["mass"], d["vol0"], d["log_E"], d["nu"],
@@ -170,12 +171,29 @@ def test_substep_non_power_of_two_grid_and_half_cell():
     assert_parity(errs)
 
 
-def test_batched_scenes_with_empty_scene():
+@pytest.mark.parametrize("mode", [dict(grid="dense"), dict(grid="sparse"), dict(deterministic=True)],
+                         ids=["dense", "sparse", "deterministic"])
+def test_batched_scenes_with_empty_scene(mode):
+    """Three scenes, the middle one empty, after 5 warm-up substeps, in
+    each grid mode."""
     d1 = random_scene(21, 700, n=24)
     d2 = random_scene(22, 1300, n=24)
     d = {k: (np.concatenate([d1[k], d2[k]]) if isinstance(d1[k], np.ndarray) else d1[k]) for k in d1}
     offsets = [0, 700, 700, 2000]
-    errs, diag, _, _ = run_case(d, offsets=offsets)
+    errs, diag, _, _ = run_case(d, warm=5, offsets=offsets, **mode)
+    assert_parity(errs)
+
+
+@pytest.mark.parametrize("mode", [dict(grid="dense"), dict(grid="sparse"), dict(deterministic=True)],
+                         ids=["dense", "sparse", "deterministic"])
+@pytest.mark.parametrize("tile_cap", [0, 64])
+def test_substep_modes_after_warmup(mode, tile_cap):
+    """A random cloud after 8 warm-up substeps with re-sorts every 3, in each
+    grid mode, with the LDS tiles and with nearly every item in global
+    memory (tile_cap 64)."""
+    d = random_scene(31, 6000, vel=3.0)
+    errs, diag, ctx, _ = run_case(d, warm=8, sort_every=3, tile_cap=tile_cap, **mode)
+    print(mode, tile_cap, diag, flush=True)
     assert_parity(errs)
 
 
