@@ -117,21 +117,24 @@ typedef struct {
  * calls is a function of the inputs alone, bit for bit (the same on every
  * run, whatever the order of the GPU's atomic operations), and a scene's
  * result in a batched context equals its result alone.  The P2G of each
- * substep then runs twice: a measuring launch finds each scene's largest
- * contribution bound B_b, and the accumulating launch adds every
- * contribution, rounded to one fixed-point scale per scene (a power of two
- * set by B_b, the scene's largest work item and its particle count), as
- * 64-bit integers, which sum exactly in any order; the particles of each
- * cell are ordered by index at
- * every sort; and the stress of a substep is taken from F as stored in
- * float32, so a run split at any call boundary (mpm_step_n, mpm_advance,
- * mpm_store / mpm_load) equals the run in one piece.  mpm_backward is
- * deterministic too: its adjoint scatter into the grid adds at one
- * fixed-point scale per scene, set by a bound of the contributions taken
- * before the scatter.  Costs a second P2G-side launch per substep, a bound
- * pass per reversed substep and 32 B per grid node of workspace.  A cell of
- * more than 4096 particles keeps the order of the atomics (counted in
- * mpm_diag.order_fallbacks). */
+ * substep adds every contribution, rounded to one fixed-point scale per
+ * scene (a power of two set by the scene's largest contribution bound B_b,
+ * its largest work item and its particle count), as 64-bit integers, which
+ * sum exactly in any order.  The first P2G launch of a context measures B_b
+ * in a launch of its own; later ones take their scales from the previous
+ * launch's bounds while measuring B_b, and scatter again, from the stored
+ * state, any scene whose measured scale differs (counted in
+ * mpm_diag.det_rescales), so the sums are always those of the measured
+ * scale.  The particles of each cell are ordered by index at every sort,
+ * and the stress of a substep is taken from F as stored in float32, so a
+ * run split at any call boundary (mpm_step_n, mpm_advance, mpm_store /
+ * mpm_load) equals the run in one piece.  mpm_backward is deterministic
+ * too: its adjoint scatter into the grid adds at one fixed-point scale per
+ * scene, set by a bound of the contributions taken before the scatter.
+ * Costs a conversion launch and a second stress evaluation per substep, v
+ * and C stored at every substep, a bound pass per reversed substep and 64 B
+ * per grid node of workspace.  A cell of more than 4096 particles keeps the
+ * order of the atomics (counted in mpm_diag.order_fallbacks). */
 #define MPM_FLAG_DETERMINISTIC 1u
 
 /* Block-sparse grid activity.  The three grid buffers the substeps rotate
@@ -172,6 +175,9 @@ typedef struct {
                              update is unstable once this is well above 1) */
   int64_t order_fallbacks; /* deterministic mode: sorts of a cell holding more than 4096
                               particles, which keep the atomics' order (0 otherwise) */
+  int64_t det_rescales;    /* deterministic mode: P2G launches in which some scene's fixed-point
+                              scale differed from the one predicted from the previous launch's
+                              bounds, so that the scene was scattered again (0 otherwise) */
 } mpm_diag;
 
 /* Status code as text (static storage). */

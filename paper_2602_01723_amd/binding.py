@@ -67,7 +67,8 @@ class mpm_tuning(ctypes.Structure):
 class mpm_diag(ctypes.Structure):
     _fields_ = [("nonfinite", ctypes.c_int64), ("out_of_grid", ctypes.c_int64), ("tile_overflow", ctypes.c_int64),
                 ("tile_escapes", ctypes.c_int64), ("substeps", ctypes.c_int64), ("cfl_violations", ctypes.c_int64),
-                ("max_cfl", ctypes.c_double), ("max_wave_cfl", ctypes.c_double), ("order_fallbacks", ctypes.c_int64)]
+                ("max_cfl", ctypes.c_double), ("max_wave_cfl", ctypes.c_double), ("order_fallbacks", ctypes.c_int64),
+                ("det_rescales", ctypes.c_int64)]
 
 
 _lib = None
@@ -354,7 +355,8 @@ def mpm_get_diagnostics(ctx: Context) -> dict:
     rc = load().mpm_get_diagnostics(ctx.handle, ctypes.byref(d))
     out = dict(nonfinite=d.nonfinite, out_of_grid=d.out_of_grid, tile_overflow=d.tile_overflow,
                tile_escapes=d.tile_escapes, substeps=d.substeps, cfl_violations=d.cfl_violations,
-               max_cfl=d.max_cfl, max_wave_cfl=d.max_wave_cfl, order_fallbacks=d.order_fallbacks, status=rc)
+               max_cfl=d.max_cfl, max_wave_cfl=d.max_wave_cfl, order_fallbacks=d.order_fallbacks,
+               det_rescales=d.det_rescales, status=rc)
     if rc not in (MPM_OK, MPM_EUNSTABLE):
         _check(ctx, rc, "mpm_get_diagnostics")
     return out

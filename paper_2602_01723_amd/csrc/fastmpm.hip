@@ -28,8 +28,9 @@ using fmpm::kBlock;
 // device counters: 0 non-finite, 1 out of grid, 2 tile overflow, 3 tile
 // escapes, 4 CFL violations, 5 max (|v'| dt / dx)^2 and 6 max (c dt / dx)^2
 // (float bits in the low word), 7 cells left in atomic order by the
-// deterministic sort (more than fmpm::kStableMax particles)
-constexpr int kDiagSlots = 8;
+// deterministic sort (more than fmpm::kStableMax particles), 8 deterministic
+// P2G launches whose predicted scales missed for some scene
+constexpr int kDiagSlots = 9;
 
 struct mpm_context {
   mpm_config cfg{};
@@ -71,13 +72,20 @@ struct mpm_context {
   const int* pdest_cur = nullptr;  // destinations of the prepared permutation
   unsigned long long* diag = nullptr;
   fmpm::Material* d_mats = nullptr;
-  // deterministic mode (MPM_FLAG_DETERMINISTIC): per-scene bounds and range
-  // factors, the 64-bit fixed-point grid, the second permutation buffer
+  // deterministic mode (MPM_FLAG_DETERMINISTIC): three banks of per-scene
+  // bounds (4 words per scene; banks 0 and 1 alternate between the forward's
+  // P2G launches, bank 2 is the adjoint's), the range factors, the 64-bit
+  // fixed-point grid and the one a rescaled scene is scattered into again,
+  // the second permutation buffer
   bool det = false;
   unsigned* fxb = nullptr;
+  float2* fxi = nullptr;    // per-item bounds of the last measuring launch
+  int* scene_item = nullptr;  // each scene's first item, then the item count (per sort)
   double* fxk = nullptr;
-  unsigned long long* gfx = nullptr;
+  unsigned long long *gfx = nullptr, *gfx2 = nullptr;
   int* perm2 = nullptr;
+  int fx_bank = 0;          // the bank the next forward P2G launch measures into
+  bool fx_primed = false;   // the other bank holds bounds of an earlier launch
   size_t workspace_bytes = 0;  // of the caller's workspace, which holds every device buffer above
 
   // kernel timing (mpm_profile): event pairs recorded around launches
@@ -226,7 +234,7 @@ int sort_keys(mpm_ctx c, const float* x, hipStream_t s) {
   fmpm::k_scan_top<<<1, fmpm::kScanThreads, 0, s>>>(c->bsum, nbs);
   fmpm::k_scan_apply<<<(unsigned)nbs, fmpm::kScanThreads, 0, s>>>(c->nchk, c->bsum, c->nblocks);
   fmpm::k_block_chunk_write<<<gb, 256, 0, s>>>(c->count, c->nchk, c->nblocks, c->N, c->item, c->nb * c->nb * c->nb,
-                                               c->dchunk_start, c->dchunk_batch, c->dn_chunks);
+                                               c->dchunk_start, c->dchunk_batch, c->dn_chunks, c->scene_item);
   LAUNCH_CHECK(c, "chunk table");
   return MPM_OK;
 }
@@ -460,9 +468,25 @@ int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
   return rc ? rc : perm_apply(c, state_planes(in, out, N), s);
 }
 
+// Deterministic mode: the scenes' bounds (bank) from the per-item bounds of
+// the launch before, each scene flagged where its scales differ from those
+// of bank prev (NULL: none is)
+int fold_bounds(mpm_ctx c, unsigned* bank, const unsigned* prev, hipStream_t s) {
+  fmpm::k_fx_fold<<<(unsigned)c->B, fmpm::kFoldThreads, 0, s>>>(c->fxi, c->dchunk_start, c->scene_item, bank, prev,
+                                                                c->fxk);
+  LAUNCH_CHECK(c, "k_fx_fold");
+  return MPM_OK;
+}
+
 // One substep kernel with arguments a.  In deterministic mode a launch
-// that scatters (P2G) is a measuring launch, the accumulating launch and
-// the conversion of the fixed-point grid into a.grid_out.
+// that scatters (P2G) takes this substep's bounds into bank cur and leaves
+// the grid in a.grid_out through the fixed-point grid:
+//  - the first such launch of a context measures the bounds in a launch of
+//    its own, then accumulates at their scales;
+//  - later ones accumulate at the scales of the bounds in the other bank
+//    (the previous launch's) while measuring, then scatter again, from the
+//    state the launch stored, every scene whose measured scales differ (a
+//    P2G-only launch that returns at once when none does).
 template <int MODE>
 int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = false) {
   if constexpr (MODE != fmpm::kG2P) {
@@ -479,24 +503,58 @@ int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = f
     return MPM_OK;
   }
   if constexpr (MODE != fmpm::kG2P) {
-    int rc = fill_u32(c, c->fxb, 4 * (int64_t)c->B, s);
-    if (rc) return rc;
-    fmpm::SubstepArgs m = a;  // reads the state, writes nothing but the bounds
-    m.grid_clear = nullptr;
-    m.clear_nodes = 0;
-    m.box_out = nullptr;
-    m.write_vc = 0;
-    m.fxb = c->fxb;
-    fmpm::k_substep<MODE, fmpm::kDetMeasure><<<c->grid_blocks, kBlock, 0, s>>>(m);
-    LAUNCH_CHECK(c, "k_substep measure");
-    a.fxb = c->fxb;
+    const int64_t B4 = 4 * (int64_t)c->B, per_scene = (int64_t)c->n * c->n * c->n;
+    unsigned* const cur = c->fxb + B4 * c->fx_bank;
+    unsigned* const prev = c->fxb + B4 * (1 - c->fx_bank);
     a.fxk = c->fxk;
     a.gfx = c->gfx;
-    fmpm::k_substep<MODE, fmpm::kDetAccumulate><<<c->grid_blocks, kBlock, 0, s>>>(a);
-    LAUNCH_CHECK(c, "k_substep accumulate");
-    fmpm::k_fx_grid<<<blocks_for(c->nodes, 256), 256, 0, s>>>(c->gfx, a.grid_out, c->nodes,
-                                                             (int64_t)c->n * c->n * c->n, c->fxb, c->fxk);
-    LAUNCH_CHECK(c, "k_fx_grid");
+    a.fxi = c->fxi;
+    if (!c->fx_primed) {
+      fmpm::SubstepArgs m = a;  // reads the state, writes nothing but the bounds
+      m.grid_clear = nullptr;
+      m.clear_nodes = 0;
+      m.box_out = nullptr;
+      m.write_vc = 0;
+      fmpm::k_substep<MODE, fmpm::kDetMeasure><<<c->grid_blocks, kBlock, 0, s>>>(m);
+      LAUNCH_CHECK(c, "k_substep measure");
+      int rc = fold_bounds(c, cur, nullptr, s);
+      if (rc) return rc;
+      a.fxb = cur;
+      fmpm::k_substep<MODE, fmpm::kDetAccumulate><<<c->grid_blocks, kBlock, 0, s>>>(a);
+      LAUNCH_CHECK(c, "k_substep accumulate");
+      fmpm::k_fx_grid<<<blocks_for(c->nodes, 256), 256, 0, s>>>(c->gfx, nullptr, a.grid_out, c->nodes, per_scene,
+                                                               cur, c->fxk);
+      LAUNCH_CHECK(c, "k_fx_grid");
+    } else {
+      a.fxb = prev;
+      if (MODE == fmpm::kFused) a.write_vc = 1;  // a scatter again reads v and C
+      fmpm::k_substep<MODE, fmpm::kDetPredict><<<c->grid_blocks, kBlock, 0, s>>>(a);
+      LAUNCH_CHECK(c, "k_substep predict");
+      int rc = fold_bounds(c, cur, prev, s);
+      if (rc) return rc;
+      fmpm::SubstepArgs r = a;  // the P2G of the stored state, at the measured scales, into gfx2
+      if (MODE == fmpm::kFused) {
+        r.x = a.xo;
+        r.v = a.vo;
+        r.C = a.Co;
+        r.F = a.Fo;
+      }
+      r.grid_in = nullptr;
+      r.grid_clear = nullptr;
+      r.clear_nodes = 0;
+      r.box_in = nullptr;
+      r.box_out = nullptr;
+      r.write_vc = 0;
+      r.fxb = cur;
+      r.gfx = c->gfx2;
+      fmpm::k_substep<fmpm::kP2G, fmpm::kDetRedo><<<c->grid_blocks, kBlock, 0, s>>>(r);
+      LAUNCH_CHECK(c, "k_substep rescale");
+      fmpm::k_fx_grid<<<blocks_for(c->nodes, 256), 256, 0, s>>>(c->gfx, c->gfx2, a.grid_out, c->nodes, per_scene,
+                                                               cur, c->fxk);
+      LAUNCH_CHECK(c, "k_fx_grid");
+    }
+    c->fx_bank ^= 1;
+    c->fx_primed = true;
   }
   return MPM_OK;
 }
@@ -621,7 +679,10 @@ size_t carve(mpm_ctx c, const Geometry& g, char* base) {
   take(c->d_mats, fmpm::kMaxMaterials);
   if (g.det) {
     take(c->gfx, 4 * g.nodes);
-    take(c->fxb, 4 * (int64_t)g.B);
+    take(c->gfx2, 4 * g.nodes);
+    take(c->fxb, 12 * (int64_t)g.B);
+    take(c->fxi, g.max_chunks + 1);
+    take(c->scene_item, (int64_t)g.B + 1);
     take(c->fxk, g.B);
     take(c->perm2, N);
   }
@@ -735,6 +796,8 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     for (int b = 0; b < c->B; ++b) k[b] = (double)(off[b + 1] - off[b]) / 8192.0;
     e = hipMemcpy(c->fxk, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->gfx, 0, (size_t)c->nodes * 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(c->gfx2, 0, (size_t)c->nodes * 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(c->fxb, 0, (size_t)c->B * 12 * sizeof(unsigned));
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -1111,18 +1174,19 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
       }
       if (ctx->det) {  // exact sums of the grid-velocity adjoint at one scale per scene
         ProfScope pa(ctx, s, 6);
-        rc = fill_u32(ctx, ctx->fxb, 4 * (int64_t)ctx->B, s);
-        if (rc) return rc;
-        b.fxb = ctx->fxb;
+        unsigned* const bank = ctx->fxb + 8 * (int64_t)ctx->B;  // the adjoint's bound bank
+        b.fxb = bank;
+        b.fxi = ctx->fxi;
         b.fxk = ctx->fxk;
         b.gfx = ctx->gfx;
         fmpm::k_adj_bound<<<(unsigned)std::max<int64_t>(ctx->max_chunks, 1), 256, 0, s>>>(b, items);
         LAUNCH_CHECK(ctx, "k_adj_bound");
+        rc = fold_bounds(ctx, bank, nullptr, s);
+        if (rc) return rc;
         fmpm::k_adj_g2p<true><<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
         LAUNCH_CHECK(ctx, "k_adj_g2p");
-        fmpm::k_fx_grid<<<blocks_for(ctx->nodes, 256), 256, 0, s>>>(ctx->gfx, tl.vhb, ctx->nodes,
-                                                                     (int64_t)ctx->n * ctx->n * ctx->n, ctx->fxb,
-                                                                     ctx->fxk);
+        fmpm::k_fx_grid<<<blocks_for(ctx->nodes, 256), 256, 0, s>>>(
+            ctx->gfx, nullptr, tl.vhb, ctx->nodes, (int64_t)ctx->n * ctx->n * ctx->n, bank, ctx->fxk);
       } else {
         ProfScope pa(ctx, s, 6);
         fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
@@ -1197,6 +1261,7 @@ int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out) {
   out->max_cfl = std::sqrt((double)v2) * scale;
   out->max_wave_cfl = std::sqrt((double)c2) * scale;
   out->order_fallbacks = (int64_t)h[7];
+  out->det_rescales = (int64_t)h[8];
   return (h[0] || h[1] || h[4]) ? MPM_EUNSTABLE : MPM_OK;
 }
 

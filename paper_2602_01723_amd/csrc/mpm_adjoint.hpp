@@ -64,8 +64,10 @@ struct AdjArgs {
   float g[3];
   // deterministic mode (k_adj_g2p<true>): per-scene bound of the
   // grid-velocity adjoint contributions (float bits, both slots of the
-  // scene), the scenes' range factors and the 64-bit fixed-point grid
+  // scene), the per-item bounds k_adj_bound stores, the scenes' range
+  // factors and the 64-bit fixed-point grid
   unsigned* fxb;
+  float2* fxi;
   const double* fxk;
   unsigned long long* gfx;
 };
@@ -577,17 +579,17 @@ struct AdjItems {
   const int* box_in;      // per-item base-cell boxes of the state (NULL: a pass over x)
 };
 
-// Deterministic mode: each scene's bound of |w (vbt + D Cbt dpos)| over its
+// Deterministic mode: each item's bound of |w (vbt + D Cbt dpos)| over its
 // particles and their 27 nodes (w <= 0.75^3, |dpos| <= 1.5 dx per axis),
-// raised into both of the scene's bound slots of a.fxb, and the scene's
-// largest item into its item slot.  One workgroup per item.
+// stored in both channels of a.fxi[item] (k_fx_fold then forms each
+// scene's bound).  One workgroup per item.
 __global__ __launch_bounds__(256) void k_adj_bound(AdjArgs a, AdjItems it) {
+  __shared__ float wmax[4];
   const int item = blockIdx.x;
   if (item >= *it.n_items) return;
   const int64_t N = a.N;
   const float dx = 1.0f / (float)a.n, D = 4.0f * (float)a.n * (float)a.n;
-  const int scene = it.item_batch[item];
-  if (threadIdx.x == 0) atomicMax(&a.fxb[4 * scene + 2], (unsigned)(it.item_start[item + 1] - it.item_start[item]));
+  float mx = 0.0f;  // this lane's largest bound
   for (int i = it.item_start[item] + (int)threadIdx.x; i < it.item_start[item + 1]; i += blockDim.x) {
     int b[3];
     float f[3];
@@ -609,10 +611,14 @@ __global__ __launch_bounds__(256) void k_adj_bound(AdjArgs a, AdjItems it) {
       bnd = fmaxf(bnd, fabsf(a.av[r * N + i] + a.dt * a.ax[r * N + i]) + D * 1.5f * dx * row);
     }
     bnd *= 0.421875f;
-    if (bnd <= 3.0e38f) {  // NaN and overflow stay out of the scale
-      raise_max(&a.fxb[4 * scene], bnd);
-      raise_max(&a.fxb[4 * scene + 1], bnd);
-    }
+    if (bnd <= 3.0e38f) mx = fmaxf(mx, bnd);  // NaN and overflow stay out of the scale
+  }
+  mx = wave_maxf(mx);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmaxf(mx, wmax[w]);
+    a.fxi[item] = make_float2(mx, mx);
   }
 }
 

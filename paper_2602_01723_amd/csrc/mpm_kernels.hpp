@@ -79,13 +79,16 @@ struct SubstepArgs {
   // are counted in diag[4]; the largest |v'|^2 goes to diag[5]
   float cfl_v2;
   int n_scenes;  // scenes (grids) of the context
-  // deterministic mode (k_substep<MODE, kDetMeasure / kDetAccumulate>):
-  // fxb[4 b + 0 / 1] = per-scene largest P2G contribution bound (momentum,
-  // mass; float bits) and fxb[4 b + 2] the particle count of the scene's
-  // largest work item, raised by the measuring launch; fxk[b] = N_b / 2^13;
-  // gfx the 64-bit fixed-point grid [node][4] the accumulating launch adds
-  // into
+  // deterministic mode (k_substep<MODE, kDet...>).  A bound bank holds, per
+  // scene b, [4 b + 0 / 1] the largest P2G contribution bound (momentum,
+  // mass; float bits) and [4 b + 2] the particle count of the largest work
+  // item, [4 b + 3] whether the scales of these bounds differ from the
+  // ones predicted (k_fx_fold forms the bank from fxi).  fxb: the bank the
+  // fixed-point scales are taken from; fxi: a measuring or predicting
+  // launch's largest bounds per work item; fxk[b] = N_b / 2^13; gfx the
+  // 64-bit fixed-point grid [node][4] the launch adds into
   unsigned* fxb;
+  float2* fxi;
   const double* fxk;
   unsigned long long* gfx;
 };
@@ -101,7 +104,15 @@ struct SubstepArgs {
 // of the item, each below 2^49 / K_b) below 2^49 and a grid node sum below
 // 2^62.  Items, and so K_b, are the same whether a scene runs alone or in a
 // batch.
-constexpr int kDetOff = 0, kDetMeasure = 1, kDetAccumulate = 2;
+//
+// After the first substep the measuring launch is replaced by a prediction:
+// the fused launch takes its scales from the previous substep's bounds and
+// raises this substep's bounds as it goes (kDetPredict).  Only a scene whose
+// scale, fx_scale(K_b B_b), differs from the predicted one is scattered
+// again, from the state the launch stored, at the measured scale into a
+// second fixed-point grid (kDetRedo), and the conversion takes that grid for
+// it.  Either way every node sum is the one the measured scale gives.
+constexpr int kDetOff = 0, kDetMeasure = 1, kDetAccumulate = 2, kDetPredict = 3, kDetRedo = 4;
 
 // K_b of scene b (deterministic mode)
 __device__ __forceinline__ double fx_range(const unsigned* fxb, const double* fxk, int b) {
@@ -170,6 +181,15 @@ __device__ __forceinline__ double fx_scale(double x) {
   (void)frexp(x, &e);  // x < 2^e
   e = min(max(49 - e, -900), 900);
   return ldexp(1.0, e);
+}
+
+// Deterministic mode: whether scene b's scales from the measured bank cur
+// differ from those predicted from bank prev (either channel)
+__device__ __forceinline__ bool fx_mismatch(const unsigned* cur, const unsigned* prev, const double* fxk, int b) {
+  const double kc = fx_range(cur, fxk, b), kp = fx_range(prev, fxk, b);
+  return fx_scale(kc * (double)__uint_as_float(cur[4 * b])) != fx_scale(kp * (double)__uint_as_float(prev[4 * b])) ||
+         fx_scale(kc * (double)__uint_as_float(cur[4 * b + 1])) !=
+             fx_scale(kp * (double)__uint_as_float(prev[4 * b + 1]));
 }
 
 // Box of base cells over the workgroup's valid particles, plus the maxima
@@ -361,7 +381,10 @@ __device__ __forceinline__ void block_minmax(const int* lo, const int* hi, int* 
 // that hold mass.
 template <int MODE, int DET = kDetOff, bool SPARSE = false>
 __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
-  constexpr bool kMeasure = DET == kDetMeasure, kAccum = DET == kDetAccumulate;
+  constexpr bool kMeasure = DET == kDetMeasure, kPredict = DET == kDetPredict, kRedo = DET == kDetRedo;
+  constexpr bool kAccum = DET == kDetAccumulate || kPredict || kRedo;  // adds into the fixed-point grid
+  constexpr bool kRaise = kMeasure || kPredict;                        // records the bounds in fxi
+  constexpr bool kQuiet = kMeasure || kRedo;  // repeats work another launch counts: no diagnostics
   // deterministic modes take the stress of the stored (float32) F, as a
   // P2G-only launch from stored state does, so that a run split at any call
   // boundary equals the run in one piece
@@ -370,6 +393,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   __shared__ float gtile[3 * kTileCapMax];               // G2P node velocities
   __shared__ int red[8 * (kBlock / 64)];
   __shared__ float fred[2 * (kBlock / 64)];
+  __shared__ float imax_s[2 * (kBlock / 64)];
   __shared__ int item_s;
   __shared__ int nbox_s[6];  // the item's box after this substep
 
@@ -378,6 +402,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   const float inv_dx = (float)n, dx = 1.0f / (float)n;
   const int cap = a.tile_cap;
   const int n_items = *a.n_chunks;
+  if (kRedo) {  // nothing to do unless a scene's measured scale differs from its predicted one
+    bool any = false;  // the fold's flags, a wave's lanes over the scenes
+    for (int b = (int)(threadIdx.x & 63); b < a.n_scenes; b += 64) any |= a.fxb[4 * b + 3] != 0u;
+    if (!__any(any)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.diag[8], 1ull);
+  }
 
   const int nbn = (n + 3) >> 2;  // 4^3-node blocks per axis
   unsigned* const flag_out =
@@ -419,6 +449,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     if (item >= n_items) break;
     const int start = a.chunk_start[item], end = a.chunk_start[item + 1];
     const int64_t gbase = (int64_t)a.chunk_batch[item] * n * n * n;
+    if (kRedo && a.fxb[4 * a.chunk_batch[item] + 3] == 0u) continue;  // its scale held
 
     // 1. box of base cells: from the previous substep, or a pass over x
     int box[6];
@@ -468,7 +499,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     const int PT = empty ? 0 : (px - 1) * SX + (py - 1) * pz + pz;
     const bool lds_g = (MODE != kP2G) && !empty && GT <= cap;
     const bool lds_p = !kMeasure && (MODE != kG2P) && !empty && PT <= cap;
-    if (!kMeasure && threadIdx.x == 0 && !empty && (((MODE != kP2G) && !lds_g) || ((MODE != kG2P) && !lds_p)))
+    if (!kQuiet && threadIdx.x == 0 && !empty && (((MODE != kP2G) && !lds_g) || ((MODE != kG2P) && !lds_p)))
       atomicAdd(&a.diag[2], 1ull);
 
     // 2. tiles
@@ -504,15 +535,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     // particle whose contribution exceeds kFxMargin times that maximum
     // scatters to global memory instead.
     double s_mom = 1.0, s_mass = 1.0;
+    float meas_mom = 0.0f, meas_mass = 0.0f;  // kRaise: this lane's largest bounds in the item
     float lim_mom = 0.0f, lim_mass = 0.0f;
     const int scene = a.chunk_batch[item];
-    if (kMeasure && threadIdx.x == 0) atomicMax(&a.fxb[4 * scene + 2], (unsigned)(end - start));
-    if (kAccum) {  // the scene's scales from the measured bounds
+    if (kAccum) {  // the scene's scales from the measured (or, predicting, the previous) bounds
       lim_mom = __uint_as_float(a.fxb[4 * scene]);
       lim_mass = __uint_as_float(a.fxb[4 * scene + 1]);
       const double K = fx_range(a.fxb, a.fxk, scene);
       s_mom = fx_scale(K * (double)lim_mom);
       s_mass = fx_scale(K * (double)lim_mass);
+      // predicting, every finite contribution enters the tile: if this
+      // substep's bounds give the same scales, they keep every sum in range
+      // (as for the measured bounds); if not, the scene is scattered again
+      if (kPredict) lim_mom = lim_mass = INFINITY;
     }
     for (int sub = start; sub < end; sub += kBlock) {
       const int i = sub + (int)threadIdx.x;
@@ -554,7 +589,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
           for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b0[k], f0[k]);
           ok = in_grid;
           if (in_grid) b0p = b0[0] | (b0[1] << 10) | (b0[2] << 20);
-          if (!in_grid && !kMeasure) {
+          if (!in_grid && !kQuiet) {
             atomicAdd(&a.diag[1], 1ull);
             if (a.xo != a.x) {  // skipped: carry the state over unchanged
 #pragma unroll
@@ -648,7 +683,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
               xp[k] = xp[k] + a.dt * vs[k];
             }
             const float v2 = vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2];
-            if (!kMeasure) {
+            if (!kQuiet) {
               v2max = fmaxf(v2max, v2);
               cfl_count += (v2 > a.cfl_v2) ? 1u : 0u;
             }
@@ -674,7 +709,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) fin &= isfinite(xp[k]);
             if (!fin) {
-              if (!kMeasure) atomicAdd(&a.diag[0], 1ull);
+              if (!kQuiet) atomicAdd(&a.diag[0], 1ull);
               ok = false;
             }
             if (!kMeasure) {
@@ -697,7 +732,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
           bool in_grid = true;
 #pragma unroll
           for (int k = 0; k < 3; ++k) in_grid &= cell_of(xp[k], n, b1[k], f1[k]);
-          if (MODE == kP2G && !in_grid && !kMeasure) atomicAdd(&a.diag[1], 1ull);
+          if (MODE == kP2G && !in_grid && !kQuiet) atomicAdd(&a.diag[1], 1ull);
           // a particle that changed cell may widen the item's next box
           if (MODE == kFused && a.box_out && in_grid && (b1[0] | (b1[1] << 10) | (b1[2] << 20)) != b0p) {
 #pragma unroll
@@ -729,7 +764,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
             for (int k = 0; k < 9; ++k) fin &= isfinite(Ad[k]);
             if (fin) {
               scat = true;
-            } else if (!kMeasure) {  // never let a bad particle reach the grid
+            } else if (!kQuiet) {  // never let a bad particle reach the grid
               atomicAdd(&a.diag[0], 1ull);
             }
           }
@@ -748,13 +783,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       }
       // a bound that overflows float32 keeps its particle out of the tile and out of the scale
       const bool fx_ok = bnd_mom <= 3.0e38f && bnd_mass <= 3.0e38f;
-      if (kMeasure) {  // the scene's largest bounds; nothing is scattered
-        if (scat && fx_ok) {
-          raise_max(&a.fxb[4 * scene], bnd_mom);
-          raise_max(&a.fxb[4 * scene + 1], bnd_mass);
-        }
-        continue;
+      if (kRaise && scat && fx_ok) {  // the lane's largest bounds
+        meas_mom = fmaxf(meas_mom, bnd_mom);
+        meas_mass = fmaxf(meas_mass, bnd_mass);
       }
+      if (kMeasure) continue;  // nothing is scattered
       if (scale_pass) {
         float m2[2] = {wave_maxf(fx_ok ? bnd_mom : 0.0f), wave_maxf(fx_ok ? bnd_mass : 0.0f)};
         if ((threadIdx.x & 63) == 0) {
@@ -777,7 +810,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       const bool in_tile = lds_p && b1[0] >= plo[0] && b1[0] <= phi[0] && b1[1] >= plo[1] && b1[1] <= phi[1] &&
                            b1[2] >= plo[2] && b1[2] <= phi[2] && fx_ok && bnd_mom <= lim_mom &&
                            bnd_mass <= lim_mass;
-      if (lds_p && !in_tile) atomicAdd(&a.diag[3], 1ull);
+      if (lds_p && !in_tile && !kQuiet) atomicAdd(&a.diag[3], 1ull);
       float w[3][3];
       bspline_w(f1[0], w[0]);
       bspline_w(f1[1], w[1]);
@@ -854,7 +887,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       }
     }
 
-    __syncthreads();  // the tile and the next box are complete
+    if (kRaise) {  // the waves' largest bounds
+      const float m0 = wave_maxf(meas_mom), m1 = wave_maxf(meas_mass);
+      if ((threadIdx.x & 63) == 0) {
+        imax_s[2 * (threadIdx.x >> 6)] = m0;
+        imax_s[2 * (threadIdx.x >> 6) + 1] = m1;
+      }
+    }
+    __syncthreads();  // the tile, the next box and the waves' bounds are complete
+    if (kRaise && threadIdx.x == 0) {  // the item's largest bounds: a plain store per item
+      float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) {
+        m0 = fmaxf(m0, imax_s[2 * w]);
+        m1 = fmaxf(m1, imax_s[2 * w + 1]);
+      }
+      a.fxi[item] = make_float2(m0, m1);
+    }
     if (a.box_out && threadIdx.x < 6) a.box_out[6 * item + threadIdx.x] = nbox_s[threadIdx.x];
 
     // 4. flush (with SPARSE, after flagging the node blocks the tile covers)
@@ -893,7 +942,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
       }
     }
   }
-  if (MODE != kP2G && !kMeasure) cfl_flush(a.diag, v2max, cfl_count);
+  if (MODE != kP2G && !kQuiet) cfl_flush(a.diag, v2max, cfl_count);
   // the queue is drained: the last workgroup out resets the counters
   if (a.done_counter && threadIdx.x == 0) {
     __threadfence();
@@ -917,20 +966,76 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n, int* counter) {
   if (i < (n & 3)) p[t] = v;
 }
 
+// Deterministic mode: each scene's bounds from the per-item bounds of a
+// measuring or predicting launch (or of k_adj_bound): bank[4 b + 0 / 1] =
+// the largest of fxi[item].x / .y over scene b's items (scene_item[b] ..
+// scene_item[b + 1] - 1), bank[4 b + 2] = the particle count of its largest
+// item (zero for a scene without items), and bank[4 b + 3] = 1 where prev
+// is set (the bank the launch's scales were predicted from) and the scales
+// of these bounds differ from it, else 0.  One workgroup of kFoldThreads
+// per scene.
+constexpr int kFoldThreads = 1024;
+__global__ __launch_bounds__(kFoldThreads) void k_fx_fold(const float2* fxi, const int* chunk_start,
+                                                          const int* scene_item, unsigned* bank,
+                                                          const unsigned* prev, const double* fxk) {
+  __shared__ float r0[kFoldThreads / 64], r1[kFoldThreads / 64];
+  __shared__ int rc[kFoldThreads / 64];
+  const int b = blockIdx.x;
+  const int lo = scene_item[b], hi = scene_item[b + 1];
+  float m0 = 0.0f, m1 = 0.0f;
+  int cnt = 0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += kFoldThreads) {
+    const float2 v = fxi[i];
+    m0 = fmaxf(m0, v.x);
+    m1 = fmaxf(m1, v.y);
+    cnt = max(cnt, chunk_start[i + 1] - chunk_start[i]);
+  }
+  m0 = wave_maxf(m0);
+  m1 = wave_maxf(m1);
+  cnt = -wave_min(-cnt);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    r0[w] = m0;
+    r1[w] = m1;
+    rc[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kFoldThreads / 64; ++k) {
+      m0 = fmaxf(m0, r0[k]);
+      m1 = fmaxf(m1, r1[k]);
+      cnt = max(cnt, rc[k]);
+    }
+    reinterpret_cast<uint4*>(bank)[b] = make_uint4(__float_as_uint(m0), __float_as_uint(m1), (unsigned)cnt, 0u);
+    if (prev && fx_mismatch(bank, prev, fxk, b)) bank[4 * b + 3] = 1u;
+  }
+}
+
 // Deterministic mode: the 64-bit fixed-point grid [node][4] -> grid (mv,
 // m) as float4 at each scene's scales (the same fx_scale of the same
-// bounds as the accumulating launch), and the fixed-point grid zeroed for
-// the next accumulation.  per_scene = n^3.  The float grid is zero where
-// nothing was added (it was cleared before the launch), so untouched nodes
-// are only read.
-__global__ void k_fx_grid(unsigned long long* gfx, float4* grid, int64_t nodes, int64_t per_scene,
-                          const unsigned* fxb, const double* fxk) {
+// bounds as the accumulating launch: bank fxb), and the fixed-point grid
+// zeroed for the next accumulation.  per_scene = n^3.  With gfx2 set, a
+// scene flagged by k_fx_fold (its measured scales differ from the
+// predicted ones) was scattered again into gfx2: its nodes are taken from
+// gfx2, and both grids are zeroed.  The float grid is zero where nothing was added (it
+// was cleared before the launch), so untouched nodes are only read.
+__global__ void k_fx_grid(unsigned long long* gfx, unsigned long long* gfx2, float4* grid, int64_t nodes,
+                          int64_t per_scene, const unsigned* fxb, const double* fxk) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nodes) return;
-  ulonglong2* g = reinterpret_cast<ulonglong2*>(gfx + 4 * t);
-  const ulonglong2 a = g[0], c = g[1];
-  if ((a.x | a.y | c.x | c.y) == 0ull) return;
   const int b = (int)(t / per_scene);
+  ulonglong2* g = reinterpret_cast<ulonglong2*>(gfx + 4 * t);
+  ulonglong2 a = g[0], c = g[1];
+  if (gfx2 && fxb[4 * b + 3]) {  // the sums at the measured scale are in gfx2
+    if ((a.x | a.y | c.x | c.y) != 0ull) {
+      g[0] = make_ulonglong2(0ull, 0ull);
+      g[1] = make_ulonglong2(0ull, 0ull);
+    }
+    g = reinterpret_cast<ulonglong2*>(gfx2 + 4 * t);
+    a = g[0];
+    c = g[1];
+  }
+  if ((a.x | a.y | c.x | c.y) == 0ull) return;
   const double K = fx_range(fxb, fxk, b);
   const double is_mom = 1.0 / fx_scale(K * (double)__uint_as_float(fxb[4 * b]));
   const double is_mass = 1.0 / fx_scale(K * (double)__uint_as_float(fxb[4 * b + 1]));
@@ -1107,15 +1212,19 @@ __global__ void k_block_chunk_count(const uint32_t* off, int64_t nblocks, int64_
   nchk[b] = (hi - lo + item - 1) / item;
 }
 
-// base = exclusive scan of nchk (same array, scanned in place beforehand)
+// base = exclusive scan of nchk (same array, scanned in place beforehand).
+// scene_item (optional, [scenes + 1]) receives each scene's first item and,
+// last, the item count: items come in scene order.
 __global__ void k_block_chunk_write(const uint32_t* off, const uint32_t* base, int64_t nblocks, int64_t N, int item,
-                                    int blocks_per_scene, int* chunk_start, int* chunk_batch, int* n_chunks) {
+                                    int blocks_per_scene, int* chunk_start, int* chunk_batch, int* n_chunks,
+                                    int* scene_item) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nblocks) return;
   const uint32_t lo = off[b * 64];
   const uint32_t hi = (b + 1 < nblocks) ? off[(b + 1) * 64] : (uint32_t)N;
   const uint32_t c0 = base[b];
   const int scene = (int)(b / blocks_per_scene);
+  if (scene_item && b % blocks_per_scene == 0) scene_item[scene] = (int)c0;
   uint32_t c = c0;
   for (uint32_t s = lo; s < hi; s += item, ++c) {
     chunk_start[c] = (int)s;
@@ -1124,6 +1233,7 @@ __global__ void k_block_chunk_write(const uint32_t* off, const uint32_t* base, i
   if (b == nblocks - 1) {
     chunk_start[c] = (int)N;
     *n_chunks = (int)c;
+    if (scene_item) scene_item[nblocks / blocks_per_scene] = (int)c;
   }
 }
 

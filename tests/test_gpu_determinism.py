@@ -6,7 +6,8 @@ order of the atomics), each cell's particles are ordered by index at
 every sort, and the stress is taken from the stored float32 F.  Checked bit
 for bit: repeated runs, the caller's particle order permuted, resident and
 mpm_step_n runs split into calls against one call, a stored state loaded
-into a new context, and a batched context against each scene alone.  The mode keeps the substep's parity with the
+into a new context, a batched context against each scene alone, and
+fixed-point scales predicted from a different state.  The mode keeps the substep's parity with the
 oracle, and its state stays within rounding of the default mode."""
 import numpy as np
 import pytest
@@ -169,6 +170,39 @@ def test_batched_context_equals_each_scene_alone():
         B.mpm_store(c1, q)
         torch.cuda.synchronize()
         assert_same_bits([r[off[b]:off[b + 1]] for r in res], state_bits(q), f"scene {b}, resident")
+
+
+def test_predicted_scales_that_miss_are_redone():
+    """After its first P2G launch a context takes each launch's fixed-point
+    scales from the previous launch's bounds while it measures this
+    launch's, and scatters a scene again from the stored state when its
+    measured scale differs.  A context that first ran a copy of the batch in
+    which scene 1 moves 20x faster (bounds about 20x larger) predicts wrong
+    scales for scene 1 of the real batch: the state must equal fresh
+    contexts' of each scene alone bit for bit, with the miss counted."""
+    import copy
+    sc = scenes.make_scene("candidate_batch", n_batch=3, grid_res=32, n_min=3000, n_max=9000)
+    off = sc.batch_offsets
+    fast = copy.deepcopy(sc)
+    fast.v[off[1]:off[2]] *= 20.0
+    fast.C[off[1]:off[2]] *= 20.0
+    print("determinism: primed by a faster scene 1", flush=True)
+    ctx = B.init_from_scene(sc, sort_every=6, deterministic=True)
+    pf = B.Particles.from_scene(fast)
+    B.mpm_step_n(ctx, pf, 2)
+    torch.cuda.synchronize()
+    r0 = B.mpm_get_diagnostics(ctx)["det_rescales"]
+    p = B.Particles.from_scene(sc)
+    B.mpm_step_n(ctx, p, 25)
+    torch.cuda.synchronize()
+    d = B.mpm_get_diagnostics(ctx)
+    print("rescales while priming", r0, "in the run", d["det_rescales"] - r0, flush=True)
+    assert d["det_rescales"] > r0
+    got = state_bits(p)
+    for b in range(3):
+        alone, da = run_step_n(sc.subset(b), 25)
+        print(f"scene {b} alone: rescales {da['det_rescales']} in 26 P2G launches", flush=True)
+        assert_same_bits([g[off[b]:off[b + 1]] for g in got], state_bits(alone), f"scene {b} after priming")
 
 
 def test_deterministic_substep_matches_the_oracle():
