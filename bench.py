@@ -804,6 +804,54 @@ def cpu_baseline(sc, n_sub=2):
                           "sample": f"1 substep of the {small.n}-particle copy of the workload ({dt1:.1f} s)"})
 
 
+def item_geometry(n_total=2_000_000, item=768):
+    """Grid work of one fused launch implied by the work-item decomposition of
+    the workload at its initial positions (host only): the library's cell
+    keys (4^3-cell blocks, Morton order inside), items of at most `item`
+    particles per block, and per item the G2P tile (base-cell box + 2 nodes
+    per axis) and the nodes the P2G tile flushes (the union of the item's
+    particles' 27-node stencils: the nodes its tile holds mass for)."""
+    import numpy as np
+
+    from paper_2602_01723_amd import scenes
+    sc = scenes.make_scene("large_scene", n_total=n_total)
+    n = sc.grid_res
+    nb = (n + 3) // 4
+    c = np.clip(np.floor(sc.x.astype(np.float64) * n - 0.5), 0, n - 1).astype(np.int64)
+    blk = ((c[:, 0] >> 2) * nb + (c[:, 1] >> 2)) * nb + (c[:, 2] >> 2)
+
+    def spread2(v):
+        return (v & 1) | ((v & 2) << 2)
+
+    key = blk * 64 + (spread2(c[:, 0] & 3) << 2 | spread2(c[:, 1] & 3) << 1 | spread2(c[:, 2] & 3))
+    order = np.argsort(key, kind="stable")
+    cs, bs = c[order], blk[order]
+    starts = np.flatnonzero(np.r_[True, bs[1:] != bs[:-1]])
+    ends = np.r_[starts[1:], len(bs)]
+    item_id = np.empty(len(bs), np.int64)
+    n_items = 0
+    for s0, e0 in zip(starts, ends):
+        item_id[s0:e0] = n_items + np.arange(e0 - s0) // item
+        n_items += (e0 - s0 + item - 1) // item
+    lo = np.full((n_items, 3), 1 << 30)
+    hi = np.full((n_items, 3), -1)
+    for a in range(3):
+        np.minimum.at(lo[:, a], item_id, cs[:, a])
+        np.maximum.at(hi[:, a], item_id, cs[:, a])
+    g2p_nodes = int(np.prod(hi - lo + 3, 1).sum())
+    n3 = n ** 3
+    ic = np.unique(item_id * n3 + (cs[:, 0] * n + cs[:, 1]) * n + cs[:, 2])
+    it, cl = ic // n3, ic % n3
+    cx, cy, cz = cl // (n * n), (cl // n) % n, cl % n
+    nodes = np.unique(np.concatenate([it * n3 + ((cx + i) * n + (cy + j)) * n + (cz + k)
+                                      for i in range(3) for j in range(3) for k in range(3)]))
+    active = int(len(np.unique(nodes % n3)))
+    return {"workload": f"large_scene, {sc.n} particles, {n}^3, initial positions", "items": int(n_items),
+            "particles_per_item": sc.n / n_items, "nodes_with_mass": active, "g2p_tile_nodes": g2p_nodes,
+            "flushed_nodes": int(len(nodes)), "flush_lane_atomics": 4 * int(len(nodes)),
+            "g2p_loads_per_node_with_mass": g2p_nodes / active, "flushes_per_node_with_mass": len(nodes) / active}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -848,7 +896,13 @@ def main():
                     help="summarise the p1 instruction-mix counter run into the VALU file and exit (no GPU use)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
+    ap.add_argument("--item-geometry", action="store_true",
+                    help="count the fused launch's G2P tile loads and flushed nodes from the workload's item "
+                         "geometry and exit (no GPU use)")
     args = ap.parse_args()
+    if args.item_geometry:
+        print(json.dumps(item_geometry(args.n_total, args.item or 768)))
+        return
     if args.summarize_counters:
         print(json.dumps(summarize_counters(args.summarize_counters, n_particles=args.n_total), indent=1))
         return
