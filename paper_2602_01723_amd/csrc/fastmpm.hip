@@ -468,6 +468,13 @@ int scatter_state(mpm_ctx c, float* out24, hipStream_t s) {
   return rc ? rc : perm_apply(c, state_planes(in, out, N), s);
 }
 
+// Workgroups of the persistent adjoint G2P (default mode): it fits three per
+// CU where the forward kernels fit two, so 1.5 times the forward's count (at
+// most one per work item)
+unsigned adj_g2p_blocks(mpm_ctx c) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(c->max_chunks, ((int64_t)c->grid_blocks * 3 + 1) / 2));
+}
+
 // Deterministic mode: the scenes' bounds (bank) from the per-item bounds of
 // the launch before, each scene flagged where its scales differ from those
 // of bank prev (NULL: none is)
@@ -1189,7 +1196,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
             ctx->gfx, nullptr, tl.vhb, ctx->nodes, (int64_t)ctx->n * ctx->n * ctx->n, bank, ctx->fxk);
       } else {
         ProfScope pa(ctx, s, 6);
-        fmpm::k_adj_g2p<<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
+        fmpm::k_adj_g2p<<<adj_g2p_blocks(ctx), kBlock, 0, s>>>(b, items);
       }
       LAUNCH_CHECK(ctx, "k_adj_g2p");
       rc = fill_u32(ctx, ctx->work_counter, 1, s);  // the item queue again, for k_adj_p2g

@@ -30,6 +30,8 @@
 //     g_nu   += -mub mu / (1 + nu) + lamb E (1 + 2 nu^2) / ((1 + nu)(1 - 2 nu))^2.
 #pragma once
 
+#include <type_traits>
+
 #include "mpm_kernels.hpp"
 
 namespace fmpm {
@@ -623,7 +625,10 @@ __global__ __launch_bounds__(256) void k_adj_bound(AdjArgs a, AdjItems it) {
 }
 
 template <bool DET = false>
-__global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
+// Three workgroups per CU (48 KB of LDS each; at most 168 VGPRs) in the
+// default mode, where the host launches 1.5 times the forward's workgroup
+// count; two in deterministic mode (its fixed-point scatter would spill).
+__global__ __launch_bounds__(kBlock, DET ? 2 : 3) void k_adj_g2p(AdjArgs a, AdjItems it) {
   __shared__ double ptile[3 * kTileCapMax];
   // deterministic mode: the same LDS as 64-bit fixed point at the scene's scale
   unsigned long long* const pu = reinterpret_cast<unsigned long long*>(ptile);
@@ -805,6 +810,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
         dprz[k] = ((float)roz[k] - f[2]) * dx;
       }
       float xo[3] = {xb[0], xb[1], xb[2]};
+      // one loop nest for the tile and one for global memory (the choice is
+      // uniform per item), so the node loops carry no per-node test
+      auto scatter = [&](auto tile_c) {
+        constexpr bool TILE = decltype(tile_c)::value;
 #pragma unroll 1
       for (int kx = 0; kx < 3; ++kx) {
         // x-axis values by selection (a rolled loop keeps register use down)
@@ -818,7 +827,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
           for (int kz = 0; kz < 3; ++kz) {
             const int oz = roz[kz];
             float vho[3];
-            node_v(ox, oy, oz, vho);
+            if (TILE) {
+              const int t = a0 + ox * sz + oy * gz + oz;
+              vho[0] = gtile[t];
+              vho[1] = gtile[kTileCapMax + t];
+              vho[2] = gtile[2 * kTileCapMax + t];
+            } else {
+              node_v(ox, oy, oz, vho);
+            }
             const float wz = wrz[kz];
             const float wt = wx * wy * wz;
             const float gw[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * dwrz[kz]};
@@ -834,7 +850,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
               gv[r] = wt * gval;
               wb += vho[r] * gval;
             }
-            if (lds) {
+            if (TILE) {
               const int t = a0 + ox * sz + oy * gz + oz;
               if (DET) {
 #pragma unroll
@@ -864,6 +880,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_g2p(AdjArgs a, AdjItems it) {
           }
         }
       }
+      };
+      if (lds)
+        scatter(std::true_type{});
+      else
+        scatter(std::false_type{});
 #pragma unroll
       for (int k = 0; k < 3; ++k) a.ax[k * N + i] = xo[k];
 #pragma unroll

@@ -1,14 +1,15 @@
 """Register and scratch budget of the hot kernels (CPU: compiler remarks).
 
-The fused substep kernel and the adjoint kernels sit at the 256-VGPR limit
-of two waves per SIMD.  A change that makes the compiler spill into AGPRs
-halves occupancy without any error, and one that spills to scratch adds
-memory traffic; both were seen to cost 40-50% of the kernel's speed.  This
-test compiles the device code with the library's flags and checks, from the
-compiler's resource-usage remarks, that each hot kernel keeps two waves per
-SIMD, uses no AGPRs and at most the scratch listed in SCRATCH_OK (the
-adjoint P2G is allowed 16 bytes per lane: some builds keep two registers
-there).  The caller-order permutation passes, which hold a plane's loads in
+The fused substep kernel and the adjoint P2G sit at the 256-VGPR limit of
+two waves per SIMD, the default-mode adjoint G2P at the 168-VGPR limit of
+three.  A change that makes the compiler spill into AGPRs lowers occupancy
+without any error, and one that spills to scratch adds memory traffic; both
+were seen to cost 40-50% of the kernel's speed.  This test compiles the
+device code with the library's flags and checks, from the compiler's
+resource-usage remarks, that each hot kernel keeps the waves per SIMD listed
+in OCCUPANCY (two unless listed), uses no AGPRs and at most the scratch
+listed in SCRATCH_OK (the adjoint kernels are allowed 16 bytes per lane:
+some builds keep a few registers there).  The caller-order permutation passes, which hold a plane's loads in
 registers across their LDS round trip, are checked the same way."""
 import os
 import re
@@ -20,9 +21,10 @@ import pytest
 
 from paper_2602_01723_amd import build as Bd
 
-HOT = ("k_substepILi1E", "k_substepILi0E", "k_substepILi2E", "k_adj_g2p", "k_adj_p2g", "k_perm_pass1_staged",
-       "k_perm_pass2")
-SCRATCH_OK = {"k_adj_p2g": 16}  # bytes per lane
+HOT = ("k_substepILi1E", "k_substepILi0E", "k_substepILi2E", "k_adj_g2pILb0", "k_adj_g2pILb1", "k_adj_p2g",
+       "k_perm_pass1_staged", "k_perm_pass2")
+SCRATCH_OK = {"k_adj_p2g": 16, "k_adj_g2pILb0": 16}  # bytes per lane
+OCCUPANCY = {"k_adj_g2pILb0": 3}  # waves per SIMD
 
 
 def _remarks():
@@ -42,7 +44,7 @@ def _remarks():
         return res.stderr
 
 
-def test_hot_kernels_keep_two_waves_and_no_scratch():
+def test_hot_kernels_keep_their_waves_and_no_scratch():
     text = _remarks()
     usage, name = {}, None
     for line in text.splitlines():
@@ -59,6 +61,6 @@ def test_hot_kernels_keep_two_waves_and_no_scratch():
         assert names, f"{key} not found in the compiler remarks"
         for n in names:
             u = usage[n]
-            assert u.get("Occupancy", 0) >= 2, (n, u)
+            assert u.get("Occupancy", 0) >= OCCUPANCY.get(key, 2), (n, u)
             assert u.get("ScratchSize", 0) <= SCRATCH_OK.get(key, 0), (n, u)
             assert u.get("AGPRs", 0) == 0, (n, u)
