@@ -651,20 +651,27 @@ def batched_vs_plain(n_batch=64, steps=100, K=20, reps=3):
 
 
 def config_timings():
-    """The other workloads, each on a context of its own: the plain cube at
-    its stated count (20,480 particles, 32^3; 100 substeps through
-    mpm_step_n), the Gaussian-scene cloud (300,000 particles, 64^3; 1,000
-    substeps on the resident scene) and the differentiation workload
-    (200,000 particles, 64^3; 200 substeps taped every 20, the position-loss
-    cotangent and the backward: one gradient)."""
+    """The other workloads, each on a context of its own, autotuned like the
+    headline (mpm_autotune on trial calls of 20 substeps; the tuning kept is
+    reported): the plain cube at its stated count (20,480 particles, 32^3;
+    100 substeps through mpm_step_n), the Gaussian-scene cloud (300,000
+    particles, 64^3; 1,000 substeps on the resident scene) and the
+    differentiation workload (200,000 particles, 64^3; 200 substeps taped
+    every 20, the position-loss cotangent and the backward: one gradient)."""
     import numpy as np
     import torch
 
     from paper_2602_01723_amd import binding as B
     from paper_2602_01723_amd import scenes
     out = {}
+
+    def tune(ctx, sc):
+        t = B.mpm_autotune(ctx, B.Particles.from_scene(sc), 20)
+        return {k: t[k] for k in ("chunk", "workgroups", "sort_every")}
+
     sc = scenes.make_scene("cube_uniform")
     ctx = B.init_from_scene(sc)
+    tuning = tune(ctx, sc)
     p = B.Particles.from_scene(sc)
     B.mpm_step_n(ctx, p, 10)
     torch.cuda.synchronize()
@@ -673,10 +680,11 @@ def config_timings():
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     out["cube_20480"] = dict(particles=sc.n, substeps=100, seconds=round(t, 5), particle_substeps_per_s=sc.n * 100 / t,
-                             path="mpm_step_n(100)")
+                             path="mpm_step_n(100)", tuning=tuning)
     del ctx, p
     sc = scenes.make_scene("gaussian_cloud")
     ctx = B.init_from_scene(sc)
+    tuning = tune(ctx, sc)
     p = B.Particles.from_scene(sc)
     B.mpm_load(ctx, p)
     B.mpm_advance(ctx, 10)
@@ -686,11 +694,13 @@ def config_timings():
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     out["gaussian_cloud_300k"] = dict(particles=sc.n, substeps=1000, seconds=round(t, 4),
-                                      particle_substeps_per_s=sc.n * 1000 / t, path="mpm_load + mpm_advance(1000)")
+                                      particle_substeps_per_s=sc.n * 1000 / t, path="mpm_load + mpm_advance(1000)",
+                                      tuning=tuning)
     del ctx, p
     sc = scenes.make_scene("colliding_pair", E=(2e5, 5e4), nu=(0.25, 0.35))
     steps, K, N = sc.n_substeps, sc.checkpoint_every, sc.n
     ctx = B.init_from_scene(sc)
+    tuning = tune(ctx, sc)
     tgt = B.Particles.from_scene(sc)
     B.mpm_step_n(ctx, tgt, steps)
     x_target = tgt.x.clone()
@@ -721,7 +731,8 @@ def config_timings():
     t = (time.perf_counter() - t0) / reps
     out["colliding_pair_200k"] = dict(particles=N, substeps=steps, checkpoint_every=K, seconds_per_gradient=round(t, 4),
                                       grads_per_s=1.0 / t, fwd_bwd_particle_substeps_per_s=N * steps / t,
-                                      path="mpm_step_n with tape + mpm_position_loss_grad + mpm_backward")
+                                      path="mpm_step_n with tape + mpm_position_loss_grad + mpm_backward",
+                                      tuning=tuning)
     del ctx, p, init, tape, tgt
     torch.cuda.empty_cache()
     out["large_domain_512"] = large_domain_timing()
