@@ -205,6 +205,21 @@ def test_predicted_scales_that_miss_are_redone():
         assert_same_bits([g[off[b]:off[b + 1]] for g in got], state_bits(alone), f"scene {b} after priming")
 
 
+def test_grid_not_a_multiple_of_four():
+    """A 38^3 grid (partial 4^3 blocks at the upper faces, where the cloud
+    is pressed against the sticky walls): two runs bitwise equal, and one
+    substep against the oracle."""
+    sc = scenes.make_scene("gaussian_cloud", n_total=6000, grid_res=38)
+    sc.x = (sc.x + (0.9 - sc.x.max(0))).astype(np.float32)
+    sc.v = np.tile(np.array([[6.0, 6.0, 6.0]], np.float32), (sc.n, 1))
+    a, _ = run_step_n(sc, 30)
+    b, _ = run_step_n(sc, 30)
+    assert_same_bits(state_bits(a), state_bits(b), "38^3 grid")
+    one, _ = run_step_n(sc, 1)
+    errs, _ = compare_substep((sc.x, sc.v, sc.C, sc.F), one.state_numpy(), None, O.Params.from_scene(sc), sc.mass)
+    assert not parity_failures(errs, TOL_SUBSTEP), errs
+
+
 def test_deterministic_substep_matches_the_oracle():
     """One substep in deterministic mode against the oracle, to the same
     element-wise bar as the default mode."""
