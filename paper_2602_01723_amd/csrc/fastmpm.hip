@@ -1108,22 +1108,30 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
     // each kernel also records the item boxes of the state it produces,
     // which the next kernel and the two adjoint kernels of that state reuse
     auto bslot = [&](int j) { return tl.boxes + (int64_t)j * 6 * (ctx->max_chunks + 1); };
+    // each launch also zeroes the grid slot the launch after it writes
+    // (slot 0 is filled above); the kernels reset the item queue themselves
     {
       fmpm::SubstepArgs a = args_for(0, 0);
       a.grid_out = gslot(0);
       a.box_out = bslot(0);
+      if (L > 1) {
+        a.grid_clear = gslot(1);
+        a.clear_nodes = ctx->nodes;
+      }
       rc = launch_args<fmpm::kP2G>(ctx, a, s);
       if (rc) return rc;
     }
     for (int j = 0; j + 1 < L; ++j) {
-      rc = fill_u32(ctx, gslot(j + 1), 4 * ctx->nodes, s, -1, ctx->work_counter);
-      if (rc) return rc;
       fmpm::SubstepArgs a = args_for(j, j + 1);
       a.grid_in = gslot(j);
       a.grid_out = gslot(j + 1);
       a.box_in = bslot(j);
       a.box_out = bslot(j + 1);
       a.write_vc = 1;
+      if (j + 2 < L) {
+        a.grid_clear = gslot(j + 2);
+        a.clear_nodes = ctx->nodes;
+      }
       rc = launch_args<fmpm::kFused>(ctx, a, s);
       if (rc) return rc;
     }
