@@ -81,6 +81,7 @@ struct mpm_context {
   unsigned* fxb = nullptr;
   float2* fxi = nullptr;    // per-item bounds of the last measuring launch
   int* scene_item = nullptr;  // each scene's first item, then the item count (per sort)
+  unsigned* gflag = nullptr;  // one flag per 4^3-node block of gfx, set by the accumulating launches
   double* fxk = nullptr;
   unsigned long long *gfx = nullptr, *gfx2 = nullptr;
   int* perm2 = nullptr;
@@ -510,12 +511,14 @@ int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = f
     return MPM_OK;
   }
   if constexpr (MODE != fmpm::kG2P) {
-    const int64_t B4 = 4 * (int64_t)c->B, per_scene = (int64_t)c->n * c->n * c->n;
+    const int64_t B4 = 4 * (int64_t)c->B;
     unsigned* const cur = c->fxb + B4 * c->fx_bank;
     unsigned* const prev = c->fxb + B4 * (1 - c->fx_bank);
     a.fxk = c->fxk;
     a.gfx = c->gfx;
     a.fxi = c->fxi;
+    a.gflag = c->gflag;
+    const unsigned fx_blocks = (unsigned)((c->nblocks + 3) / 4);  // k_fx_grid_blocks: four blocks per workgroup
     if (!c->fx_primed) {
       fmpm::SubstepArgs m = a;  // reads the state, writes nothing but the bounds
       m.grid_clear = nullptr;
@@ -529,8 +532,8 @@ int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = f
       a.fxb = cur;
       fmpm::k_substep<MODE, fmpm::kDetAccumulate><<<c->grid_blocks, kBlock, 0, s>>>(a);
       LAUNCH_CHECK(c, "k_substep accumulate");
-      fmpm::k_fx_grid<<<blocks_for(c->nodes, 256), 256, 0, s>>>(c->gfx, nullptr, a.grid_out, c->nodes, per_scene,
-                                                               cur, c->fxk);
+      fmpm::k_fx_grid_blocks<<<fx_blocks, 256, 0, s>>>(c->gfx, nullptr, a.grid_out, c->gflag, c->nblocks, c->nb, c->n,
+                                                       cur, c->fxk);
       LAUNCH_CHECK(c, "k_fx_grid");
     } else {
       a.fxb = prev;
@@ -556,8 +559,8 @@ int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = f
       r.gfx = c->gfx2;
       fmpm::k_substep<fmpm::kP2G, fmpm::kDetRedo><<<c->grid_blocks, kBlock, 0, s>>>(r);
       LAUNCH_CHECK(c, "k_substep rescale");
-      fmpm::k_fx_grid<<<blocks_for(c->nodes, 256), 256, 0, s>>>(c->gfx, c->gfx2, a.grid_out, c->nodes, per_scene,
-                                                               cur, c->fxk);
+      fmpm::k_fx_grid_blocks<<<fx_blocks, 256, 0, s>>>(c->gfx, c->gfx2, a.grid_out, c->gflag, c->nblocks, c->nb, c->n,
+                                                       cur, c->fxk);
       LAUNCH_CHECK(c, "k_fx_grid");
     }
     c->fx_bank ^= 1;
@@ -690,6 +693,7 @@ size_t carve(mpm_ctx c, const Geometry& g, char* base) {
     take(c->fxb, 12 * (int64_t)g.B);
     take(c->fxi, g.max_chunks + 1);
     take(c->scene_item, (int64_t)g.B + 1);
+    take(c->gflag, g.nblocks);
     take(c->fxk, g.B);
     take(c->perm2, N);
   }
@@ -808,6 +812,7 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
     e = hipMemcpy(c->fxk, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->gfx, 0, (size_t)c->nodes * 4 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(c->gfx2, 0, (size_t)c->nodes * 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(c->gflag, 0, (size_t)c->nblocks * sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(c->fxb, 0, (size_t)c->B * 12 * sizeof(unsigned));
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -91,6 +91,10 @@ struct SubstepArgs {
   float2* fxi;
   const double* fxk;
   unsigned long long* gfx;
+  // deterministic accumulation: one flag per 4^3-node block of gfx (the
+  // layout of the sparse grid's flags), set for every block the launch adds
+  // into, so the conversion visits only those blocks
+  unsigned* gflag;
 };
 
 // Deterministic mode.  The P2G of a substep runs twice: a measuring launch
@@ -410,8 +414,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
   }
 
   const int nbn = (n + 3) >> 2;  // 4^3-node blocks per axis
-  unsigned* const flag_out =
-      (SPARSE && a.grid_out) ? reinterpret_cast<unsigned*>(a.grid_out + a.clear_nodes) : nullptr;
+  // block flags of the buffer this launch adds into: the rotation's grid
+  // buffer (SPARSE) or the fixed-point grid (deterministic accumulation)
+  unsigned* const flag_out = SPARSE ? (a.grid_out ? reinterpret_cast<unsigned*>(a.grid_out + a.clear_nodes) : nullptr)
+                                    : (kAccum ? a.gflag : nullptr);
   if (SPARSE && a.grid_clear) {
     // this workgroup's slice of the block flags: a thread zeroes the 64
     // nodes of a flagged block (rows of 4 nodes along z) and resets its flag
@@ -866,7 +872,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
           const float wgt = sel3(w[0], ox) * sel3(w[1], oy) * sel3(w[2], oz);
           const int ix = b1[0] + ox, iy = b1[1] + oy, iz = b1[2] + oz;
           const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
-          if (SPARSE && flag_out)
+          if ((SPARSE || kAccum) && flag_out)
             flag_out[(int64_t)scene * nbn * nbn * nbn + ((int64_t)(ix >> 2) * nbn + (iy >> 2)) * nbn + (iz >> 2)] = 1u;
           if (kAccum) {  // the scene's fixed point, added exactly
             unsigned long long* gq = a.gfx + 4 * node;
@@ -907,7 +913,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_substep(SubstepArgs a) {
     if (a.box_out && threadIdx.x < 6) a.box_out[6 * item + threadIdx.x] = nbox_s[threadIdx.x];
 
     // 4. flush (with SPARSE, after flagging the node blocks the tile covers)
-    if (SPARSE && lds_p && flag_out) {
+    if ((SPARSE || kAccum) && lds_p && flag_out) {
       const int bx0 = plo[0] >> 2, by0 = plo[1] >> 2, bz0 = plo[2] >> 2;
       const int nx = ((phi[0] + 2) >> 2) - bx0 + 1, ny = ((phi[1] + 2) >> 2) - by0 + 1,
                 nz = ((phi[2] + 2) >> 2) - bz0 + 1;
@@ -1011,19 +1017,16 @@ __global__ __launch_bounds__(kFoldThreads) void k_fx_fold(const float2* fxi, con
   }
 }
 
-// Deterministic mode: the 64-bit fixed-point grid [node][4] -> grid (mv,
-// m) as float4 at each scene's scales (the same fx_scale of the same
-// bounds as the accumulating launch: bank fxb), and the fixed-point grid
-// zeroed for the next accumulation.  per_scene = n^3.  With gfx2 set, a
-// scene flagged by k_fx_fold (its measured scales differ from the
-// predicted ones) was scattered again into gfx2: its nodes are taken from
-// gfx2, and both grids are zeroed.  The float grid is zero where nothing was added (it
-// was cleared before the launch), so untouched nodes are only read.
-__global__ void k_fx_grid(unsigned long long* gfx, unsigned long long* gfx2, float4* grid, int64_t nodes,
-                          int64_t per_scene, const unsigned* fxb, const double* fxk) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nodes) return;
-  const int b = (int)(t / per_scene);
+// Deterministic mode: node t (of scene b) of the 64-bit fixed-point grid
+// [node][4] -> grid (mv, m) as float4 at the scene's scales (the same
+// fx_scale of the same bounds as the accumulating launch: bank fxb), and
+// the fixed-point node zeroed for the next accumulation.  With gfx2 set, a
+// scene flagged by k_fx_fold (its measured scales differ from the predicted
+// ones) was scattered again into gfx2: its node is taken from gfx2, and
+// both grids' nodes are zeroed.  The float grid is zero where nothing was
+// added (it was cleared before the launch), so untouched nodes are only read.
+__device__ __forceinline__ void fx_convert_node(unsigned long long* gfx, unsigned long long* gfx2, float4* grid,
+                                                int64_t t, int b, const unsigned* fxb, const double* fxk) {
   ulonglong2* g = reinterpret_cast<ulonglong2*>(gfx + 4 * t);
   ulonglong2 a = g[0], c = g[1];
   if (gfx2 && fxb[4 * b + 3]) {  // the sums at the measured scale are in gfx2
@@ -1043,6 +1046,31 @@ __global__ void k_fx_grid(unsigned long long* gfx, unsigned long long* gfx2, flo
                         (float)((double)(long long)c.x * is_mom), (float)((double)(long long)c.y * is_mass));
   g[0] = make_ulonglong2(0ull, 0ull);
   g[1] = make_ulonglong2(0ull, 0ull);
+}
+
+// The conversion over every node (per_scene = n^3): the adjoint's grid.
+__global__ void k_fx_grid(unsigned long long* gfx, unsigned long long* gfx2, float4* grid, int64_t nodes,
+                          int64_t per_scene, const unsigned* fxb, const double* fxk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nodes) return;
+  fx_convert_node(gfx, gfx2, grid, t, (int)(t / per_scene), fxb, fxk);
+}
+
+// The conversion over the flagged 4^3-node blocks only (the forward: the
+// accumulating launches flag every block they add into), one wave per
+// block, resetting its flag.  nflags = scenes * nbn^3, nbn = (n + 3) / 4.
+__global__ void k_fx_grid_blocks(unsigned long long* gfx, unsigned long long* gfx2, float4* grid, unsigned* flags,
+                                 int64_t nflags, int nbn, int n, const unsigned* fxb, const double* fxk) {
+  const int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (blk >= nflags) return;  // whole waves
+  if (!flags[blk]) return;    // wave-uniform
+  const int per = nbn * nbn * nbn;
+  const int b = (int)(blk / per), rb = (int)(blk - (int64_t)b * per);
+  const int bx = rb / (nbn * nbn), by = (rb / nbn) % nbn, bz = rb % nbn;
+  const int l = threadIdx.x & 63;
+  const int ix = 4 * bx + (l >> 4), iy = 4 * by + ((l >> 2) & 3), iz = 4 * bz + (l & 3);
+  if (ix < n && iy < n && iz < n) fx_convert_node(gfx, gfx2, grid, (((int64_t)b * n + ix) * n + iy) * n + iz, b, fxb, fxk);
+  if (l == 0) flags[blk] = 0u;  // after the wave's read of the flag
 }
 
 // Deterministic mode: order the particles of each cell by source index
