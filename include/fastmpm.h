@@ -133,8 +133,9 @@ typedef struct {
  * scene, set by a bound of the contributions taken before the scatter.
  * Costs a conversion launch and a second stress evaluation per substep, v
  * and C stored at every substep, a bound pass per reversed substep and 64 B
- * per grid node of workspace (plus 4 B per 4^3-node block).  A cell of more than 4096 particles keeps the
- * order of the atomics (counted in mpm_diag.order_fallbacks). */
+ * per grid node (plus 4 B per 4^3-node block) of workspace.  A cell of more
+ * than 4096 particles keeps the order of the atomics (counted in
+ * mpm_diag.order_fallbacks). */
 #define MPM_FLAG_DETERMINISTIC 1u
 
 /* Block-sparse grid activity.  The three grid buffers the substeps rotate
