@@ -534,7 +534,7 @@ int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = f
       LAUNCH_CHECK(c, "k_substep accumulate");
       fmpm::k_fx_grid_blocks<<<fx_blocks, 256, 0, s>>>(c->gfx, nullptr, a.grid_out, c->gflag, c->nblocks, c->nb, c->n,
                                                        cur, c->fxk);
-      LAUNCH_CHECK(c, "k_fx_grid");
+      LAUNCH_CHECK(c, "k_fx_grid_blocks");
     } else {
       a.fxb = prev;
       if (MODE == fmpm::kFused) a.write_vc = 1;  // a scatter again reads v and C
@@ -561,7 +561,7 @@ int launch_args(mpm_ctx c, fmpm::SubstepArgs a, hipStream_t s, bool rotation = f
       LAUNCH_CHECK(c, "k_substep rescale");
       fmpm::k_fx_grid_blocks<<<fx_blocks, 256, 0, s>>>(c->gfx, c->gfx2, a.grid_out, c->gflag, c->nblocks, c->nb, c->n,
                                                        cur, c->fxk);
-      LAUNCH_CHECK(c, "k_fx_grid");
+      LAUNCH_CHECK(c, "k_fx_grid_blocks");
     }
     c->fx_bank ^= 1;
     c->fx_primed = true;
@@ -1201,6 +1201,7 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
         unsigned* const bank = ctx->fxb + 8 * (int64_t)ctx->B;  // the adjoint's bound bank
         b.fxb = bank;
         b.fxi = ctx->fxi;
+        b.gflag = ctx->gflag;
         b.fxk = ctx->fxk;
         b.gfx = ctx->gfx;
         fmpm::k_adj_bound<<<(unsigned)std::max<int64_t>(ctx->max_chunks, 1), 256, 0, s>>>(b, items);
@@ -1209,8 +1210,8 @@ int mpm_backward(mpm_ctx ctx, const mpm_particles* p, const void* tape, int32_t 
         if (rc) return rc;
         fmpm::k_adj_g2p<true><<<ctx->grid_blocks, kBlock, 0, s>>>(b, items);
         LAUNCH_CHECK(ctx, "k_adj_g2p");
-        fmpm::k_fx_grid<<<blocks_for(ctx->nodes, 256), 256, 0, s>>>(
-            ctx->gfx, nullptr, tl.vhb, ctx->nodes, (int64_t)ctx->n * ctx->n * ctx->n, bank, ctx->fxk);
+        fmpm::k_fx_grid_blocks<<<(unsigned)((ctx->nblocks + 3) / 4), 256, 0, s>>>(
+            ctx->gfx, nullptr, tl.vhb, ctx->gflag, ctx->nblocks, ctx->nb, ctx->n, bank, ctx->fxk);
       } else {
         ProfScope pa(ctx, s, 6);
         fmpm::k_adj_g2p<<<adj_g2p_blocks(ctx), kBlock, 0, s>>>(b, items);

@@ -72,6 +72,7 @@ struct AdjArgs {
   float2* fxi;
   const double* fxk;
   unsigned long long* gfx;
+  unsigned* gflag;  // flags of gfx's 4^3-node blocks the scatter adds into (k_fx_grid_blocks)
 };
 
 __device__ __forceinline__ void bspline_dw(float f, float* dw) {
@@ -863,6 +864,9 @@ __global__ __launch_bounds__(kBlock, DET ? 2 : 3) void k_adj_g2p(AdjArgs a, AdjI
               const int ix = b[0] + ox, iy = b[1] + oy, iz = b[2] + oz;
               const int64_t node = gbase + ((int64_t)ix * n + iy) * n + iz;
               if (DET) {
+                const int nbn = (n + 3) >> 2;
+                a.gflag[(int64_t)it.item_batch[item] * nbn * nbn * nbn + ((int64_t)(ix >> 2) * nbn + (iy >> 2)) * nbn +
+                        (iz >> 2)] = 1u;
 #pragma unroll
                 for (int r = 0; r < 3; ++r)
                   atomicAdd(a.gfx + 4 * node + r, (unsigned long long)fx_value(fx_bits(gv[r], s_fx)));
@@ -892,6 +896,17 @@ __global__ __launch_bounds__(kBlock, DET ? 2 : 3) void k_adj_g2p(AdjArgs a, AdjI
     }
     if (lds) {
       __syncthreads();
+      if (DET) {  // flag the 4^3-node blocks the tile covers (nodes box.lo .. box.hi + 2)
+        const int nbn = (n + 3) >> 2;
+        const int bx0 = box[0] >> 2, by0 = box[1] >> 2, bz0 = box[2] >> 2;
+        const int nx = ((box[3] + 2) >> 2) - bx0 + 1, ny = ((box[4] + 2) >> 2) - by0 + 1,
+                  nz = ((box[5] + 2) >> 2) - bz0 + 1;
+        const int64_t sbase = (int64_t)it.item_batch[item] * nbn * nbn * nbn;
+        for (int t = threadIdx.x; t < nx * ny * nz; t += kBlock) {
+          const int bx = bx0 + t / (ny * nz), by = by0 + (t / nz) % ny, bz = bz0 + t % nz;
+          a.gflag[sbase + ((int64_t)bx * nbn + by) * nbn + bz] = 1u;
+        }
+      }
       for (int t = threadIdx.x; t < GT; t += kBlock) {
         const int ti = t / sz, tr = t - ti * sz;
         const int tj = tr / gz, tk = tr - tj * gz;

@@ -1048,17 +1048,10 @@ __device__ __forceinline__ void fx_convert_node(unsigned long long* gfx, unsigne
   g[1] = make_ulonglong2(0ull, 0ull);
 }
 
-// The conversion over every node (per_scene = n^3): the adjoint's grid.
-__global__ void k_fx_grid(unsigned long long* gfx, unsigned long long* gfx2, float4* grid, int64_t nodes,
-                          int64_t per_scene, const unsigned* fxb, const double* fxk) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nodes) return;
-  fx_convert_node(gfx, gfx2, grid, t, (int)(t / per_scene), fxb, fxk);
-}
-
-// The conversion over the flagged 4^3-node blocks only (the forward: the
-// accumulating launches flag every block they add into), one wave per
-// block, resetting its flag.  nflags = scenes * nbn^3, nbn = (n + 3) / 4.
+// The conversion over the flagged 4^3-node blocks only (the accumulating
+// launches and the deterministic adjoint scatter flag every block they add
+// into), one wave per block, resetting its flag.  nflags = scenes * nbn^3,
+// nbn = (n + 3) / 4.
 __global__ void k_fx_grid_blocks(unsigned long long* gfx, unsigned long long* gfx2, float4* grid, unsigned* flags,
                                  int64_t nflags, int nbn, int n, const unsigned* fxb, const double* fxk) {
   const int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
