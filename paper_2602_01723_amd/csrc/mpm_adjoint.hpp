@@ -625,10 +625,10 @@ __global__ __launch_bounds__(256) void k_adj_bound(AdjArgs a, AdjItems it) {
   }
 }
 
-template <bool DET = false>
 // Three workgroups per CU (48 KB of LDS each; at most 168 VGPRs) in the
 // default mode, where the host launches 1.5 times the forward's workgroup
 // count; two in deterministic mode (its fixed-point scatter would spill).
+template <bool DET = false>
 __global__ __launch_bounds__(kBlock, DET ? 2 : 3) void k_adj_g2p(AdjArgs a, AdjItems it) {
   __shared__ double ptile[3 * kTileCapMax];
   // deterministic mode: the same LDS as 64-bit fixed point at the scene's scale
