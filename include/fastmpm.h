@@ -289,9 +289,11 @@ int mpm_get_diagnostics(mpm_ctx ctx, mpm_diag* out);
  * substeps between re-sorts; tile_cap = LDS tile nodes (27..1331);
  * workgroups = width of the persistent substep kernel.  In mpm_set_tuning a
  * zero field keeps the current value; ms_per_substep is an output of
- * mpm_autotune only.  Defaults after mpm_init: chunk 768 (256 below 131,072
- * particles), the library's re-sort interval, tile_cap 1331, 512 workgroups
- * (at most one per possible work item). */
+ * mpm_autotune only.  Defaults after mpm_init: chunk 768, the library's
+ * re-sort interval, tile_cap 1331, 512 workgroups (at most one per possible
+ * work item).  Small scenes run faster with smaller work items (mpm_autotune
+ * picks 256 for 20,480 particles), at more float32 partial sums per grid
+ * node when many particles share a cell. */
 typedef struct {
   int32_t chunk;
   int32_t sort_every;

@@ -786,10 +786,6 @@ int mpm_init(const mpm_config* cfg, const mpm_material* materials, int32_t n_mat
   c->nblocks = g.nblocks;
   c->max_chunks = g.max_chunks;
   c->grid_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(c->max_chunks, 256 * 2));
-  // below 2^17 particles 768-particle items leave most workgroups idle and a
-  // substep waits on a few long items: 256 (the autotuner's choice on a
-  // 20,480-particle scene, twice as fast)
-  if (n_particles < 131072) c->item = 256;
   c->workspace_bytes = carve(c, g, static_cast<char*>(workspace));
 
   hipError_t e = hipMemcpy(c->chunk_start, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice);
