@@ -160,6 +160,7 @@ def test_substep_max_contention_one_cell():
     n = d["n"]
     d["x"] = ((16.6 + rng.uniform(0, 0.8, (4096, 3))) / n).astype(np.float32)
     errs, diag, _, _ = run_case(d)
+    print(errs, flush=True)
     assert_parity(errs)
 
 
