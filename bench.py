@@ -127,6 +127,47 @@ def measured_valu(n_particles):
     return t["valu_instructions_per_particle"]
 
 
+ATOMICS_FILE = os.path.join(ROOT, "profiles", "fused_substep_large_scene_atomics.json")
+ATOMICS_COMMAND = ("cd /tmp && rocprofv3 --pmc TCC_EA0_ATOMIC_sum TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_ATOMIC_sum "
+                   "-f csv -d <out>/pmc_eaw -o eaw -- python3 <repo>/bench.py --steps 1 --warmup 1 "
+                   "--substeps-per-step 10 --no-autotune --no-step-n --no-cpu-baseline --no-batched --no-bgdo "
+                   "--no-models --no-mcis --no-ipf --no-det --no-configs --no-atomics")
+
+
+def write_atomics(eaw_csv, n_particles=2_000_000):
+    """Summarise the memory-side request pass of the fused kernel (global
+    atomics and write requests at the L2/memory interface, mean per
+    dispatch) into ATOMICS_FILE, stamped with the kernel source hash."""
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(eaw_csv)):
+        if FUSED_KERNEL in r["Kernel_Name"]:
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    mean = {k: sum(v) / len(v) for k, v in acc.items()}
+    out = {"kernel": FUSED_KERNEL, "particles": n_particles,
+           "dispatches": len(next(iter(acc.values()))) if acc else 0,
+           "global_atomic_requests": mean.get("TCC_ATOMIC_sum"),
+           "global_atomic_requests_at_memory_side": mean.get("TCC_EA0_ATOMIC_sum"),
+           "write_requests": mean.get("TCC_EA0_WRREQ_sum"), "write_requests_64B": mean.get("TCC_EA0_WRREQ_64B_sum"),
+           "kernel_source_hash": kernel_source_hash(), "command": ATOMICS_COMMAND}
+    with open(ATOMICS_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def measured_atomics(n_particles):
+    """Counter summary of the fused kernel's global atomics, or None if the
+    kernel sources changed since it was taken."""
+    try:
+        with open(ATOMICS_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("particles") != n_particles:
+        return None
+    return t
+
+
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {c} -f csv -d <out>/pmc_{c} -o {c} -- python3 <repo>/bench.py "
                "--steps 1 --warmup 1 --substeps-per-step 10 --no-autotune --no-step-n --no-cpu-baseline --no-batched "
                "--no-bgdo --no-models --no-mcis --no-ipf --no-det --no-configs --no-atomics")
@@ -907,10 +948,15 @@ def main():
                     help="summarise the p1 instruction-mix counter run into the VALU file and exit (no GPU use)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit (no GPU use)")
+    ap.add_argument("--write-atomics", metavar="EAW_CSV",
+                    help="summarise the memory-side request pass into the atomics file and exit (no GPU use)")
     ap.add_argument("--item-geometry", action="store_true",
                     help="count the fused launch's G2P tile loads and flushed nodes from the workload's item "
                          "geometry and exit (no GPU use)")
     args = ap.parse_args()
+    if args.write_atomics:
+        print(json.dumps(write_atomics(args.write_atomics, n_particles=args.n_total)))
+        return
     if args.item_geometry:
         print(json.dumps(item_geometry(args.n_total, args.item or 768)))
         return
@@ -1065,6 +1111,16 @@ def main():
             global_add_f32_peak_node_channels=probes["global_add_f32_node_channels"],
             global_add_f32_peak_distinct=probes["global_add_f32_distinct"], unit="T lane-ops/s",
             note="LDS adds averaged over the whole launch; the P2G scatter is about a third of it")
+        ga = measured_atomics(sc.n)
+        if ga and ga.get("global_atomic_requests"):
+            # the tile flushes' float atomics, counted at the L2 (TCC_ATOMIC) and at
+            # the memory side (TCC_EA0_ATOMIC): every one is performed there
+            roofline["atomics"].update(
+                global_atomic_requests_per_launch=round(ga["global_atomic_requests"]),
+                global_atomic_requests_achieved=round(ga["global_atomic_requests"] / fused_avg_s / 1e9, 2),
+                global_atomic_requests_unit="G requests/s",
+                global_atomics_at_memory_side=round(ga["global_atomic_requests_at_memory_side"] /
+                                                    ga["global_atomic_requests"], 4))
     breakdown = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]}
     log("  kernel time by class:", json.dumps(breakdown))
     log("  diagnostics:", diag)
